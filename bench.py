@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Throughput of the MEnKF hot path on one MI355X.
+
+Workload: 2D compressible Navier-Stokes, fine 1024^2, coarse 256^2, 64
+members, 4096 velocity probes, an analysis every 20 RK4 steps (dt 5e-4).
+One step of this bench = one assimilation cycle: fine forecast (20 steps),
+ensemble forecast (64 members x 20 steps), restriction, gain (FP64
+innovation covariance + Cholesky), member update, prolongation + 3 relaxed
+sweeps (plain) or the learned prolongation.  The cycle is captured once as
+a HIP graph and replayed; observations for every cycle are generated
+beforehand (a truth run on the GPU) and sit in HBM.
+
+Prints one JSON line (metric, value in cycles/s, roofline of the dominant
+kernel measured with HIP events on its own stream, oracle CPU baseline).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "assimilation cycles/s, 2D 1024²/256² N=64, learned vs plain at equal RMSE"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--sweeps", type=int, default=3)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
+    return ap.parse_args()
+
+
+def make_cfg(small):
+    from synthetic import configs
+    return configs.tiny_2d(precision="f32") if small else configs.CONFIGS["C3"]
+
+
+class Cycle:
+    """Device state of one assimilation instance and its captured cycle."""
+
+    def __init__(self, cfg, n_sweeps, mode=0, net=None):
+        import torch
+
+        import paper_2012_10091_amd as m
+        from synthetic import fields
+        self.m = m
+        self.cfg = cfg
+        self.ctx = m.Context(cfg)
+        idx, comp = fields.probes_for(cfg)
+        self.ctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+        f32 = torch.float32
+        self.fine = torch.as_tensor(fields.model_ic(cfg), dtype=f32, device="cuda").contiguous()
+        self.members = torch.as_tensor(fields.member_ics(cfg), dtype=f32, device="cuda").contiguous()
+        self.prev = torch.empty_like(self.fine)
+        self.xs = torch.empty((4, cfg.nyc, cfg.nxc), dtype=f32, device="cuda")
+        self.dc = torch.empty_like(self.xs)
+        self.y = torch.zeros(cfg.n_probes, dtype=torch.float64, device="cuda")
+        self.n_sweeps = n_sweeps
+        self.mode = mode
+        self.net = net
+        self.seed = cfg.seed + 5
+        self.graph = None
+
+    def issue(self, stream):
+        c, m = self.ctx, self.m
+        c.forecast(m.MENKF_FINE, self.fine, self.cfg.n_obs, prev=self.prev, stream=stream)
+        c.forecast(m.MENKF_COARSE, self.members, self.cfg.n_obs, stream=stream)
+        c.restrict(self.fine, self.xs, stream=stream)
+        c.gain(self.members, self.xs, self.y, self.seed, m.MENKF_CYCLE_DEVICE, stream=stream)
+        c.update(self.members, self.dc, stream=stream)
+        c.prolong_smooth(self.dc, self.fine, self.prev, n_sweeps=self.n_sweeps, alpha=0.5, mode=self.mode,
+                         net=self.net, stream=stream)
+
+    def capture(self, stream):
+        import torch
+        with torch.cuda.stream(stream):
+            self.m.Graph.begin(stream)
+            self.issue(stream)
+            self.graph = self.m.Graph.end(stream)
+        self.ctx.set_cycle(1, stream=stream)
+
+
+def truth_observations(cfg, n_cycles):
+    """Truth run on the GPU (same fine model) and noisy probe observations."""
+    import numpy as np
+    import torch
+
+    import paper_2012_10091_amd as m
+    from synthetic import fields
+    ctx = m.Context(cfg.with_(n_members=2))
+    idx, comp = fields.probes_for(cfg)
+    ctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+    truth = torch.as_tensor(fields.truth_ic(cfg), dtype=torch.float32, device="cuda").contiguous()
+    Y = torch.empty((n_cycles, cfg.n_probes), dtype=torch.float64, device="cuda")
+    states = []
+    for c in range(n_cycles):
+        ctx.forecast(m.MENKF_FINE, truth, cfg.n_obs)
+        Y[c] = ctx.observe(m.MENKF_FINE, truth)[0] + torch.as_tensor(fields.obs_noise(cfg, c + 1), device="cuda")
+        states.append(truth.clone() if c % 10 == 9 else None)
+    torch.cuda.synchronize()
+    del np
+    return Y, states
+
+
+def time_cycles(cyc, Y, warmup, steps):
+    import torch
+    stream = torch.cuda.Stream()
+    cyc.capture(stream)
+    torch.cuda.synchronize()
+    for c in range(warmup):
+        with torch.cuda.stream(stream):
+            cyc.y.copy_(Y[c])
+        cyc.graph.launch(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for c in range(warmup, warmup + steps):
+        with torch.cuda.stream(stream):
+            cyc.y.copy_(Y[c])
+        cyc.graph.launch(stream)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def stage_kernel_roofline(cfg, cyc, reps=2):
+    """Average duration of the ensemble RK4 stage kernel, timed with HIP events
+    on the stream it is launched on, and its bytes per launch."""
+    import torch
+    import paper_2012_10091_amd as m
+    stream = torch.cuda.Stream()
+    scratch = cyc.members.clone()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        cyc.ctx.forecast(m.MENKF_COARSE, scratch, cfg.n_obs, stream=stream)     # warm
+        ev0.record(stream)
+        for _ in range(reps):
+            cyc.ctx.forecast(m.MENKF_COARSE, scratch, cfg.n_obs, stream=stream)
+        ev1.record(stream)
+    stream.synchronize()
+    launches = reps * cfg.n_obs * 4
+    avg_s = ev0.elapsed_time(ev1) / 1e3 / launches
+    pts = cfg.n_members * cfg.nxc * cfg.nyc
+    state_bytes = pts * 4 * 4
+    # kernel contract: 16 state passes per RK4 step over 4 launches (stage 1: 1R 2W,
+    # stages 2-3: 3R 2W, stage 4: 2R 1W) -> 4 passes per launch on average
+    contract = 4.0 * state_bytes
+    minimum = 2.0 * state_bytes / 4.0      # one read + one write of the state per step
+    return {
+        "kernel": "ns_stage<float,32,16,*> (ensemble RK4 stage, 64 x 4 x 256^2)",
+        "avg_launch_us": avg_s * 1e6,
+        "contract_bytes": contract,
+        "min_bytes": minimum,
+        "achieved": contract / avg_s / 1e9,
+        "achieved_min": minimum / avg_s / 1e9,
+    }
+
+
+def cpu_baseline(cfg):
+    """The FP64 oracle on a bounded sample of one cycle, extrapolated to cycles/s."""
+    import numpy as np
+    from oracle import cycle as ocycle
+    from oracle import enkf, grids, rng, smooth
+    from oracle.models import Model
+    from synthetic import fields
+    cores = len(os.sched_getaffinity(0))
+    fine = fields.model_ic(cfg)
+    mem = fields.member_ics(cfg)
+    mf, mc = Model(cfg, "fine"), Model(cfg, "coarse")
+    t = time.perf_counter()
+    mf.step(fine)
+    t_fine_step = time.perf_counter() - t
+    nm = 2
+    t = time.perf_counter()
+    mc.step(mem[:nm])
+    t_member_step = (time.perf_counter() - t) / nm
+    idx, comp = fields.probes_for(cfg)
+    xs = grids.restrict(fine, cfg.ratio, cfg.dim)
+    y = np.zeros(cfg.n_probes)
+    eps = rng.perturbations(1, 1, cfg.n_members, cfg.n_probes, cfg.obs_sigma)
+    t = time.perf_counter()
+    res = enkf.analysis(mem, xs, y, eps, ocycle.make_H(cfg, idx, comp), cfg.obs_sigma)
+    t_analysis = time.perf_counter() - t
+    t = time.perf_counter()
+    x = fine + grids.prolong(res["delta"], cfg.ratio, cfg.dim)
+    smooth.smooth(x, fine, mf, 3, 0.5)
+    t_prolong = time.perf_counter() - t
+    per_cycle = (cfg.n_obs * (t_fine_step + cfg.n_members * t_member_step) + t_analysis + t_prolong)
+    return {
+        "value": 1.0 / per_cycle,
+        "unit": "cycles/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"1 fine RK4 step ({t_fine_step:.2f}s), {nm} member steps ({t_member_step:.2f}s each), "
+                   f"1 analysis ({t_analysis:.2f}s), prolong + 3 sweeps ({t_prolong:.2f}s); "
+                   f"extrapolated to one cycle = {cfg.n_obs} fine + {cfg.n_obs * cfg.n_members} member steps"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU: this build measures the single-GPU hot path "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2012_10091_amd as m
+    m.load_library()
+    cfg = make_cfg(args.small)
+    n_cyc = args.warmup + args.steps
+    log(f"bench: workload {cfg.name}, warmup {args.warmup}, steps {args.steps}")
+    Y, _ = truth_observations(cfg, n_cyc)
+    log("bench: observations ready")
+    plain = Cycle(cfg, args.sweeps)
+    sec, wall = time_cycles(plain, Y, args.warmup, args.steps)
+    status = plain.ctx.get_status()
+    log(f"bench: plain {args.steps / sec:.2f} cycles/s (graph events {sec:.3f}s, wall {wall:.3f}s), status {status}")
+    rl = stage_kernel_roofline(cfg, plain)
+    log(f"bench: stage kernel avg {rl['avg_launch_us']:.1f} us, contract {rl['achieved']:.0f} GB/s")
+    out = {
+        "metric": METRIC,
+        "value": args.steps / sec,
+        "unit": "cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg.name, "fine": [cfg.ny, cfg.nx], "coarse": [cfg.nyc, cfg.nxc],
+            "members": cfg.n_members, "probes": cfg.n_probes, "steps_per_cycle": cfg.n_obs,
+            "variant": f"plain (Pi_F + {args.sweeps} relaxed sweeps)", "status_word": status,
+            "precision": "FP32 stencils, FP64 innovation covariance/Cholesky/gain of x*, BF16x3 member update",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": rl["achieved"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": rl["achieved"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": rl["kernel"],
+            "avg_launch_us": rl["avg_launch_us"],
+            "bytes_per_launch": rl["contract_bytes"],
+            "frac_vs_step_minimum": rl["achieved_min"] / HBM_PEAK_GBS,
+        },
+    }
+    if args.cpu_baseline and not args.small:
+        log("bench: timing the oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

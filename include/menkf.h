@@ -1,0 +1,243 @@
+/*
+ * menkf.h - C ABI of the MI355X (gfx950) multigrid ensemble Kalman filter
+ * (MEnKF) hot path.
+ *
+ * The calls follow the paper's statement of the problem and its MEnKF
+ * algorithm (Moldovan, Lehnasch, Cordier & Meldi, "A multigrid/ensemble
+ * Kalman filter strategy for assimilation of unsteady flows", J. Comput.
+ * Phys., arXiv 2012.10091):
+ *   model        x_k = M(x_{k-1}) (+ eta)                   Sec. 2.1.1, state-evolution equation
+ *   observation  y^o = H(x_k) + eps,  eps ~ N(0, R)        Sec. 2.1.1, observation equation
+ *   one cycle    Algo. 4 steps 2-6 with the state part of Algo. 3
+ *       menkf_forecast(FINE)      Algo. 4 step 2   fine forecast x^F_f
+ *       menkf_forecast(COARSE)    Algo. 3 step 2   ensemble forecast on the coarse grid
+ *       menkf_restrict            Algo. 4 step 4   x* = Pi_C(x^F_f)
+ *       menkf_gain                Algo. 3 steps 3,4,7,8 (gain) and Algo. 4 step 5 (gain of x*)
+ *       menkf_update              Algo. 3 step 8 (member update) and Algo. 4 step 5 (delta^C)
+ *       menkf_prolong_smooth      Algo. 4 steps 5-6: x' = x^F_f + Pi_F(delta^C), relaxed iteration
+ *
+ * Conventions shared by every call
+ *   - Every pointer argument named *_dev is DEVICE memory on the context's
+ *     device, owned by the caller; the library never frees or retains it
+ *     beyond the call, except the probe tables (menkf_set_probes) and the
+ *     workspace (menkf_set_workspace), which must stay valid while the
+ *     context uses them.
+ *   - State arrays hold float (MENKF_F32 contexts) or double (MENKF_F64
+ *     contexts), passed as void*.  Layout: [nb][F][ny][nx], x fastest,
+ *     members outermost; F = 1 (Burgers, ny = 1) or 4 (rho, rho u, rho v, E).
+ *   - Calls are asynchronous on the given stream (NULL = default stream),
+ *     allocate nothing, never synchronise and never read device results
+ *     on the host, so a sequence of them can be captured in a HIP graph.
+ *     The only exceptions are menkf_get_status (synchronises the stream)
+ *     and the menkf_graph_* helpers.
+ *   - Argument and shape errors are detected on the host before any launch
+ *     and returned as negative codes; menkf_last_error gives the text.
+ *     Failures found on the device (a non-positive Cholesky pivot) are
+ *     written to a device status word read by menkf_get_status; the calls
+ *     that follow (menkf_update, menkf_prolong_smooth) test it on the
+ *     device and leave their outputs untouched when it is set.
+ */
+#ifndef MENKF_H
+#define MENKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct menkf_ctx menkf_ctx;
+typedef struct menkf_graph menkf_graph;
+typedef void *menkf_stream; /* a hipStream_t */
+
+typedef enum {
+    MENKF_OK = 0,
+    MENKF_E_ARG = -1,         /* bad argument (null pointer, bad enum, bad count) */
+    MENKF_E_SHAPE = -2,       /* sizes inconsistent with the configuration */
+    MENKF_E_NOT_SPD = -3,     /* innovation covariance not positive definite (device) */
+    MENKF_E_NONFINITE = -4,   /* NaN/Inf found by a diagnostic */
+    MENKF_E_HIP = -5,         /* a HIP runtime call failed */
+    MENKF_E_UNSUPPORTED = -6, /* valid request outside what this build implements */
+    MENKF_E_WORKSPACE = -7    /* workspace missing or too small */
+} menkf_status;
+
+enum { MENKF_BURGERS1D = 1, MENKF_NS2D = 2 };          /* model */
+enum { MENKF_F32 = 0, MENKF_F64 = 1 };                 /* precision */
+enum { MENKF_GAIN_EXACT_R = 0, MENKF_GAIN_SAMPLE_EE = 1 };
+enum { MENKF_FINE = 0, MENKF_COARSE = 1 };             /* grid level */
+enum { MENKF_PROLONG_PLAIN = 0, MENKF_PROLONG_LEARNED = 1, MENKF_PROLONG_LEARNED_FALLBACK = 2 };
+
+/*
+ * Configuration of one assimilation instance.
+ *   model      MENKF_BURGERS1D: u_t + u u_x = nu u_xx (Sec. 4, Burgers equation),
+ *              second-order centred differences, three-stage SSP Runge-Kutta.
+ *              MENKF_NS2D: compressible Navier-Stokes in conservative form
+ *              (Sec. 6, mass/momentum/energy equations), fourth-order centred
+ *              differences, classical four-stage Runge-Kutta.
+ *              Both periodic on [0, length)^dim.
+ *   precision  MENKF_F32: float states and stencils, BF16 member-update
+ *              products with FP32 accumulation, FP64 innovation covariance
+ *              (S = Y Y^T + R), Cholesky and gain of x*.
+ *              MENKF_F64: everything in double.
+ *   gain_mode  MENKF_GAIN_EXACT_R: S = Y Y^T + obs_sigma^2 I.
+ *              MENKF_GAIN_SAMPLE_EE: S = Y Y^T + E E^T (Algo. 1 step 6 as
+ *              printed; singular when n_probes > 2 n_members - 2).
+ *   nx, ny     fine grid points (ny = 1 for the 1D model); ratio = coarsening
+ *              ratio r_C per direction, must divide nx (and ny in 2D).
+ *   n_members  ensemble size 2 <= N_e <= 256 (anomalies scaled by 1/sqrt(N_e - 1)).
+ *   n_probes   number of scalar observations N_y >= 1.
+ *   dt         time step of both levels; nu Burgers viscosity; gamma, mach,
+ *              reynolds, prandtl the non-dimensional gas constants
+ *              (rho0 = U0 = T0 = 1, mu = 1/Re, p = (gamma-1)(E - rho|u|^2/2)).
+ *   obs_sigma  observation noise standard deviation (R = obs_sigma^2 I).
+ *   anomaly_terms  MENKF_F32 member update X Z on BF16 MFMA: 1 = plain BF16
+ *              operands; 3 (or 0 = default) = each operand split into a BF16
+ *              pair hi + lo, product hi*hi + hi*lo + lo*hi (FP32-level accuracy).
+ */
+typedef struct {
+    int32_t model, precision, gain_mode;
+    int32_t nx, ny, ratio;
+    int32_t n_members, n_probes;
+    double length, dt, nu;
+    double gamma, mach, reynolds, prandtl;
+    double obs_sigma;
+    int32_t anomaly_terms;
+} menkf_config;
+
+/* Create / destroy a context for the current HIP device.  The context owns
+ * only host-side metadata; on failure *out is NULL and the status says why
+ * (menkf_last_error(NULL) gives the text). */
+menkf_status menkf_create(const menkf_config *cfg, menkf_ctx **out);
+void menkf_destroy(menkf_ctx *ctx);
+const char *menkf_last_error(const menkf_ctx *ctx);
+
+/* Bytes of device workspace the context needs (no GPU call made). */
+menkf_status menkf_workspace_size(const menkf_ctx *ctx, size_t *bytes);
+/* Attach caller-owned device workspace of at least menkf_workspace_size
+ * bytes, 256-byte aligned.  Its contents are the library's between calls. */
+menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws_dev, size_t bytes);
+
+/* Observation probes (observation equation of Sec. 2.1.1): probe p
+ * observes the fine node idx_dev[p] (linear index y*nx + x) and component
+ * comp_dev[p] (0: u = (rho u)/rho in 2D or u in 1D; 1: v = (rho v)/rho).
+ * On the coarse level the operator is H^C = H^F o Pi_F at the probe node.
+ * Device arrays of n_probes int32, kept by reference.  A set-up call: it
+ * copies the tables to the host once (synchronously) and rejects nodes
+ * outside the fine grid or components other than 0 (1D) / 0, 1 (2D). */
+menkf_status menkf_set_probes(menkf_ctx *ctx, const int32_t *idx_dev, const int32_t *comp_dev);
+
+/* Explicit forecast (state-evolution equation; Algo. 4 step 2 for
+ * level = MENKF_FINE with nb = 1, Algo. 3 step 2 for level = MENKF_COARSE
+ * with nb <= n_members states).  Advances state_dev in place by nsteps
+ * time steps.  If prev_dev is not NULL it receives the state one step
+ * before the end (the right-hand side x_{k-1} of the fine-grid implicit
+ * system used by the relaxed iteration).  nsteps >= 1. */
+menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state_dev, int32_t nb,
+                            int32_t nsteps, void *prev_dev, menkf_stream stream);
+
+/* x* = Pi_C(x^F_f) (Algo. 4 step 4): the fourth-order Lagrange restriction
+ * of Sec. 2.2 on nested vertex-centred grids, i.e. injection of every
+ * ratio-th node.  xf_dev: one fine state; xc_dev: one coarse state. */
+menkf_status menkf_restrict(menkf_ctx *ctx, const void *xf_dev, void *xc_dev, menkf_stream stream);
+
+/* Ensemble gain (Algo. 3 steps 3, 4, 7, 8; Algo. 1 steps 2-6).
+ *   members_dev  the N_e forecast members (coarse states), unchanged
+ *   xstar_dev    x* (coarse state)
+ *   yobs_dev     N_y double observations y^o
+ *   eps_dev      NULL: draw eps^(i) ~ N(0, obs_sigma^2) with Philox4x32-10
+ *                keyed by seed and counter (probe/2, member, cycle, 0x5045),
+ *                Box-Muller in FP64; else N_e x N_y doubles used as given.
+ * Computes H^C of every member and of x*, secant anomalies Y, the
+ * perturbed-observation innovations D = y^o + eps^(i) - y^(i) and
+ * d* = y^o - H^C(x*), S = Y Y^T + R (or + E E^T), its FP64 Cholesky
+ * factor, and the gain factors Z = Y^T S^-1 [D | d*] kept in the
+ * workspace for menkf_update.  A non-positive pivot sets the device status
+ * to column+1 (MENKF_E_NOT_SPD via menkf_get_status). */
+menkf_status menkf_gain(menkf_ctx *ctx, const void *members_dev, const void *xstar_dev,
+                        const double *yobs_dev, uint64_t seed, uint64_t cycle,
+                        const double *eps_dev, menkf_stream stream);
+
+/* cycle = MENKF_CYCLE_DEVICE makes menkf_gain take the cycle number from a
+ * counter kept in the workspace and advance it by one on the device, so a
+ * captured cycle replayed many times draws new perturbations each time.
+ * menkf_set_cycle sets that counter (stream-ordered, no allocation). */
+#define MENKF_CYCLE_DEVICE (~(uint64_t)0)
+menkf_status menkf_set_cycle(menkf_ctx *ctx, uint64_t cycle, menkf_stream stream);
+
+/* Copy the gain factors Z of the last menkf_gain into z_dev, laid out as
+ * (N_e + 1) x N_e doubles, row j = column j of Z (j < N_e: member j's
+ * innovation; j = N_e: the x* innovation). */
+menkf_status menkf_get_gain(menkf_ctx *ctx, double *z_dev, menkf_stream stream);
+
+/* Member update and coarse correction (Algo. 3 step 8; Algo. 4 step 5):
+ *   members_dev  in/out: x^a(i) = x^(i) + X Z[:, i], X the normalised anomalies
+ *   deltac_dev   out: delta^C = X Z[:, N_e] (= x^C' - x*), computed in FP64
+ * Uses the factors of the preceding menkf_gain on the same members.  A no-op
+ * on the device if the status word is set. */
+menkf_status menkf_update(menkf_ctx *ctx, void *members_dev, void *deltac_dev, menkf_stream stream);
+
+/* Fine-grid correction and regularisation (Algo. 4 steps 5-6):
+ *   xf_dev       in: x^F_f, out: x^F_a
+ *   deltac_dev   delta^C (coarse state)
+ *   xprev_dev    x^F_{k-1}, the fine state one step before x^F_f
+ *   MENKF_PROLONG_PLAIN: x' = x^F_f + Pi_F(delta^C) (cubic Lagrange,
+ *   Sec. 2.2), then n_sweeps damped Jacobi sweeps of the implicit-Euler
+ *   system x - dt F(x) = x^F_{k-1}:  x <- x + alpha/D (x_{k-1} + dt F(x) - x),
+ *   D the viscous diagonal (one sweep with alpha = 0.5 in the paper's
+ *   implementation notes).
+ *   MENKF_PROLONG_LEARNED: x' = x^F_f + Pi_F(delta^C) + NN(Pi_F(delta^C), x^F_f)
+ *   with the network described by net (menkf_net, 2D only), no sweeps.
+ *   MENKF_PROLONG_LEARNED_FALLBACK: as LEARNED, but every pixel block whose
+ *   network output is non-finite or exceeds guard * |Pi_F(delta^C)|
+ *   falls back to the plain correction, then n_sweeps sweeps.
+ * A no-op on the device if the status word is set. */
+typedef struct {
+    const void *w1;  /* bf16 [32][8][3][3]  */
+    const float *b1; /* [32] */
+    const void *w2;  /* bf16 [32][32][3][3] */
+    const float *b2; /* [32] */
+    const void *w3;  /* bf16 [4][32][3][3]  */
+    const float *b3; /* [4] */
+    float in_scale[8], in_offset[8], out_scale[4];
+    float guard;     /* fallback amplitude guard (LEARNED_FALLBACK) */
+    int32_t *fallback_count_dev; /* optional: incremented per fallback block */
+} menkf_net;
+
+menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *deltac_dev, void *xf_dev,
+                                  const void *xprev_dev, int32_t n_sweeps, double alpha,
+                                  int32_t mode, const menkf_net *net, menkf_stream stream);
+
+/* Synchronise the stream and read the device status word into *info
+ * (0 = fine, j+1 = first non-positive pivot at column j).  Returns
+ * MENKF_E_NOT_SPD if it is set.  Clears the word when clear != 0. */
+menkf_status menkf_get_status(menkf_ctx *ctx, int32_t *info, int32_t clear, menkf_stream stream);
+
+/* Observation operator on nb states: level MENKF_FINE applies H^F (state =
+ * fine), MENKF_COARSE applies H^C = H^F o Pi_F; y_dev gets nb x N_y doubles. */
+menkf_status menkf_observe(menkf_ctx *ctx, int32_t level, const void *state_dev, int32_t nb,
+                           double *y_dev, menkf_stream stream);
+
+/* Diagnostics of a fine state against a reference (Sec. 4 relative RMSE):
+ * out_dev[0] = sum (xa - xt)^2, out_dev[1] = sum xt^2 over the observed
+ * quantity (u in 1D; (u, v) in 2D), out_dev[2] = number of non-finite
+ * entries of xa, accumulated in FP64. */
+menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa_dev, const void *xt_dev,
+                               double *out_dev, menkf_stream stream);
+
+/* Normalised RAM requirement R_RAM = 1 + N_e / r_C^dim of one fine
+ * simulation plus N_e coarse members (Sec. 3).  Host only. */
+double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
+
+/* HIP graph helpers: capture the menkf_* calls issued on stream between
+ * begin and end into a graph, then replay it.  The stream must not be the
+ * legacy default stream. */
+menkf_status menkf_graph_begin(menkf_stream stream);
+menkf_status menkf_graph_end(menkf_stream stream, menkf_graph **out);
+menkf_status menkf_graph_launch(menkf_graph *g, menkf_stream stream);
+void menkf_graph_destroy(menkf_graph *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MENKF_H */

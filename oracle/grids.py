@@ -63,7 +63,7 @@ def restrict(xf: np.ndarray, ratio: int, dim: int) -> np.ndarray:
     if dim == 1:
         return xf @ Rx.T
     Ry = restrict_matrix(xf.shape[-2], ratio)
-    return np.einsum("ab,...bc,dc->...ad", Ry, xf, Rx)
+    return Ry @ xf @ Rx.T
 
 
 def prolong(xc: np.ndarray, ratio: int, dim: int) -> np.ndarray:
@@ -73,4 +73,4 @@ def prolong(xc: np.ndarray, ratio: int, dim: int) -> np.ndarray:
     if dim == 1:
         return xc @ Px.T
     Py = prolong_matrix(xc.shape[-2], ratio)
-    return np.einsum("ab,...bc,dc->...ad", Py, xc, Px)
+    return Py @ xc @ Px.T

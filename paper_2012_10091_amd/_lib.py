@@ -1,0 +1,96 @@
+"""ctypes loader for libmenkf.so.
+
+The library is the product: if it is missing this module raises, it never
+falls back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmenkf.so")
+
+c_int32 = ctypes.c_int32
+c_uint64 = ctypes.c_uint64
+c_double = ctypes.c_double
+c_size_t = ctypes.c_size_t
+c_void_p = ctypes.c_void_p
+c_char_p = ctypes.c_char_p
+
+
+class MenkfConfig(ctypes.Structure):
+    _fields_ = [
+        ("model", c_int32), ("precision", c_int32), ("gain_mode", c_int32),
+        ("nx", c_int32), ("ny", c_int32), ("ratio", c_int32),
+        ("n_members", c_int32), ("n_probes", c_int32),
+        ("length", c_double), ("dt", c_double), ("nu", c_double),
+        ("gamma", c_double), ("mach", c_double), ("reynolds", c_double), ("prandtl", c_double),
+        ("obs_sigma", c_double),
+        ("anomaly_terms", c_int32),
+    ]
+
+
+class MenkfNet(ctypes.Structure):
+    _fields_ = [
+        ("w1", c_void_p), ("b1", c_void_p),
+        ("w2", c_void_p), ("b2", c_void_p),
+        ("w3", c_void_p), ("b3", c_void_p),
+        ("in_scale", ctypes.c_float * 8), ("in_offset", ctypes.c_float * 8),
+        ("out_scale", ctypes.c_float * 4),
+        ("guard", ctypes.c_float),
+        ("fallback_count_dev", c_void_p),
+    ]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "menkf_create": (c_int32, [ctypes.POINTER(MenkfConfig), ctypes.POINTER(c_void_p)]),
+    "menkf_destroy": (None, [c_void_p]),
+    "menkf_last_error": (c_char_p, [c_void_p]),
+    "menkf_workspace_size": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
+    "menkf_set_workspace": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "menkf_set_probes": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "menkf_forecast": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "menkf_restrict": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "menkf_gain": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_uint64, c_uint64, c_void_p, c_void_p]),
+    "menkf_get_gain": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "menkf_set_cycle": (c_int32, [c_void_p, c_uint64, c_void_p]),
+    "menkf_update": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "menkf_prolong_smooth": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
+                                       ctypes.POINTER(MenkfNet), c_void_p]),
+    "menkf_get_status": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_int32, c_void_p]),
+    "menkf_observe": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
+    "menkf_diagnostics": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "menkf_ram_ratio": (c_double, [c_int32, c_int32, c_int32]),
+    "menkf_graph_begin": (c_int32, [c_void_p]),
+    "menkf_graph_end": (c_int32, [c_void_p, ctypes.POINTER(c_void_p)]),
+    "menkf_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "menkf_graph_destroy": (None, [c_void_p]),
+}
+
+TEST_HOOKS = {
+    "menkf_test_philox": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
+    "menkf_test_mfma": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+}
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmenkf.so and declare every entry point; raises if it is not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libmenkf.so not found at {path}: build it with `python -m paper_2012_10091_amd.build` "
+            "(hipcc, gfx950). There is no fallback implementation.")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in {**SIGNATURES, **TEST_HOOKS}.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib

@@ -1,0 +1,266 @@
+"""Thin Python binding of libmenkf (argument marshalling only).
+
+Every method maps one-to-one onto a ``menkf_*`` C entry point of
+include/menkf.h; torch tensors supply device memory and the current HIP
+stream.  No computation of the method happens here.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+MENKF_BURGERS1D = 1
+MENKF_NS2D = 2
+MENKF_F32 = 0
+MENKF_F64 = 1
+MENKF_GAIN_EXACT_R = 0
+MENKF_GAIN_SAMPLE_EE = 1
+MENKF_FINE = 0
+MENKF_COARSE = 1
+MENKF_PROLONG_PLAIN = 0
+MENKF_PROLONG_LEARNED = 1
+MENKF_PROLONG_LEARNED_FALLBACK = 2
+MENKF_CYCLE_DEVICE = (1 << 64) - 1
+
+STATUS = {0: "MENKF_OK", -1: "MENKF_E_ARG", -2: "MENKF_E_SHAPE", -3: "MENKF_E_NOT_SPD",
+          -4: "MENKF_E_NONFINITE", -5: "MENKF_E_HIP", -6: "MENKF_E_UNSUPPORTED", -7: "MENKF_E_WORKSPACE"}
+
+
+class MenkfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_config(model, nx, ny, ratio, n_members, n_probes, dt, precision=MENKF_F32,
+                gain_mode=MENKF_GAIN_EXACT_R, length=6.283185307179586, nu=0.0, gamma=1.4,
+                mach=0.3, reynolds=1000.0, prandtl=0.71, obs_sigma=0.01, anomaly_terms=0) -> _lib.MenkfConfig:
+    return _lib.MenkfConfig(model, precision, gain_mode, nx, ny, ratio, n_members, n_probes,
+                            length, dt, nu, gamma, mach, reynolds, prandtl, obs_sigma, anomaly_terms)
+
+
+def config_from(cfg) -> _lib.MenkfConfig:
+    """menkf_config from any object with the workload attributes (dim, nx, ny, ...)."""
+    return make_config(
+        MENKF_NS2D if cfg.dim == 2 else MENKF_BURGERS1D, cfg.nx, cfg.ny, cfg.ratio, cfg.n_members,
+        cfg.n_probes, cfg.dt, precision=MENKF_F64 if cfg.precision == "f64" else MENKF_F32,
+        gain_mode=getattr(cfg, "gain_mode", MENKF_GAIN_EXACT_R), length=cfg.length, nu=cfg.nu,
+        gamma=cfg.gamma, mach=cfg.mach, reynolds=cfg.reynolds, prandtl=cfg.prandtl,
+        obs_sigma=cfg.obs_sigma, anomaly_terms=getattr(cfg, "anomaly_terms", 0))
+
+
+def ram_ratio(dim: int, ratio: int, n_members: int) -> float:
+    return _lib.load().menkf_ram_ratio(dim, ratio, n_members)
+
+
+def last_error(ctx=None) -> str:
+    s = _lib.load().menkf_last_error(ctx)
+    return s.decode() if s else ""
+
+
+class Context:
+    """One assimilation instance: a menkf_ctx plus its torch-owned workspace."""
+
+    def __init__(self, cfg, device: str = "cuda", allocate: bool = True):
+        self.lib = _lib.load()
+        self.c_cfg = cfg if isinstance(cfg, _lib.MenkfConfig) else config_from(cfg)
+        h = ctypes.c_void_p()
+        st = self.lib.menkf_create(ctypes.byref(self.c_cfg), ctypes.byref(h))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+        self.handle = h
+        c = self.c_cfg
+        self.dim = 2 if c.model == MENKF_NS2D else 1
+        self.F = 4 if self.dim == 2 else 1
+        self.dtype = torch.float64 if c.precision == MENKF_F64 else torch.float32
+        self.nx, self.ny, self.ratio = c.nx, c.ny, c.ratio
+        self.nxc = c.nx // c.ratio
+        self.nyc = c.ny // c.ratio if self.dim == 2 else 1
+        self.N, self.Ny = c.n_members, c.n_probes
+        self.device = device
+        self.workspace = None
+        self._probes = None
+        if allocate:
+            self.allocate()
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, st):
+        if st != 0:
+            raise MenkfError(st, last_error(self.handle))
+
+    @property
+    def fine_shape(self):
+        return (self.F, self.nx) if self.dim == 1 else (self.F, self.ny, self.nx)
+
+    @property
+    def coarse_shape(self):
+        return (self.F, self.nxc) if self.dim == 1 else (self.F, self.nyc, self.nxc)
+
+    def _state(self, t, shape, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != self.dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous {self.dtype}")
+        if tuple(t.shape[-len(shape):]) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., {shape})")
+        return t
+
+    def workspace_size(self) -> int:
+        n = ctypes.c_size_t()
+        self._check(self.lib.menkf_workspace_size(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def allocate(self):
+        nbytes = self.workspace_size()
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.menkf_set_workspace(self.handle, _ptr(self.workspace), nbytes))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.menkf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ entry points
+    def set_probes(self, idx: torch.Tensor, comp: torch.Tensor):
+        for t in (idx, comp):
+            if t.dtype != torch.int32 or not t.is_cuda or t.numel() != self.Ny:
+                raise ValueError("probe tables must be CUDA int32 tensors of n_probes entries")
+        self._probes = (idx.contiguous(), comp.contiguous())
+        self._check(self.lib.menkf_set_probes(self.handle, _ptr(self._probes[0]), _ptr(self._probes[1])))
+
+    def forecast(self, level: int, state: torch.Tensor, nsteps: int, prev: Optional[torch.Tensor] = None,
+                 stream=None):
+        shape = self.fine_shape if level == MENKF_FINE else self.coarse_shape
+        self._state(state, shape, "state")
+        nb = 1 if state.dim() == len(shape) else state.shape[0]
+        if prev is not None:
+            self._state(prev, shape, "prev")
+            if prev.numel() != state.numel():
+                raise ValueError("prev must match state")
+        self._check(self.lib.menkf_forecast(self.handle, level, _ptr(state), nb, nsteps, _ptr(prev),
+                                            _stream(stream)))
+
+    def restrict(self, xf: torch.Tensor, xc: torch.Tensor, stream=None):
+        self._state(xf, self.fine_shape, "xf")
+        self._state(xc, self.coarse_shape, "xc")
+        self._check(self.lib.menkf_restrict(self.handle, _ptr(xf), _ptr(xc), _stream(stream)))
+
+    def gain(self, members: torch.Tensor, xstar: torch.Tensor, yobs: torch.Tensor, seed: int, cycle: int,
+             eps: Optional[torch.Tensor] = None, stream=None):
+        self._state(members, self.coarse_shape, "members")
+        if members.shape[0] != self.N:
+            raise ValueError("members must hold n_members states")
+        self._state(xstar, self.coarse_shape, "xstar")
+        if yobs.dtype != torch.float64 or yobs.numel() != self.Ny or not yobs.is_cuda:
+            raise ValueError("yobs must be a CUDA float64 tensor of n_probes entries")
+        if eps is not None and (eps.dtype != torch.float64 or eps.numel() != self.N * self.Ny
+                                or not eps.is_contiguous()):
+            raise ValueError("eps must be contiguous float64 (n_members, n_probes)")
+        self._check(self.lib.menkf_gain(self.handle, _ptr(members), _ptr(xstar), _ptr(yobs), seed, cycle,
+                                        _ptr(eps), _stream(stream)))
+
+    def set_cycle(self, cycle: int, stream=None):
+        self._check(self.lib.menkf_set_cycle(self.handle, cycle, _stream(stream)))
+
+    def get_gain(self, stream=None) -> torch.Tensor:
+        z = torch.empty((self.N + 1, self.N), dtype=torch.float64, device=self.device)
+        self._check(self.lib.menkf_get_gain(self.handle, _ptr(z), _stream(stream)))
+        return z
+
+    def update(self, members: torch.Tensor, deltac: torch.Tensor, stream=None):
+        self._state(members, self.coarse_shape, "members")
+        self._state(deltac, self.coarse_shape, "deltac")
+        self._check(self.lib.menkf_update(self.handle, _ptr(members), _ptr(deltac), _stream(stream)))
+
+    def prolong_smooth(self, deltac: torch.Tensor, xf: torch.Tensor, xprev: Optional[torch.Tensor],
+                       n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN,
+                       net=None, stream=None):
+        self._state(deltac, self.coarse_shape, "deltac")
+        self._state(xf, self.fine_shape, "xf")
+        if xprev is not None:
+            self._state(xprev, self.fine_shape, "xprev")
+        netp = None if net is None else ctypes.byref(net.c_struct())
+        self._check(self.lib.menkf_prolong_smooth(self.handle, _ptr(deltac), _ptr(xf), _ptr(xprev), n_sweeps,
+                                                  alpha, mode, netp, _stream(stream)))
+
+    def get_status(self, clear: bool = True, stream=None) -> int:
+        info = ctypes.c_int32()
+        st = self.lib.menkf_get_status(self.handle, ctypes.byref(info), int(clear), _stream(stream))
+        if st not in (0, -3):
+            self._check(st)
+        return info.value
+
+    def observe(self, level: int, state: torch.Tensor, stream=None) -> torch.Tensor:
+        shape = self.fine_shape if level == MENKF_FINE else self.coarse_shape
+        self._state(state, shape, "state")
+        nb = 1 if state.dim() == len(shape) else state.shape[0]
+        y = torch.empty((nb, self.Ny), dtype=torch.float64, device=self.device)
+        self._check(self.lib.menkf_observe(self.handle, level, _ptr(state), nb, _ptr(y), _stream(stream)))
+        return y
+
+    def diagnostics(self, xa: torch.Tensor, xt: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+        self._state(xa, self.fine_shape, "xa")
+        self._state(xt, self.fine_shape, "xt")
+        if out is None:
+            out = torch.empty(3, dtype=torch.float64, device=self.device)
+        self._check(self.lib.menkf_diagnostics(self.handle, _ptr(xa), _ptr(xt), _ptr(out), _stream(stream)))
+        return out
+
+
+class Graph:
+    """A captured sequence of menkf_* calls (menkf_graph_* entry points)."""
+
+    def __init__(self, handle):
+        self.lib = _lib.load()
+        self.handle = handle
+
+    @staticmethod
+    def begin(stream):
+        lib = _lib.load()
+        st = lib.menkf_graph_begin(_stream(stream))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+
+    @staticmethod
+    def end(stream) -> "Graph":
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        st = lib.menkf_graph_end(_stream(stream), ctypes.byref(h))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+        return Graph(h)
+
+    def launch(self, stream=None):
+        st = self.lib.menkf_graph_launch(self.handle, _stream(stream))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+
+    def __del__(self):
+        try:
+            if self.handle:
+                self.lib.menkf_graph_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

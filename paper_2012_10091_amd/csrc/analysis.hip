@@ -1,0 +1,714 @@
+// Ensemble Kalman analysis on the coarse level (Algo. 3 steps 3, 4, 7, 8;
+// Algo. 1 steps 2-7) and the gain of the projected fine forecast x*
+// (Algo. 4 step 5).
+//
+// With N members, N_y probes and normalised anomalies
+//   X = [x^(i) - xbar]/sqrt(N-1),  Y = [H(x^(i)) - ybar]/sqrt(N-1)   (secant form),
+// the gain is K = X Y^T S^-1 with S = Y Y^T + R (or Y Y^T + E E^T).  The
+// state-space gain is never formed: with B = [D | d*],
+// D_i = y^o + eps^(i) - H(x^(i)), d* = y^o - H(x*), the analysis needs only
+//   Z = Y^T S^-1 B        (N x (N+1)),  x^a(i) = x^(i) + X Z[:, i],  delta^C = X Z[:, N].
+//
+// Z comes out of one FP64 Cholesky factorisation of the symmetric
+// augmented matrix
+//        [ S    B   Y ]            rows/cols 0..n-1      : S (padded to a block multiple with I)
+//   A =  [ B^T  0   0 ]            rows n.. : B^T (N+1 rows) then Y^T (N rows)
+//        [ Y^T  0   0 ]
+// stopped after the first n columns: the trailing block is then the Schur
+// complement -[B Y]^T S^-1 [B Y], whose (Y^T, B) block is -Z.  This folds
+// the two triangular solves of S^-1 B into the factorisation's own panel
+// and trailing updates.
+//
+// Precision: member states FP32; H(x) and anomalies in FP64; S = Y Y^T
+// from BF16 anomalies on MFMA with FP32 accumulation, stored FP64;
+// Cholesky, Z and the x* column (delta^C) in FP64; member update
+// X Z[:, :N] on BF16 MFMA with FP32 accumulation.  MENKF_F64 contexts keep
+// everything in FP64.
+#include <utility>
+
+#include "common.hpp"
+
+namespace menkf {
+
+// ----------------------------------------------------------------- Philox4x32-10
+// Salmon et al., SC'11: per round the products M0*c0 and M1*c2 are split
+// into hi/lo words and the counter becomes (hi1^c1^k0, lo1, hi0^c3^k1, lo0);
+// the key advances by the Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+    }
+}
+
+// Standard normal for (member i, probe p) at a cycle: counter
+// (p >> 1, i, cycle, 0x5045), 53-bit uniforms u = (k + 1/2) 2^-53 from
+// word pairs, Box-Muller cos branch for even p and sin branch for odd p.
+__device__ __forceinline__ double perturb_normal(uint64_t seed, uint64_t cycle, int i, int p) {
+    uint32_t c[4] = {(uint32_t)(p >> 1), (uint32_t)i, (uint32_t)cycle, 0x5045u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) * 0x1p-53;
+    const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) * 0x1p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 6.283185307179586 * u2;
+    return (p & 1) ? rad * sin(ang) : rad * cos(ang);
+}
+
+__global__ void philox_test_kernel(const uint32_t *in, uint32_t *out, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[4] = {in[6 * i], in[6 * i + 1], in[6 * i + 2], in[6 * i + 3]};
+    philox4x32_10(c, in[6 * i + 4], in[6 * i + 5]);
+    for (int k = 0; k < 4; ++k) out[4 * i + k] = c[k];
+}
+
+// ----------------------------------------------------------------- observation operator
+// y[s][p] for nb states (plus an optional extra state as row nb): H^F on the
+// fine level, H^C = H^F o Pi_F (cubic Lagrange at the probe node) on the coarse level.
+template <typename T>
+__global__ __launch_bounds__(256) void obs_eval(const T *__restrict__ states, long long stride, int nb,
+                                                const T *__restrict__ extra, const int32_t *__restrict__ idx,
+                                                const int32_t *__restrict__ comp, int Ny, double *__restrict__ y,
+                                                int ldy, int coarse, int dim, int nx, int ny, int r, int nxc,
+                                                int nyc) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sidx = blockIdx.y;
+    if (p >= Ny) return;
+    const T *st = sidx < nb ? states + (long long)sidx * stride : extra;
+    const int node = idx[p];
+    const int cp = comp[p];
+    double val;
+    if (!coarse) {
+        if (dim == 1) {
+            val = (double)st[node];
+        } else {
+            const long long nf = (long long)nx * ny;
+            const double rho = (double)st[node];
+            const double mom = (double)st[(cp == 0 ? nf : 2 * nf) + node];
+            val = mom / rho;
+        }
+    } else {
+        const int fx = node % nx, fy = node / nx;
+        const int jx = fx / r, mx = fx - jx * r;
+        double wx[4];
+        lagrange4<double>((double)mx / (double)r, wx);
+        if (dim == 1) {
+            double a = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) a += wx[b] * (double)st[wrap(jx - 1 + b, nxc)];
+            val = a;
+        } else {
+            const int jy = fy / r, my = fy - jy * r;
+            double wy[4];
+            lagrange4<double>((double)my / (double)r, wy);
+            const long long nc = (long long)nxc * nyc;
+            const T *rho_f = st;
+            const T *mom_f = st + (cp == 0 ? nc : 2 * nc);
+            double rho = 0.0, mom = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const long long row = (long long)wrap(jy - 1 + a, nyc) * nxc;
+                double ra = 0.0, ma = 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const long long g = row + wrap(jx - 1 + b, nxc);
+                    ra += wx[b] * (double)rho_f[g];
+                    ma += wx[b] * (double)mom_f[g];
+                }
+                rho += wy[a] * ra;
+                mom += wy[a] * ma;
+            }
+            val = mom / rho;
+        }
+    }
+    y[(long long)sidx * ldy + p] = val;
+}
+
+// ----------------------------------------------------------------- anomalies and innovations
+// One thread per (padded) probe p.  Writes, in FP64,
+//   Yk[p][0..N) = Y_p, Yk[p][N..2N) = E_p in sample mode, zero up to kdim;
+//   A[(nyp + j) ld + p] = D_pj (j < N), d*_p (j = N), Y_p,j-N-1 (N < j <= 2N).
+// S and the right-hand sides are built from the very same Y values: S^-1
+// amplifies any inconsistency between them by up to 1/sigma^2.
+__global__ __launch_bounds__(256) void obs_pack(const double *__restrict__ yraw, int ldy, int N, int Ny, int nyp,
+                                                const double *__restrict__ yobs, const double *__restrict__ eps,
+                                                uint64_t seed, uint64_t cycle, const uint64_t *__restrict__ dcycle,
+                                                double sigma, int sample_mode, double *__restrict__ Yk, int kdim,
+                                                double *__restrict__ A, int ld) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nyp) return;
+    if (dcycle) cycle = *dcycle;
+    double *yk = Yk + (long long)p * kdim;
+    double *B = A + (long long)nyp * ld + p;
+    if (p >= Ny) {
+        for (int k = 0; k < kdim; ++k) yk[k] = 0.0;
+        for (int j = 0; j <= 2 * N; ++j) B[(long long)j * ld] = 0.0;
+        return;
+    }
+    const double scale = 1.0 / sqrt((double)(N - 1));
+    double ybar = 0.0, ebar = 0.0;
+    for (int i = 0; i < N; ++i) ybar += yraw[(long long)i * ldy + p];
+    ybar /= (double)N;
+    if (sample_mode) {
+        for (int i = 0; i < N; ++i)
+            ebar += eps ? eps[(long long)i * Ny + p] : sigma * perturb_normal(seed, cycle, i, p);
+        ebar /= (double)N;
+    }
+    const double yo = yobs[p];
+    for (int i = 0; i < N; ++i) {
+        const double yi = yraw[(long long)i * ldy + p];
+        const double e = eps ? eps[(long long)i * Ny + p] : sigma * perturb_normal(seed, cycle, i, p);
+        const double an = (yi - ybar) * scale;
+        yk[i] = an;
+        B[(long long)i * ld] = yo + e - yi;
+        B[(long long)(N + 1 + i) * ld] = an;
+        if (sample_mode) yk[N + i] = (e - ebar) * scale;
+    }
+    for (int k = sample_mode ? 2 * N : N; k < kdim; ++k) yk[k] = 0.0;
+    B[(long long)N * ld] = yo - yraw[(long long)N * ldy + p];
+}
+
+// Zero the trailing (Schur) block and the padding rows of the extra block,
+// and reset the status word for this factorisation.
+__global__ __launch_bounds__(256) void zero_extra(double *__restrict__ A, int ld, int nyp, int mext,
+                                                  int32_t *__restrict__ info) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
+    const int rows = ld - nyp;
+    const long long tot = (long long)rows * ld;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(t / ld), c = (int)(t - (long long)a * ld);
+        if (c >= nyp || a >= mext) A[(long long)(nyp + a) * ld + c] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void tri_index(int t, int &bi, int &bj) {
+    int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    bi = i;
+    bj = t - i * (i + 1) / 2;
+}
+
+// ----------------------------------------------------------------- blocked FP64 Cholesky
+// Right-looking, block size 64, on the lower triangle of A (row-major,
+// element (r, c) at r*ld + c, r >= c).  Step k: factor the diagonal block
+// and invert its factor (one wave), panel X = A_ik L_kk^-T for every block
+// row below (including the extra rows), trailing update A_ij -= L_ik L_jk^T
+// for k < j <= i over the whole matrix (the extra rows accumulate the Schur
+// complement).  Every kernel exits if the status word is set.
+constexpr int LDP = 65;  // padded LDS row (doubles)
+
+// Factor the 64x64 diagonal block and invert its factor in one sweep of
+// 64 pivot steps.  W is the block being reduced (columns are never rescaled
+// in place) and Xw the rows of the inverse in unscaled form; at step j,
+// with piv = W[j][j],
+//   W[r][c]  -= W[r][j] W[c][j] / piv    (j < c <= r)      Schur update
+//   Xw[r][c] -= W[r][j] Xw[j][c] / piv   (r > j, c <= j)   inverse rows
+// and at the end L[r][c] = W[r][c] / d_c with d_c = sqrt(W[c][c]),
+// L^-1[r][c] = Xw[r][c] / d_r.
+// Thread t owns row r = t / 4 and the 16 columns c = 4 i + t % 4 of both W
+// and Xw in registers.  Step j only needs column j of W and row j of Xw from
+// other threads: their owners publish them to a double-buffered LDS slot,
+// so each pivot costs one barrier.  The step loop is unrolled at compile
+// time so that register indices are static.
+__global__ __launch_bounds__(256) void chol_diag(double *__restrict__ A, int ld, int k, double *__restrict__ Linv,
+                                                 int32_t *__restrict__ info) {
+    __shared__ double colbuf[2][64];
+    __shared__ double rowbuf[2][64];
+    __shared__ double dsq[64];
+    if (*info != 0) return;
+    const int t = threadIdx.x;
+    const int r = t >> 2, q = t & 3;
+    double *Ak = A + (long long)(k * 64) * ld + k * 64;
+    double w[16], x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int c = 4 * i + q;
+        w[i] = c <= r ? Ak[(long long)r * ld + c] : 0.0;
+        x[i] = c == r ? 1.0 : 0.0;
+    }
+    int bad = 0;
+    // Branch-free pivot step: every thread reads one published value per
+    // owned column (row j of Xw for c <= j, column j of W otherwise) and
+    // applies the update through selects; rows r <= j use m = 0.
+#define MENKF_DIAG_STEP(J)                                                   \
+    if (!bad) {                                                              \
+        constexpr int b_ = (J) & 1, ji_ = (J) >> 2, jq_ = (J) & 3;           \
+        if (q == jq_) colbuf[b_][r] = w[ji_];                                \
+        if (r == (J)) {                                                      \
+            _Pragma("unroll") for (int i = 0; i < 16; ++i)                   \
+                rowbuf[b_][4 * i + q] = x[i];                                \
+        }                                                                    \
+        __syncthreads();                                                     \
+        const double piv = colbuf[b_][J];                                    \
+        if (t == 0) dsq[J] = piv;                                            \
+        bad = (piv > 0.0) ? 0 : (J) + 1;                                     \
+        const double inv = 1.0 / piv;                                        \
+        const double m = r > (J) ? colbuf[b_][r] * inv : 0.0;                \
+        _Pragma("unroll") for (int i = 0; i < 16; ++i) {                     \
+            const int c = 4 * i + q;                                         \
+            const bool lo = c <= (J);                                        \
+            const double v = lo ? rowbuf[b_][c] : colbuf[b_][c];             \
+            const double nv = (lo ? x[i] : w[i]) - m * v;                    \
+            x[i] = lo ? nv : x[i];                                           \
+            w[i] = (!lo && c <= r) ? nv : w[i];                              \
+        }                                                                    \
+    }
+#define MENKF_DIAG_STEP4(J) MENKF_DIAG_STEP(J) MENKF_DIAG_STEP(J + 1) MENKF_DIAG_STEP(J + 2) MENKF_DIAG_STEP(J + 3)
+#define MENKF_DIAG_STEP16(J) MENKF_DIAG_STEP4(J) MENKF_DIAG_STEP4(J + 4) MENKF_DIAG_STEP4(J + 8) MENKF_DIAG_STEP4(J + 12)
+    MENKF_DIAG_STEP16(0)
+    MENKF_DIAG_STEP16(16)
+    MENKF_DIAG_STEP16(32)
+    MENKF_DIAG_STEP16(48)
+#undef MENKF_DIAG_STEP16
+#undef MENKF_DIAG_STEP4
+#undef MENKF_DIAG_STEP
+    if (bad) {
+        if (t == 0) *info = k * 64 + bad;
+        return;
+    }
+    __syncthreads();
+    if (t < 64) dsq[t] = sqrt(dsq[t]);     // pivots -> d_c
+    __syncthreads();
+    const double dr = dsq[r];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int c = 4 * i + q;
+        if (c <= r) Ak[(long long)r * ld + c] = c == r ? dr : w[i] / dsq[c];
+        Linv[r * 64 + c] = c <= r ? x[i] / dr : 0.0;
+    }
+}
+
+// acc += P Q^T for 64-row blocks P (rows of length K at ldp) and Q, K a
+// multiple of 64, staged 64 columns at a time through LDS.  FP64 MFMA
+// 16x16x4; 4 waves, each a 32x32 quarter held as 2x2 16x16 accumulators.
+// v_mfma_f64_16x16x4f64: lane l holds A(l % 16, l / 16), B(l / 16, l % 16);
+// result element e of lane l is row 4 e + l / 16, column l % 16.
+__device__ __forceinline__ void mfma_nt_64_acc(const double *__restrict__ P, long long ldp,
+                                               const double *__restrict__ Q, long long ldq, int K,
+                                               f64x4 (&acc)[2][2], double *Ps, double *Qs) {
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
+    const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+    for (int k0 = 0; k0 < K; k0 += 64) {
+        __syncthreads();
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int r = e >> 6, c = e & 63;
+            Ps[r * LDP + c] = P[r * ldp + k0 + c];
+            Qs[r * LDP + c] = Q[r * ldq + k0 + c];
+        }
+        __syncthreads();
+        for (int kk = 0; kk < 64; kk += 4) {
+            const int kcol = kk + (l >> 4);
+            double a[2], b[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                a[s] = Ps[(r0 + s * 16 + (l & 15)) * LDP + kcol];
+                b[s] = Qs[(c0 + s * 16 + (l & 15)) * LDP + kcol];
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[u], acc[s][u], 0, 0, 0);
+        }
+    }
+}
+
+// Visit the accumulator entries: f(row, col, value) within the 64x64 block.
+template <typename Fn>
+__device__ __forceinline__ void for_each_acc(const f64x4 (&acc)[2][2], Fn f) {
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
+    const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f(r0 + s * 16 + 4 * e + (l >> 4), c0 + u * 16 + (l & 15), acc[s][u][e]);
+}
+
+// C (64x64, ldc) = beta*C + sgn * P Q^T with K = 64.
+__device__ __forceinline__ void gemm_nt_64(const double *__restrict__ P, long long ldp, const double *__restrict__ Q,
+                                           long long ldq, double *__restrict__ C, long long ldc, double beta,
+                                           double sgn, double *Ps, double *Qs, bool lower_only) {
+    f64x4 acc[2][2] = {};
+    mfma_nt_64_acc(P, ldp, Q, ldq, 64, acc, Ps, Qs);
+    for_each_acc(acc, [&](int r, int c, double v) {
+        if (lower_only && c > r) return;
+        double *dst = C + (long long)r * ldc + c;
+        *dst = (beta != 0.0 ? beta * *dst : 0.0) + sgn * v;
+    });
+}
+
+// S = Yk Yk^T + R on the lower 64x64 blocks (identity on the padding rows).
+__global__ __launch_bounds__(256) void syrk_f64_mfma(const double *__restrict__ Yk, int kdim, int Ny, double r_diag,
+                                                     double *__restrict__ A, int ld) {
+    extern __shared__ double smem_d[];
+    int bi, bj;
+    tri_index(blockIdx.x, bi, bj);
+    f64x4 acc[2][2] = {};
+    mfma_nt_64_acc(Yk + (long long)bi * 64 * kdim, kdim, Yk + (long long)bj * 64 * kdim, kdim, kdim, acc, smem_d,
+                   smem_d + 64 * LDP);
+    double *C = A + (long long)(bi * 64) * ld + bj * 64;
+    for_each_acc(acc, [&](int r, int c, double v) {
+        const int p = bi * 64 + r, q = bj * 64 + c;
+        if (q > p) return;
+        if (p == q) v += p < Ny ? r_diag : 1.0;
+        C[(long long)r * ld + c] = v;
+    });
+}
+
+__global__ __launch_bounds__(256) void chol_panel(double *__restrict__ A, int ld, int k, const double *__restrict__ Linv,
+                                                  const int32_t *__restrict__ info) {
+    extern __shared__ double smem_d[];
+    if (*info != 0) return;
+    const int i = k + 1 + blockIdx.x;
+    double *Aik = A + (long long)(i * 64) * ld + k * 64;
+    // X = A_ik Linv^T, in place (A_ik is staged in LDS before any write)
+    gemm_nt_64(Aik, ld, Linv, 64, Aik, ld, 0.0, 1.0, smem_d, smem_d + 64 * LDP, false);
+}
+
+__global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int ld, int k, int nblk,
+                                                   const int32_t *__restrict__ info) {
+    extern __shared__ double smem_d[];
+    if (*info != 0) return;
+    int bi, bj;
+    tri_index(blockIdx.x, bi, bj);
+    const int i = k + 1 + bi, j = k + 1 + bj;
+    (void)nblk;
+    const double *Lik = A + (long long)(i * 64) * ld + k * 64;
+    const double *Ljk = A + (long long)(j * 64) * ld + k * 64;
+    double *Aij = A + (long long)(i * 64) * ld + j * 64;
+    gemm_nt_64(Lik, ld, Ljk, ld, Aij, ld, 1.0, -1.0, smem_d, smem_d + 64 * LDP, i == j);
+}
+
+// ----------------------------------------------------------------- Z from the Schur block
+// Z[i][j] = -M[N+1+i][j] with M the trailing block (rows/cols from nyp).
+// z64[j][i] = Z[i][j]; zstar[i] = Z[i][N]; zt holds Z^T for the member
+// update, zero-padded to npad x npad: FP64 for MENKF_F64 contexts, else a
+// BF16 pair (hi = bf16(z), lo = bf16(z - hi)) at zt and zt + npad^2.
+template <typename ZT>
+__global__ __launch_bounds__(256) void gain_extract(const double *__restrict__ A, int ld, int nyp, int N, int npad,
+                                                    double *__restrict__ z64, ZT *__restrict__ zt,
+                                                    double *__restrict__ zstar, uint64_t *__restrict__ dcycle) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0 && dcycle) *dcycle += 1;
+    if (t >= npad * npad) return;
+    const int j = t / npad, i = t - j * npad;
+    const double *M = A + (long long)nyp * ld + nyp;
+    double z = 0.0;
+    if (i < N && j < N) z = -M[(long long)(N + 1 + i) * ld + j];
+    if constexpr (sizeof(ZT) == 8) {
+        zt[t] = z;
+    } else {
+        const ZT hi = ZT((float)z);
+        zt[t] = hi;
+        zt[t + npad * npad] = ZT((float)(z - (double)(float)hi));
+    }
+    if (i < N && j < N) z64[(long long)j * N + i] = z;
+    if (j == 0) {
+        const double zs = i < N ? -M[(long long)(N + 1 + i) * ld + N] : 0.0;
+        zstar[i] = zs;
+        if (i < N) z64[(long long)N * N + i] = zs;
+    }
+}
+
+// ----------------------------------------------------------------- member update
+// x^a(j) = x^(j) + sum_i Xa_i Z[i][j] and delta^C = sum_i Xa_i z*_i, with
+// Xa_i = (x^(i) - xbar) / sqrt(N-1) formed on the fly from the members.
+// PW points per workgroup (PW * NPAD floats staged in LDS); the output tile
+// (members x points) is Zt (NPAD x NPAD, BF16) times Xa (NPAD x 32 points)
+// per wave.  With PW < 128 the four waves also split the output member
+// tiles between them.
+// TERMS = 1: plain BF16 operands.  TERMS = 3: each operand split into a
+// BF16 pair v = hi + lo and the product taken as hi*hi + hi*lo + lo*hi, all
+// on BF16 MFMA with FP32 accumulation (about FP32 accuracy at no extra
+// memory traffic).
+template <int NPAD, int TERMS>
+__global__ __launch_bounds__(256) void update_bf16(float *__restrict__ X, float *__restrict__ dc,
+                                                   const __bf16 *__restrict__ zt, const double *__restrict__ zstar,
+                                                   int N, long long npts, float scale,
+                                                   const int32_t *__restrict__ info) {
+    constexpr int PW = NPAD <= 128 ? 128 : 64;   // points per workgroup
+    constexpr int WPP = PW / 32;                 // waves per point set
+    constexpr int MSPLIT = 4 / WPP;              // waves sharing one point set
+    __shared__ float xs[NPAD * PW];
+    __shared__ float meanf[PW];
+    if (*info != 0) return;
+    const long long p0 = (long long)blockIdx.x * PW;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NPAD * PW; e += 256) {
+        const int i = e / PW, p = e - i * PW;
+        xs[e] = (i < N && p0 + p < npts) ? X[(long long)i * npts + p0 + p] : 0.0f;
+    }
+    __syncthreads();
+    if (tid < PW) {
+        double m = 0.0;
+        for (int i = 0; i < N; ++i) m += (double)xs[i * PW + tid];
+        m /= (double)N;
+        meanf[tid] = (float)m;
+        double d = 0.0;
+        const double sc = (double)scale;
+        for (int i = 0; i < N; ++i) d += ((double)xs[i * PW + tid] - m) * sc * zstar[i];
+        if (p0 + tid < npts) dc[p0 + tid] = (float)d;
+    }
+    __syncthreads();
+    const int w = tid >> 6, l = tid & 63;
+    const int pl = (w % WPP) * 32 + (l & 31);
+    const int msub = w / WPP;
+    const float mp = meanf[pl];
+    bf16x8 bfrag[NPAD / 16];
+    bf16x8 bfrag_lo[TERMS == 3 ? NPAD / 16 : 1];
+#pragma unroll
+    for (int ks = 0; ks < NPAD / 16; ++ks) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = ks * 16 + (l >> 5) * 8 + e;
+            const float v = k < N ? (xs[k * PW + pl] - mp) * scale : 0.0f;
+            const __bf16 hi = (__bf16)v;
+            bfrag[ks][e] = hi;
+            if constexpr (TERMS == 3) bfrag_lo[ks][e] = (__bf16)(v - (float)hi);
+        }
+    }
+#pragma unroll
+    for (int mt = msub; mt < NPAD / 32; mt += MSPLIT) {
+        f32x16 acc = {};
+        const __bf16 *za = zt + (long long)(mt * 32 + (l & 31)) * NPAD + (l >> 5) * 8;
+#pragma unroll
+        for (int ks = 0; ks < NPAD / 16; ++ks) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(za + ks * 16);
+            if constexpr (TERMS == 3) {
+                const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(za + NPAD * NPAD + ks * 16);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bfrag[ks], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfrag_lo[ks], acc, 0, 0, 0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfrag[ks], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int j = mt * 32 + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
+            if (j < N && p0 + pl < npts) X[(long long)j * npts + p0 + pl] = xs[j * PW + pl] + acc[e];
+        }
+    }
+}
+
+// FP64 update for MENKF_F64 contexts: 64 points per workgroup, one thread per point.
+__global__ __launch_bounds__(64) void update_f64(double *__restrict__ X, double *__restrict__ dc,
+                                                 const double *__restrict__ zt, const double *__restrict__ zstar,
+                                                 int N, int npad, long long npts, double scale,
+                                                 const int32_t *__restrict__ info) {
+    extern __shared__ double xsd[];
+    if (*info != 0) return;
+    const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
+    const bool ok = p < npts;
+    double m = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double v = ok ? X[(long long)i * npts + p] : 0.0;
+        xsd[i * 64 + threadIdx.x] = v;
+        m += v;
+    }
+    m /= (double)N;
+    for (int i = 0; i < N; ++i) xsd[i * 64 + threadIdx.x] = (xsd[i * 64 + threadIdx.x] - m) * scale;
+    if (!ok) return;
+    double d = 0.0;
+    for (int i = 0; i < N; ++i) d += xsd[i * 64 + threadIdx.x] * zstar[i];
+    dc[p] = d;
+    for (int j = 0; j < N; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < N; ++i) s += xsd[i * 64 + threadIdx.x] * zt[(long long)j * npad + i];
+        X[(long long)j * npts + p] += s;
+    }
+}
+
+// ----------------------------------------------------------------- launchers
+static hipError_t set_lds(const void *k, size_t bytes) {
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, double *y, const int32_t *idx,
+                          const int32_t *comp, hipStream_t s) {
+    const bool coarse = level == MENKF_COARSE;
+    const long long stride = (coarse ? p.nc : p.nf) * p.F;
+    dim3 grid((p.Ny + 255) / 256, nb);
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(obs_eval<double>, grid, dim3(256), 0, s, (const double *)state, stride, nb,
+                           (const double *)nullptr, idx, comp, p.Ny, y, p.Ny, coarse ? 1 : 0, p.dim, p.nx, p.ny,
+                           p.cfg.ratio, p.nxc, p.nyc);
+    else
+        hipLaunchKernelGGL(obs_eval<float>, grid, dim3(256), 0, s, (const float *)state, stride, nb,
+                           (const float *)nullptr, idx, comp, p.Ny, y, p.Ny, coarse ? 1 : 0, p.dim, p.nx, p.ny,
+                           p.cfg.ratio, p.nxc, p.nyc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, const double *yobs, uint64_t seed,
+                       uint64_t cycle, const double *eps, const int32_t *idx, const int32_t *comp, void *ws,
+                       hipStream_t s) {
+    char *w = (char *)ws;
+    int32_t *info = (int32_t *)(w + p.off_info);
+    double *yraw = (double *)(w + p.off_scratch);
+    double *A = (double *)(w + p.off_a);
+    double *Linv = (double *)(w + p.off_linv);
+    double *Yk = (double *)(w + p.off_yb);
+    const int N = p.N;
+    const long long stride = p.nc * p.F;
+    const bool f64 = p.cfg.precision == MENKF_F64;
+    const int sample = p.cfg.gain_mode == MENKF_GAIN_SAMPLE_EE ? 1 : 0;
+    const double rdiag = p.cfg.obs_sigma * p.cfg.obs_sigma;
+    hipError_t e;
+    const size_t lds = 2 * 64 * LDP * sizeof(double);
+    if ((e = set_lds((const void *)chol_panel, lds)) != hipSuccess) return e;
+    if ((e = set_lds((const void *)chol_update, lds)) != hipSuccess) return e;
+    if ((e = set_lds((const void *)syrk_f64_mfma, lds)) != hipSuccess) return e;
+    // 1. H^C of the members and of x*
+    dim3 g1((p.Ny + 255) / 256, N + 1);
+    if (f64)
+        hipLaunchKernelGGL(obs_eval<double>, g1, dim3(256), 0, s, (const double *)members, stride, N,
+                           (const double *)xstar, idx, comp, p.Ny, yraw, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
+                           p.nxc, p.nyc);
+    else
+        hipLaunchKernelGGL(obs_eval<float>, g1, dim3(256), 0, s, (const float *)members, stride, N,
+                           (const float *)xstar, idx, comp, p.Ny, yraw, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
+                           p.nxc, p.nyc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 2. clear the Schur block, reset status
+    hipLaunchKernelGGL(zero_extra, dim3(256), dim3(256), 0, s, A, p.ld, p.nyp, p.mext, info);
+    // 3. anomalies, innovations, perturbations (FP64)
+    uint64_t *dcycle = cycle == MENKF_CYCLE_DEVICE ? (uint64_t *)(w + p.off_info + 64) : nullptr;
+    hipLaunchKernelGGL(obs_pack, dim3((p.nyp + 255) / 256), dim3(256), 0, s, yraw, p.nyp, N, p.Ny, p.nyp, yobs, eps,
+                       seed, cycle, (const uint64_t *)dcycle, p.cfg.obs_sigma, sample, Yk, p.kdim, A, p.ld);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 4. S = Y Y^T + R (+ identity on the padding), FP64 MFMA
+    const int nbs = p.nyp / CHOL_NB;
+    hipLaunchKernelGGL(syrk_f64_mfma, dim3(nbs * (nbs + 1) / 2), dim3(256), lds, s, (const double *)Yk, p.kdim, p.Ny,
+                       sample ? 0.0 : rdiag, A, p.ld);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // 5. blocked Cholesky of the first nyp columns, Schur complement on the rest
+    const int nblk = p.ld / CHOL_NB;
+    for (int k = 0; k < nbs; ++k) {
+        hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, p.ld, k, Linv, info);
+        const int below = nblk - k - 1;
+        if (below > 0) {
+            hipLaunchKernelGGL(chol_panel, dim3(below), dim3(256), lds, s, A, p.ld, k, (const double *)Linv, info);
+            hipLaunchKernelGGL(chol_update, dim3(below * (below + 1) / 2), dim3(256), lds, s, A, p.ld, k, nblk,
+                               info);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // 6. Z
+    const int ge = (p.npad * p.npad + 255) / 256;
+    if (f64)
+        hipLaunchKernelGGL(gain_extract<double>, dim3(ge), dim3(256), 0, s, (const double *)A, p.ld, p.nyp, N, p.npad,
+                           (double *)(w + p.off_z), (double *)(w + p.off_zt), (double *)(w + p.off_zstar), dcycle);
+    else
+        hipLaunchKernelGGL(gain_extract<__bf16>, dim3(ge), dim3(256), 0, s, (const double *)A, p.ld, p.nyp, N,
+                           p.npad, (double *)(w + p.off_z), (__bf16 *)(w + p.off_zt), (double *)(w + p.off_zstar),
+                           dcycle);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_gain(const Plan &p, double *z, void *ws, hipStream_t s) {
+    return hipMemcpyAsync(z, (char *)ws + p.off_z, sizeof(double) * (size_t)(p.N + 1) * p.N,
+                          hipMemcpyDeviceToDevice, s);
+}
+
+template <int NPAD>
+static void launch_update_np(const Plan &p, dim3 grid, hipStream_t s, float *X, float *dc, const __bf16 *zt,
+                             const double *zs, long long npts, float scale, const int32_t *info) {
+    if (p.cfg.anomaly_terms == 1)
+        hipLaunchKernelGGL((update_bf16<NPAD, 1>), grid, dim3(256), 0, s, X, dc, zt, zs, p.N, npts, scale, info);
+    else
+        hipLaunchKernelGGL((update_bf16<NPAD, 3>), grid, dim3(256), 0, s, X, dc, zt, zs, p.N, npts, scale, info);
+}
+
+hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipStream_t s) {
+    char *w = (char *)ws;
+    const int32_t *info = (const int32_t *)(w + p.off_info);
+    const long long npts = p.nc * p.F;
+    const int N = p.N;
+    if (p.cfg.precision == MENKF_F64) {
+        const size_t lds = (size_t)N * 64 * sizeof(double);
+        hipError_t e = set_lds((const void *)update_f64, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(update_f64, dim3((unsigned)((npts + 63) / 64)), dim3(64), lds, s, (double *)members,
+                           (double *)dc, (const double *)(w + p.off_zt), (const double *)(w + p.off_zstar), N, p.npad,
+                           npts, 1.0 / sqrt((double)(N - 1)), info);
+        return hipGetLastError();
+    }
+    const int pw = p.npad <= 128 ? 128 : 64;
+    const dim3 grid((unsigned)((npts + pw - 1) / pw));
+    const float scale = (float)(1.0 / sqrt((double)(N - 1)));
+    const __bf16 *zt = (const __bf16 *)(w + p.off_zt);
+    const double *zs = (const double *)(w + p.off_zstar);
+    float *X = (float *)members;
+    float *D = (float *)dc;
+    switch (p.npad) {
+        case 32: launch_update_np<32>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        case 64: launch_update_np<64>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        case 96: launch_update_np<96>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        case 128: launch_update_np<128>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        case 160: launch_update_np<160>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        case 192: launch_update_np<192>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        case 224: launch_update_np<224>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        case 256: launch_update_np<256>(p, grid, s, X, D, zt, zs, npts, scale, info); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace menkf
+
+// Test hook: Philox4x32-10 on n (counter, key) sextuples, device pointers.
+extern "C" int menkf_test_philox(const uint32_t *in_dev, uint32_t *out_dev, int n, void *stream) {
+    hipLaunchKernelGGL(menkf::philox_test_kernel, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)stream, in_dev,
+                       out_dev, n);
+    return (int)hipGetLastError();
+}
+
+// Test hook: one MFMA with the operand/result lane mapping the kernels above
+// rely on.  which = 0: A 32x16 BF16, B 16x32 BF16 (row-major) -> C 32x32 FP32;
+// which = 1: A 16x4 FP64, B 4x16 FP64 -> C 16x16 FP64.  One wave.
+namespace menkf {
+__global__ __launch_bounds__(64) void mfma_test_bf16(const __bf16 *a, const __bf16 *b, float *out) {
+    const int l = threadIdx.x;
+    bf16x8 av, bv;
+    for (int e = 0; e < 8; ++e) {
+        av[e] = a[(l & 31) * 16 + (l >> 5) * 8 + e];
+        bv[e] = b[((l >> 5) * 8 + e) * 32 + (l & 31)];
+    }
+    f32x16 acc = {};
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    for (int e = 0; e < 16; ++e) out[(8 * (e >> 2) + 4 * (l >> 5) + (e & 3)) * 32 + (l & 31)] = acc[e];
+}
+__global__ __launch_bounds__(64) void mfma_test_f64(const double *a, const double *b, double *out) {
+    const int l = threadIdx.x;
+    f64x4 acc = {};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[(l & 15) * 4 + (l >> 4)], b[(l >> 4) * 16 + (l & 15)], acc, 0, 0, 0);
+    for (int e = 0; e < 4; ++e) out[(4 * e + (l >> 4)) * 16 + (l & 15)] = acc[e];
+}
+}  // namespace menkf
+
+extern "C" int menkf_test_mfma(int which, const void *a, const void *b, void *out, void *stream) {
+    if (which == 0)
+        hipLaunchKernelGGL(menkf::mfma_test_bf16, dim3(1), dim3(64), 0, (hipStream_t)stream, (const __bf16 *)a,
+                           (const __bf16 *)b, (float *)out);
+    else if (which == 1)
+        hipLaunchKernelGGL(menkf::mfma_test_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, (const double *)a,
+                           (const double *)b, (double *)out);
+    else
+        return (int)hipErrorInvalidValue;
+    return (int)hipGetLastError();
+}

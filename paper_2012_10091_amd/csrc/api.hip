@@ -1,0 +1,376 @@
+// C ABI of libmenkf: context, workspace planner, argument validation and
+// dispatch to the HIP kernels.  See include/menkf.h for the contract of
+// every entry point.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+using namespace menkf;
+
+struct menkf_ctx {
+    Plan plan;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    const int32_t *idx = nullptr;
+    const int32_t *comp = nullptr;
+    char err[512] = {0};
+};
+
+struct menkf_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static thread_local char g_err[512];
+
+static menkf_status fail(menkf_ctx *c, menkf_status st, const char *fmt, ...) {
+    char *buf = c ? c->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+static menkf_status hip_fail(menkf_ctx *c, hipError_t e, const char *where) {
+    return fail(c, MENKF_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+static int roundup(int v, int m) { return (v + m - 1) / m * m; }
+
+static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
+    std::memset(p, 0, sizeof(*p));
+    p->cfg = *cfg;
+    if (cfg->model != MENKF_BURGERS1D && cfg->model != MENKF_NS2D)
+        return fail(nullptr, MENKF_E_ARG, "model must be MENKF_BURGERS1D or MENKF_NS2D (got %d)", cfg->model);
+    if (cfg->precision != MENKF_F32 && cfg->precision != MENKF_F64)
+        return fail(nullptr, MENKF_E_ARG, "precision must be MENKF_F32 or MENKF_F64 (got %d)", cfg->precision);
+    if (cfg->gain_mode != MENKF_GAIN_EXACT_R && cfg->gain_mode != MENKF_GAIN_SAMPLE_EE)
+        return fail(nullptr, MENKF_E_ARG, "unknown gain_mode %d", cfg->gain_mode);
+    p->dim = cfg->model == MENKF_NS2D ? 2 : 1;
+    p->F = p->dim == 2 ? 4 : 1;
+    const int r = cfg->ratio;
+    if (r < 1 || r > 64) return fail(nullptr, MENKF_E_ARG, "ratio must be in [1, 64] (got %d)", r);
+    if (cfg->nx < 1 || cfg->nx % r) return fail(nullptr, MENKF_E_SHAPE, "nx=%d must be a positive multiple of ratio=%d", cfg->nx, r);
+    if (p->dim == 1 && cfg->ny != 1) return fail(nullptr, MENKF_E_SHAPE, "1D model needs ny = 1 (got %d)", cfg->ny);
+    if (p->dim == 2 && (cfg->ny < 1 || cfg->ny % r))
+        return fail(nullptr, MENKF_E_SHAPE, "ny=%d must be a positive multiple of ratio=%d", cfg->ny, r);
+    p->nx = cfg->nx;
+    p->ny = cfg->ny;
+    p->nxc = cfg->nx / r;
+    p->nyc = p->dim == 2 ? cfg->ny / r : 1;
+    if (p->nxc < 4 || (p->dim == 2 && p->nyc < 4))
+        return fail(nullptr, MENKF_E_SHAPE, "coarse grid %dx%d too small (cubic prolongation and the stencils need >= 4 nodes per direction)", p->nxc, p->nyc);
+    if (p->dim == 2 && (long long)cfg->nx * cfg->ny >= (1LL << 31))
+        return fail(nullptr, MENKF_E_SHAPE, "fine grid too large for 32-bit node indices");
+    p->nf = (long long)p->nx * p->ny;
+    p->nc = (long long)p->nxc * p->nyc;
+    if (cfg->n_members < 2 || cfg->n_members > 256)
+        return fail(nullptr, MENKF_E_ARG, "n_members must be in [2, 256] (got %d)", cfg->n_members);
+    if (cfg->n_probes < 1) return fail(nullptr, MENKF_E_ARG, "n_probes must be >= 1 (got %d)", cfg->n_probes);
+    if (!(cfg->dt > 0) || !(cfg->length > 0)) return fail(nullptr, MENKF_E_ARG, "dt and length must be positive");
+    if (p->dim == 1 && !(cfg->nu >= 0)) return fail(nullptr, MENKF_E_ARG, "nu must be >= 0");
+    if (p->dim == 2 && !(cfg->gamma > 1 && cfg->mach > 0 && cfg->reynolds > 0 && cfg->prandtl > 0))
+        return fail(nullptr, MENKF_E_ARG, "need gamma > 1, mach > 0, reynolds > 0, prandtl > 0");
+    if (cfg->gain_mode == MENKF_GAIN_EXACT_R && !(cfg->obs_sigma > 0))
+        return fail(nullptr, MENKF_E_ARG, "obs_sigma must be > 0 with MENKF_GAIN_EXACT_R");
+    if (cfg->gain_mode == MENKF_GAIN_SAMPLE_EE && cfg->n_probes > 2 * cfg->n_members - 2)
+        return fail(nullptr, MENKF_E_ARG,
+                    "MENKF_GAIN_SAMPLE_EE: Y Y^T + E E^T has rank <= 2(N-1) = %d < n_probes = %d (singular)",
+                    2 * cfg->n_members - 2, cfg->n_probes);
+    if (cfg->anomaly_terms != 0 && cfg->anomaly_terms != 1 && cfg->anomaly_terms != 3)
+        return fail(nullptr, MENKF_E_ARG, "anomaly_terms must be 0, 1 or 3 (got %d)", cfg->anomaly_terms);
+    if (cfg->anomaly_terms == 0) p->cfg.anomaly_terms = 3;
+    p->N = cfg->n_members;
+    p->Ny = cfg->n_probes;
+    p->npad = roundup(p->N, 32);
+    p->kdim = roundup(cfg->gain_mode == MENKF_GAIN_SAMPLE_EE ? 2 * p->N : p->N, 64);
+    p->nyp = roundup(p->Ny, CHOL_NB);
+    p->mext = 2 * p->N + 1;
+    p->mextp = roundup(p->mext, CHOL_NB);
+    p->ld = p->nyp + p->mextp;
+    const bool f64 = cfg->precision == MENKF_F64;
+    p->tsize = f64 ? 8 : 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t fine = (size_t)p->nf * p->F * p->tsize;
+    const size_t coarse = (size_t)p->N * p->nc * p->F * p->tsize;
+    p->off_info = take(256);
+    p->off_f1 = take(fine);
+    p->off_f2 = take(fine);
+    p->off_facc = take(fine);
+    p->off_c1 = take(coarse);
+    p->off_c2 = take(coarse);
+    p->off_cacc = take(coarse);
+    p->off_yb = take((size_t)p->nyp * p->kdim * 8);
+    p->off_a = take((size_t)p->ld * p->ld * 8);
+    p->off_linv = take(64 * 64 * 8);
+    p->off_z = take((size_t)(p->N + 1) * p->N * 8);
+    p->off_zt = take((size_t)p->npad * p->npad * (f64 ? 8 : 4));
+    p->off_zstar = take((size_t)p->npad * 8);
+    size_t scratch = (size_t)(p->N + 1) * p->nyp * 8;
+    if (scratch < 4096 * 8) scratch = 4096 * 8;
+    p->off_scratch = take(scratch);
+    p->ws_bytes = o;
+    return MENKF_OK;
+}
+
+extern "C" {
+
+menkf_status menkf_create(const menkf_config *cfg, menkf_ctx **out) {
+    if (!out) return fail(nullptr, MENKF_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, MENKF_E_ARG, "cfg is NULL");
+    menkf_ctx *c = new (std::nothrow) menkf_ctx();
+    if (!c) return fail(nullptr, MENKF_E_ARG, "out of host memory");
+    const menkf_status st = build_plan(cfg, &c->plan);
+    if (st != MENKF_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return MENKF_OK;
+}
+
+void menkf_destroy(menkf_ctx *ctx) { delete ctx; }
+
+const char *menkf_last_error(const menkf_ctx *ctx) { return ctx ? ctx->err : g_err; }
+
+menkf_status menkf_workspace_size(const menkf_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return fail(nullptr, MENKF_E_ARG, "null argument");
+    *bytes = ctx->plan.ws_bytes;
+    return MENKF_OK;
+}
+
+menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws, size_t bytes) {
+    if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
+    if (!ws) return fail(ctx, MENKF_E_ARG, "workspace pointer is NULL");
+    if (((uintptr_t)ws) & 255) return fail(ctx, MENKF_E_ARG, "workspace must be 256-byte aligned");
+    if (bytes < ctx->plan.ws_bytes)
+        return fail(ctx, MENKF_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", bytes,
+                    ctx->plan.ws_bytes);
+    ctx->ws = ws;
+    ctx->ws_bytes = bytes;
+    hipError_t e = launch_set_word((int32_t *)((char *)ws + ctx->plan.off_info), 0, nullptr);
+    if (e == hipSuccess) e = launch_set_word64((uint64_t *)((char *)ws + ctx->plan.off_info + 64), 1, nullptr);
+    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_set_workspace");
+    return MENKF_OK;
+}
+
+menkf_status menkf_set_probes(menkf_ctx *ctx, const int32_t *idx, const int32_t *comp) {
+    if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
+    if (!idx || !comp) return fail(ctx, MENKF_E_ARG, "probe tables must be non-NULL device pointers");
+    // One-time host-side validation (set-up call, synchronous): every probe
+    // must address a fine node and a valid component.
+    const Plan &p = ctx->plan;
+    std::vector<int32_t> hi(p.Ny), hc(p.Ny);
+    hipError_t e = hipMemcpy(hi.data(), idx, sizeof(int32_t) * p.Ny, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(hc.data(), comp, sizeof(int32_t) * p.Ny, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_set_probes");
+    for (int k = 0; k < p.Ny; ++k) {
+        if (hi[k] < 0 || (long long)hi[k] >= p.nf)
+            return fail(ctx, MENKF_E_ARG, "probe %d: node %d outside the fine grid of %lld nodes", k, hi[k], p.nf);
+        if (hc[k] < 0 || hc[k] > (p.dim == 2 ? 1 : 0))
+            return fail(ctx, MENKF_E_ARG, "probe %d: component %d invalid", k, hc[k]);
+    }
+    ctx->idx = idx;
+    ctx->comp = comp;
+    return MENKF_OK;
+}
+
+#define NEED_WS(ctx)                                                                         \
+    do {                                                                                     \
+        if (!(ctx)) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");                        \
+        if (!(ctx)->ws) return fail((ctx), MENKF_E_WORKSPACE, "no workspace attached");      \
+    } while (0)
+
+menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state, int32_t nb, int32_t nsteps, void *prev,
+                            menkf_stream stream) {
+    NEED_WS(ctx);
+    const Plan &p = ctx->plan;
+    if (level != MENKF_FINE && level != MENKF_COARSE) return fail(ctx, MENKF_E_ARG, "bad level %d", level);
+    if (!state) return fail(ctx, MENKF_E_ARG, "state is NULL");
+    if (nsteps < 1) return fail(ctx, MENKF_E_ARG, "nsteps must be >= 1 (got %d)", nsteps);
+    if (level == MENKF_FINE && nb != 1) return fail(ctx, MENKF_E_ARG, "the fine level takes nb = 1 (got %d)", nb);
+    if (level == MENKF_COARSE && (nb < 1 || nb > p.N))
+        return fail(ctx, MENKF_E_ARG, "coarse nb must be in [1, %d] (got %d)", p.N, nb);
+    const hipError_t e = p.dim == 1 ? launch_burgers_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream)
+                                    : launch_ns_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_forecast");
+}
+
+menkf_status menkf_restrict(menkf_ctx *ctx, const void *xf, void *xc, menkf_stream stream) {
+    if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
+    if (!xf || !xc) return fail(ctx, MENKF_E_ARG, "null state pointer");
+    const hipError_t e = launch_restrict(ctx->plan, xf, xc, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_restrict");
+}
+
+menkf_status menkf_gain(menkf_ctx *ctx, const void *members, const void *xstar, const double *yobs, uint64_t seed,
+                        uint64_t cycle, const double *eps, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!members || !xstar || !yobs) return fail(ctx, MENKF_E_ARG, "null input pointer");
+    if (!ctx->idx) return fail(ctx, MENKF_E_ARG, "probes not set (menkf_set_probes)");
+    const hipError_t e = launch_gain(ctx->plan, members, xstar, yobs, seed, cycle, eps, ctx->idx, ctx->comp, ctx->ws,
+                                     (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_gain");
+}
+
+menkf_status menkf_set_cycle(menkf_ctx *ctx, uint64_t cycle, menkf_stream stream) {
+    NEED_WS(ctx);
+    const hipError_t e =
+        launch_set_word64((uint64_t *)((char *)ctx->ws + ctx->plan.off_info + 64), cycle, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_set_cycle");
+}
+
+menkf_status menkf_get_gain(menkf_ctx *ctx, double *z, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!z) return fail(ctx, MENKF_E_ARG, "z is NULL");
+    const hipError_t e = launch_get_gain(ctx->plan, z, ctx->ws, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_get_gain");
+}
+
+menkf_status menkf_update(menkf_ctx *ctx, void *members, void *dc, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!members || !dc) return fail(ctx, MENKF_E_ARG, "null pointer");
+    const hipError_t e = launch_update(ctx->plan, members, dc, ctx->ws, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_update");
+}
+
+menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, const void *xprev, int32_t n_sweeps,
+                                  double alpha, int32_t mode, const menkf_net *net, menkf_stream stream) {
+    NEED_WS(ctx);
+    const Plan &p = ctx->plan;
+    if (!dc || !xf) return fail(ctx, MENKF_E_ARG, "null state pointer");
+    if (n_sweeps < 0 || n_sweeps > 64) return fail(ctx, MENKF_E_ARG, "n_sweeps must be in [0, 64]");
+    if (n_sweeps > 0 && !xprev) return fail(ctx, MENKF_E_ARG, "sweeps need x_{k-1} (xprev)");
+    if (!(alpha > 0 && alpha <= 1)) return fail(ctx, MENKF_E_ARG, "alpha must be in (0, 1]");
+    if (mode != MENKF_PROLONG_PLAIN && mode != MENKF_PROLONG_LEARNED && mode != MENKF_PROLONG_LEARNED_FALLBACK)
+        return fail(ctx, MENKF_E_ARG, "bad prolongation mode %d", mode);
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t *info = (const int32_t *)((char *)ctx->ws + p.off_info);
+    void *W = (char *)ctx->ws + p.off_f1;
+    hipError_t e;
+    const void *src;
+    if (mode == MENKF_PROLONG_PLAIN) {
+        if (n_sweeps % 2 == 1) {
+            e = launch_prolong_add(p, dc, xf, W, info, s);
+            src = W;
+        } else {
+            e = launch_prolong_add(p, dc, xf, xf, info, s);
+            src = xf;
+        }
+    } else {
+        if (p.dim != 2) return fail(ctx, MENKF_E_UNSUPPORTED, "the learned prolongation is defined for the 2D model");
+        if (p.cfg.precision != MENKF_F32) return fail(ctx, MENKF_E_UNSUPPORTED, "the learned prolongation runs in the F32 path");
+        if (!net || !net->w1 || !net->w2 || !net->w3 || !net->b1 || !net->b2 || !net->b3)
+            return fail(ctx, MENKF_E_ARG, "learned prolongation needs a complete menkf_net");
+        void *target = (n_sweeps % 2 == 1) ? W : xf;
+        if (target != xf) {
+            e = launch_copy(p, xf, W, info, s);
+            if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth");
+        }
+        e = launch_net_prolong(p, dc, target, xprev, net, mode == MENKF_PROLONG_LEARNED_FALLBACK, ctx->ws, s);
+        src = target;
+        if (mode == MENKF_PROLONG_LEARNED) n_sweeps = 0;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth");
+    for (int k = 0; k < n_sweeps; ++k) {
+        void *dst = (src == xf) ? W : xf;
+        e = launch_sweep(p, src, xprev, dst, alpha, info, ctx->ws, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth (sweep)");
+        src = dst;
+    }
+    if (src != xf) {
+        e = launch_copy(p, src, xf, info, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth (copy)");
+    }
+    return MENKF_OK;
+}
+
+menkf_status menkf_get_status(menkf_ctx *ctx, int32_t *info, int32_t clear, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!info) return fail(ctx, MENKF_E_ARG, "info is NULL");
+    int32_t *dinfo = (int32_t *)((char *)ctx->ws + ctx->plan.off_info);
+    hipError_t e = hipMemcpyAsync(info, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_get_status");
+    if (clear && *info != 0) {
+        e = launch_set_word(dinfo, 0, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_get_status (clear)");
+    }
+    if (*info != 0)
+        return fail(ctx, MENKF_E_NOT_SPD, "innovation covariance not positive definite at column %d", *info - 1);
+    return MENKF_OK;
+}
+
+menkf_status menkf_observe(menkf_ctx *ctx, int32_t level, const void *state, int32_t nb, double *y,
+                           menkf_stream stream) {
+    if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
+    if (level != MENKF_FINE && level != MENKF_COARSE) return fail(ctx, MENKF_E_ARG, "bad level %d", level);
+    if (!state || !y) return fail(ctx, MENKF_E_ARG, "null pointer");
+    if (nb < 1 || nb > 65535) return fail(ctx, MENKF_E_ARG, "nb must be in [1, 65535]");
+    if (!ctx->idx) return fail(ctx, MENKF_E_ARG, "probes not set (menkf_set_probes)");
+    const hipError_t e = launch_observe(ctx->plan, level, state, nb, y, ctx->idx, ctx->comp, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_observe");
+}
+
+menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa, const void *xt, double *out, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!xa || !xt || !out) return fail(ctx, MENKF_E_ARG, "null pointer");
+    const hipError_t e = launch_diagnostics(ctx->plan, xa, xt, out, ctx->ws, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_diagnostics");
+}
+
+double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members) {
+    if (dim < 1 || ratio < 1 || n_members < 0) return -1.0;
+    return 1.0 + (double)n_members / std::pow((double)ratio, (double)dim);
+}
+
+menkf_status menkf_graph_begin(menkf_stream stream) {
+    if (!stream) return fail(nullptr, MENKF_E_ARG, "graph capture needs a non-default stream");
+    const hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed);
+    return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_graph_begin");
+}
+
+menkf_status menkf_graph_end(menkf_stream stream, menkf_graph **out) {
+    if (!out) return fail(nullptr, MENKF_E_ARG, "out is NULL");
+    *out = nullptr;
+    menkf_graph *g = new (std::nothrow) menkf_graph();
+    if (!g) return fail(nullptr, MENKF_E_ARG, "out of host memory");
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return hip_fail(nullptr, e, "menkf_graph_end");
+    }
+    *out = g;
+    return MENKF_OK;
+}
+
+menkf_status menkf_graph_launch(menkf_graph *g, menkf_stream stream) {
+    if (!g) return fail(nullptr, MENKF_E_ARG, "graph is NULL");
+    const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_graph_launch");
+}
+
+void menkf_graph_destroy(menkf_graph *g) {
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

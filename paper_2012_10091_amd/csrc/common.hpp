@@ -1,0 +1,96 @@
+// Internal declarations shared by the HIP translation units of libmenkf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/menkf.h"
+
+namespace menkf {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+
+// Blocks are dispatched round-robin over the 8 XCDs (block i -> XCD i % 8).
+// Remap so that each XCD receives one contiguous range of logical blocks:
+// neighbouring stencil tiles then share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int i, int total) {
+    const int xcd = i & 7;
+    const int local = i >> 3;
+    const int per = total >> 3;
+    const int rem = total & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+__device__ __forceinline__ __bf16 to_bf16(float v) { return __float2bfloat16(v); }
+
+// Four-point Lagrange basis on nodes -1, 0, 1, 2 evaluated at s in [0, 1).
+template <typename R>
+__host__ __device__ __forceinline__ void lagrange4(R s, R w[4]) {
+    const R sm1 = s - R(1), sm2 = s - R(2), sp1 = s + R(1);
+    w[0] = -s * sm1 * sm2 / R(6);
+    w[1] = sp1 * sm1 * sm2 / R(2);
+    w[2] = -sp1 * s * sm2 / R(2);
+    w[3] = sp1 * s * sm1 / R(6);
+}
+
+// Derived sizes and workspace offsets of one context.
+struct Plan {
+    menkf_config cfg;
+    int dim, F;
+    int nx, ny, nxc, nyc;
+    long long nf, nc;          // points per field, fine / coarse
+    int N, Ny;                 // members, probes
+    int npad;                  // N rounded up to 32 (MFMA tiles)
+    int kdim;                  // K of the S product: N or 2N (sample mode), rounded up to 64
+    int nyp;                   // Ny rounded up to the Cholesky block
+    int mext;                  // extra rows of the augmented factorisation: 2N+1
+    int mextp;                 // rounded up to the block
+    int ld;                    // leading dimension of the augmented matrix
+    size_t tsize;              // sizeof state element
+    // workspace offsets (bytes)
+    size_t off_info, off_f1, off_f2, off_facc, off_c1, off_c2, off_cacc;
+    size_t off_yb, off_a, off_linv, off_z, off_zt, off_zstar, off_scratch;
+    size_t ws_bytes;
+};
+
+constexpr int CHOL_NB = 64;
+
+// Kernel launchers (each returns hipError_t of the launch).
+// forecast
+hipError_t launch_burgers_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
+                                   void *prev, void *ws, hipStream_t s);
+hipError_t launch_ns_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
+                              void *prev, void *ws, hipStream_t s);
+// grids
+hipError_t launch_restrict(const Plan &p, const void *xf, void *xc, hipStream_t s);
+hipError_t launch_prolong_add(const Plan &p, const void *dc, const void *xin, void *xout,
+                              const int32_t *info, hipStream_t s);
+hipError_t launch_sweep(const Plan &p, const void *xin, const void *xprev, void *xout,
+                        double alpha, const int32_t *info, void *ws, hipStream_t s);
+hipError_t launch_copy(const Plan &p, const void *src, void *dst, const int32_t *info, hipStream_t s);
+// analysis
+hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, const double *yobs,
+                       uint64_t seed, uint64_t cycle, const double *eps, const int32_t *idx,
+                       const int32_t *comp, void *ws, hipStream_t s);
+hipError_t launch_get_gain(const Plan &p, double *z, void *ws, hipStream_t s);
+hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipStream_t s);
+hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, double *y,
+                          const int32_t *idx, const int32_t *comp, hipStream_t s);
+hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, double *out, void *ws, hipStream_t s);
+hipError_t launch_set_word(int32_t *w, int32_t v, hipStream_t s);
+hipError_t launch_set_word64(uint64_t *w, uint64_t v, hipStream_t s);
+// learned prolongation
+hipError_t launch_net_prolong(const Plan &p, const void *dc, void *xf, const void *xprev,
+                              const menkf_net *net, int fallback, void *ws, hipStream_t s);
+
+}  // namespace menkf

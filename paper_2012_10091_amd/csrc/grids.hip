@@ -1,0 +1,115 @@
+// Two-grid projections (Sec. 2.2): Pi_C (injection at the coincident nodes
+// of nested vertex-centred periodic grids, which is what a fourth-order
+// Lagrange restriction reduces to there) and Pi_F (four-point cubic
+// Lagrange interpolation per direction, tensor product in 2D), plus the
+// fine-grid correction x' = x^F_f + Pi_F(delta^C) of Algo. 4 step 5.
+#include "common.hpp"
+
+namespace menkf {
+
+hipError_t launch_burgers_sweep(const Plan &p, const void *x, const void *xp, void *out, double alpha,
+                                const int32_t *info, hipStream_t s);
+hipError_t launch_ns_sweep(const Plan &p, const void *x, const void *xp, void *out, double alpha,
+                           const int32_t *info, hipStream_t s);
+
+template <typename T>
+__global__ __launch_bounds__(256) void restrict_inject(const T *__restrict__ xf, T *__restrict__ xc, int nx,
+                                                       int ny, int r, int nxc, int nyc, int F) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nc = (long long)nxc * nyc;
+    if (i >= nc * F) return;
+    const int f = (int)(i / nc);
+    const long long j = i - f * nc;
+    const int jy = (int)(j / nxc), jx = (int)(j - (long long)jy * nxc);
+    xc[i] = xf[(long long)f * nx * ny + (long long)(jy * r) * nx + (long long)jx * r];
+}
+
+// xout = xin + Pi_F(dc) for every field; 1D when nyc == 1 (then ny == 1).
+template <typename T>
+__global__ __launch_bounds__(256) void prolong_add(const T *__restrict__ dc, const T *__restrict__ xin,
+                                                   T *__restrict__ xout, int nx, int ny, int r, int nxc,
+                                                   int nyc, int F, const int32_t *__restrict__ info) {
+    if (*info != 0) return;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nf = (long long)nx * ny;
+    if (i >= nf * F) return;
+    const int f = (int)(i / nf);
+    const long long j = i - f * nf;
+    const int y = (int)(j / nx), x = (int)(j - (long long)y * nx);
+    const T *d = dc + (long long)f * nxc * nyc;
+    const int jx = x / r, mx = x - jx * r;
+    T wx[4];
+    lagrange4<T>(T(mx) / T(r), wx);
+    T acc = T(0);
+    if (nyc == 1 && ny == 1) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc += wx[a] * d[wrap(jx - 1 + a, nxc)];
+    } else {
+        const int jy = y / r, my = y - jy * r;
+        T wy[4];
+        lagrange4<T>(T(my) / T(r), wy);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const T *row = d + (long long)wrap(jy - 1 + a, nyc) * nxc;
+            T sa = T(0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) sa += wx[b] * row[wrap(jx - 1 + b, nxc)];
+            acc += wy[a] * sa;
+        }
+    }
+    xout[i] = xin[i] + acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void copy_guarded(const T *__restrict__ src, T *__restrict__ dst, long long n,
+                                                    const int32_t *__restrict__ info) {
+    if (*info != 0) return;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_restrict(const Plan &p, const void *xf, void *xc, hipStream_t s) {
+    const long long n = p.nc * p.F;
+    const int blocks = (int)((n + 255) / 256);
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(restrict_inject<double>, dim3(blocks), dim3(256), 0, s, (const double *)xf,
+                           (double *)xc, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, p.F);
+    else
+        hipLaunchKernelGGL(restrict_inject<float>, dim3(blocks), dim3(256), 0, s, (const float *)xf,
+                           (float *)xc, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, p.F);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_add(const Plan &p, const void *dc, const void *xin, void *xout, const int32_t *info,
+                              hipStream_t s) {
+    const long long n = p.nf * p.F;
+    const int blocks = (int)((n + 255) / 256);
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(prolong_add<double>, dim3(blocks), dim3(256), 0, s, (const double *)dc,
+                           (const double *)xin, (double *)xout, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, p.F, info);
+    else
+        hipLaunchKernelGGL(prolong_add<float>, dim3(blocks), dim3(256), 0, s, (const float *)dc,
+                           (const float *)xin, (float *)xout, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, p.F, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const Plan &p, const void *src, void *dst, const int32_t *info, hipStream_t s) {
+    const long long n = p.nf * p.F;
+    const int blocks = (int)((n + 255) / 256);
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(copy_guarded<double>, dim3(blocks), dim3(256), 0, s, (const double *)src,
+                           (double *)dst, n, info);
+    else
+        hipLaunchKernelGGL(copy_guarded<float>, dim3(blocks), dim3(256), 0, s, (const float *)src, (float *)dst,
+                           n, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const Plan &p, const void *xin, const void *xprev, void *xout, double alpha,
+                        const int32_t *info, void *ws, hipStream_t s) {
+    (void)ws;
+    if (p.dim == 1) return launch_burgers_sweep(p, xin, xprev, xout, alpha, info, s);
+    return launch_ns_sweep(p, xin, xprev, xout, alpha, info, s);
+}
+
+}  // namespace menkf

@@ -1,0 +1,281 @@
+// 2D compressible Navier-Stokes forecast (Sec. 6, mass / momentum / energy
+// equations) in conservative variables q = (rho, rho u, rho v, E) on a
+// periodic box, fourth-order centred differences, classical RK4.
+//
+// Spatial operator F(q) (non-dimensional, rho0 = U0 = T0 = 1):
+//   p = (gamma-1)(E - (m u + n v)/2), T = gamma Ma^2 p / rho, mu = 1/Re,
+//   kappa = mu c_p / Pr, c_p = 1/((gamma-1) Ma^2), Stokes stress.
+//   F_rho = -(D1x m + D1y n)
+//   F_m   = -(D1x(m u + p) + D1y(m v)) + mu (4/3 D2x u + D2y u + 1/3 D1y(D1x v))
+//   F_n   = -(D1x(n u) + D1y(n v + p)) + mu (D2x v + 4/3 D2y v + 1/3 D1x(D1y u))
+//   F_E   = -(D1x((E+p)u) + D1y((E+p)v)) + D1x(txx u + txy v) + D1y(txy u + tyy v)
+//           + kappa (D2x T + D2y T)
+//   D1 f = (f[-2] - 8 f[-1] + 8 f[1] - f[2]) / 12h,
+//   D2 f = (-f[-2] + 16 f[-1] - 30 f[0] + 16 f[1] - f[2]) / 12h^2,
+//   txx = mu(4/3 u_x - 2/3 v_y), tyy = mu(4/3 v_y - 2/3 u_x), txy = mu(u_y + v_x).
+//
+// Kernel structure (one launch per RK stage, all members of a level in one
+// grid): a workgroup owns a TX x TY tile of one member and stages, in LDS,
+//   phase 1: u, v on the tile + halo 4; m, n, E+p, p, T on the tile + halo 2
+//   phase 2: u_y, v_x and the viscous work fluxes (tau.u) on the tile + halo 2
+//   phase 3: F(q) at the tile points, then the stage epilogue
+// The epilogue fuses the Runge-Kutta combination so that each stage reads
+// and writes every field once:
+//   stage 1: acc = q + dt/6 k1,      s1 = q + dt/2 k1      (+ x_{k-1} copy)
+//   stage 2: acc += dt/3 k2,         s2 = q + dt/2 k2
+//   stage 3: acc += dt/3 k3,         s1 = q + dt k3
+//   stage 4: q = acc + dt/6 k4
+//   sweep  : x' = x + (alpha/D)(x_prev + dt F(x) - x)     (relaxed Jacobi)
+#include "common.hpp"
+
+namespace menkf {
+
+template <typename T>
+struct NSCoef {
+    T i12hx, i12hy, i12hx2, i12hy2;
+    T gm1, tfac, mu, kappa;
+    T dt, w;  // w = alpha / D for the sweep
+};
+
+enum { ST1 = 1, ST2 = 2, ST3 = 3, ST4 = 4, SWEEP = 5 };
+
+template <typename T, int TX, int TY, int MODE>
+__global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, const T *__restrict__ q0,
+                                                T *__restrict__ acc, T *__restrict__ snext,
+                                                T *__restrict__ qout, T *__restrict__ prev, int nx, int ny,
+                                                int tiles_x, int tiles_per_member, int total_blocks,
+                                                NSCoef<T> c, const int32_t *__restrict__ info) {
+    constexpr int BX = TX + 8, BY = TY + 8;   // box with halo 4
+    constexpr int CX = TX + 4, CY = TY + 4;   // inner box with halo 2
+    constexpr int NB = BX * BY, NC = CX * CY;
+    __shared__ T su[NB], sv[NB];
+    __shared__ T sm[NC], sn[NC], sEp[NC], sp[NC], sT[NC], sqx[NC], sqy[NC], suy[NC], svx[NC];
+
+    if (MODE == SWEEP && *info != 0) return;
+
+    const int lb = xcd_remap(blockIdx.x, total_blocks);
+    const int member = lb / tiles_per_member;
+    const int t = lb - member * tiles_per_member;
+    const int ty0 = (t / tiles_x) * TY;
+    const int tx0 = (t % tiles_x) * TX;
+    const long long nxy = (long long)nx * ny;
+    const long long mbase = (long long)member * 4 * nxy;
+    const T *q_rho = sin_ + mbase;
+    const T *q_m = q_rho + nxy;
+    const T *q_n = q_m + nxy;
+    const T *q_E = q_n + nxy;
+
+    // phase 1
+    for (int i = threadIdx.x; i < NB; i += 256) {
+        const int by = i / BX, bx = i - by * BX;
+        const int gx = wrap(tx0 - 4 + bx, nx), gy = wrap(ty0 - 4 + by, ny);
+        const long long g = (long long)gy * nx + gx;
+        const T rho = q_rho[g], m = q_m[g], n = q_n[g];
+        const T ir = T(1) / rho;
+        const T u = m * ir, v = n * ir;
+        su[i] = u;
+        sv[i] = v;
+        if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) {
+            const T E = q_E[g];
+            const T p = c.gm1 * (E - T(0.5) * (m * u + n * v));
+            const int ci = (by - 2) * CX + (bx - 2);
+            sm[ci] = m;
+            sn[ci] = n;
+            sEp[ci] = E + p;
+            sp[ci] = p;
+            sT[ci] = c.tfac * p * ir;
+        }
+    }
+    __syncthreads();
+
+    // phase 2
+    for (int i = threadIdx.x; i < NC; i += 256) {
+        const int cy = i / CX, cx = i - cy * CX;
+        const int b = (cy + 2) * BX + (cx + 2);
+        const T ux = (su[b - 2] - T(8) * su[b - 1] + T(8) * su[b + 1] - su[b + 2]) * c.i12hx;
+        const T vx = (sv[b - 2] - T(8) * sv[b - 1] + T(8) * sv[b + 1] - sv[b + 2]) * c.i12hx;
+        const T uy = (su[b - 2 * BX] - T(8) * su[b - BX] + T(8) * su[b + BX] - su[b + 2 * BX]) * c.i12hy;
+        const T vy = (sv[b - 2 * BX] - T(8) * sv[b - BX] + T(8) * sv[b + BX] - sv[b + 2 * BX]) * c.i12hy;
+        const T div = ux + vy;
+        const T txx = c.mu * (T(2) * ux - T(2.0 / 3.0) * div);
+        const T tyy = c.mu * (T(2) * vy - T(2.0 / 3.0) * div);
+        const T txy = c.mu * (uy + vx);
+        const T u = su[b], v = sv[b];
+        sqx[i] = txx * u + txy * v;
+        sqy[i] = txy * u + tyy * v;
+        suy[i] = uy;
+        svx[i] = vx;
+    }
+    __syncthreads();
+
+    // phase 3
+    for (int i = threadIdx.x; i < TX * TY; i += 256) {
+        const int ty = i / TX, tx = i - ty * TX;
+        const int gx = tx0 + tx, gy = ty0 + ty;
+        if (gx >= nx || gy >= ny) continue;
+        const int ci = (ty + 2) * CX + (tx + 2);
+        const int b = (ty + 4) * BX + (tx + 4);
+#define D1X(A) ((A[ci - 2] - T(8) * A[ci - 1] + T(8) * A[ci + 1] - A[ci + 2]) * c.i12hx)
+#define D1Y(A) ((A[ci - 2 * CX] - T(8) * A[ci - CX] + T(8) * A[ci + CX] - A[ci + 2 * CX]) * c.i12hy)
+#define D2XB(A) ((-A[b - 2] + T(16) * A[b - 1] - T(30) * A[b] + T(16) * A[b + 1] - A[b + 2]) * c.i12hx2)
+#define D2YB(A) \
+    ((-A[b - 2 * BX] + T(16) * A[b - BX] - T(30) * A[b] + T(16) * A[b + BX] - A[b + 2 * BX]) * c.i12hy2)
+#define D2XC(A) ((-A[ci - 2] + T(16) * A[ci - 1] - T(30) * A[ci] + T(16) * A[ci + 1] - A[ci + 2]) * c.i12hx2)
+#define D2YC(A) \
+    ((-A[ci - 2 * CX] + T(16) * A[ci - CX] - T(30) * A[ci] + T(16) * A[ci + CX] - A[ci + 2 * CX]) * c.i12hy2)
+        // fluxes at the x-neighbours (offset k) and y-neighbours
+        T fxm[4], fxn[4], fxE[4], fym[4], fyn[4], fyE[4];
+        const int offs[4] = {-2, -1, 1, 2};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int o = offs[k];
+            const int cx_ = ci + o, bx_ = b + o;
+            const T ux_ = su[bx_];
+            fxm[k] = sm[cx_] * ux_ + sp[cx_];
+            fxn[k] = sn[cx_] * ux_;
+            fxE[k] = sEp[cx_] * ux_;
+            const int cy_ = ci + o * CX, by_ = b + o * BX;
+            const T vy_ = sv[by_];
+            fym[k] = sm[cy_] * vy_;
+            fyn[k] = sn[cy_] * vy_ + sp[cy_];
+            fyE[k] = sEp[cy_] * vy_;
+        }
+#define DF(F, h) ((F[0] - T(8) * F[1] + T(8) * F[2] - F[3]) * h)
+        const T k_rho = -(D1X(sm) + D1Y(sn));
+        const T k_m = -(DF(fxm, c.i12hx) + DF(fym, c.i12hy)) +
+                      c.mu * (T(4.0 / 3.0) * D2XB(su) + D2YB(su) + T(1.0 / 3.0) * D1Y(svx));
+        const T k_n = -(DF(fxn, c.i12hx) + DF(fyn, c.i12hy)) +
+                      c.mu * (D2XB(sv) + T(4.0 / 3.0) * D2YB(sv) + T(1.0 / 3.0) * D1X(suy));
+        const T k_E = -(DF(fxE, c.i12hx) + DF(fyE, c.i12hy)) + D1X(sqx) + D1Y(sqy) +
+                      c.kappa * (D2XC(sT) + D2YC(sT));
+#undef DF
+#undef D1X
+#undef D1Y
+#undef D2XB
+#undef D2YB
+#undef D2XC
+#undef D2YC
+        const T kk[4] = {k_rho, k_m, k_n, k_E};
+        const long long g = mbase + (long long)gy * nx + gx;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const long long gf = g + f * nxy;
+            if (MODE == ST1) {
+                const T q = sin_[gf];
+                acc[gf] = q + c.dt * T(1.0 / 6.0) * kk[f];
+                snext[gf] = q + c.dt * T(0.5) * kk[f];
+                if (prev) prev[gf] = q;
+            } else if (MODE == ST2) {
+                acc[gf] = acc[gf] + c.dt * T(1.0 / 3.0) * kk[f];
+                snext[gf] = q0[gf] + c.dt * T(0.5) * kk[f];
+            } else if (MODE == ST3) {
+                acc[gf] = acc[gf] + c.dt * T(1.0 / 3.0) * kk[f];
+                snext[gf] = q0[gf] + c.dt * kk[f];
+            } else if (MODE == ST4) {
+                qout[gf] = acc[gf] + c.dt * T(1.0 / 6.0) * kk[f];
+            } else {
+                const T x = sin_[gf];
+                qout[gf] = x + c.w * (q0[gf] + c.dt * kk[f] - x);
+            }
+        }
+    }
+}
+
+template <typename T>
+static NSCoef<T> ns_coef(const Plan &p, int level, double alpha) {
+    const int nx = level == MENKF_FINE ? p.nx : p.nxc;
+    const int ny = level == MENKF_FINE ? p.ny : p.nyc;
+    const double hx = p.cfg.length / nx, hy = p.cfg.length / ny;
+    const double g = p.cfg.gamma, ma = p.cfg.mach;
+    const double mu = 1.0 / p.cfg.reynolds;
+    const double cp = 1.0 / ((g - 1.0) * ma * ma);
+    NSCoef<T> c;
+    c.i12hx = (T)(1.0 / (12.0 * hx));
+    c.i12hy = (T)(1.0 / (12.0 * hy));
+    c.i12hx2 = (T)(1.0 / (12.0 * hx * hx));
+    c.i12hy2 = (T)(1.0 / (12.0 * hy * hy));
+    c.gm1 = (T)(g - 1.0);
+    c.tfac = (T)(g * ma * ma);
+    c.mu = (T)mu;
+    c.kappa = (T)(mu * cp / p.cfg.prandtl);
+    c.dt = (T)p.cfg.dt;
+    const double D = 1.0 + p.cfg.dt * mu * (30.0 / 12.0) * (1.0 / (hx * hx) + 1.0 / (hy * hy));
+    c.w = (T)(alpha / D);
+    return c;
+}
+
+template <typename T, int TX, int TY>
+struct NSLauncher {
+    template <int MODE>
+    static hipError_t stage(const T *s, const T *q0, T *acc, T *snext, T *qout, T *prev, int nx, int ny, int nb,
+                            const NSCoef<T> &c, const int32_t *info, hipStream_t st) {
+        const int tiles_x = (nx + TX - 1) / TX, tiles_y = (ny + TY - 1) / TY;
+        const int tpm = tiles_x * tiles_y;
+        const int total = tpm * nb;
+        hipLaunchKernelGGL((ns_stage<T, TX, TY, MODE>), dim3(total), dim3(256), 0, st, s, q0, acc, snext, qout,
+                           prev, nx, ny, tiles_x, tpm, total, c, info);
+        return hipGetLastError();
+    }
+    static hipError_t forecast(T *state, T *s1, T *s2, T *acc, T *prev, int nx, int ny, int nb, int nsteps,
+                               const NSCoef<T> &c, hipStream_t st) {
+        hipError_t e = hipSuccess;
+        for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
+            T *pv = (prev && step == nsteps - 1) ? prev : nullptr;
+            e = stage<ST1>(state, nullptr, acc, s1, nullptr, pv, nx, ny, nb, c, nullptr, st);
+            if (e == hipSuccess) e = stage<ST2>(s1, state, acc, s2, nullptr, nullptr, nx, ny, nb, c, nullptr, st);
+            if (e == hipSuccess) e = stage<ST3>(s2, state, acc, s1, nullptr, nullptr, nx, ny, nb, c, nullptr, st);
+            if (e == hipSuccess) e = stage<ST4>(s1, nullptr, acc, nullptr, state, nullptr, nx, ny, nb, c, nullptr, st);
+        }
+        return e;
+    }
+};
+
+// Tile shape per precision: 32 x 16 (FP32, ~34 KB LDS) and 32 x 8 (FP64, ~41 KB LDS).
+template <typename T>
+struct NSTile;
+template <>
+struct NSTile<float> {
+    static constexpr int TX = 32, TY = 16;
+};
+template <>
+struct NSTile<double> {
+    static constexpr int TX = 32, TY = 8;
+};
+
+template <typename T>
+static hipError_t ns_forecast_t(const Plan &p, int level, T *state, int nb, int nsteps, T *prev, void *ws,
+                                hipStream_t s) {
+    char *w = (char *)ws;
+    const bool fine = level == MENKF_FINE;
+    T *s1 = (T *)(w + (fine ? p.off_f1 : p.off_c1));
+    T *s2 = (T *)(w + (fine ? p.off_f2 : p.off_c2));
+    T *acc = (T *)(w + (fine ? p.off_facc : p.off_cacc));
+    const int nx = fine ? p.nx : p.nxc, ny = fine ? p.ny : p.nyc;
+    const NSCoef<T> c = ns_coef<T>(p, level, 0.0);
+    using L = NSLauncher<T, NSTile<T>::TX, NSTile<T>::TY>;
+    return L::forecast(state, s1, s2, acc, prev, nx, ny, nb, nsteps, c, s);
+}
+
+hipError_t launch_ns_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev, void *ws,
+                              hipStream_t s) {
+    if (p.cfg.precision == MENKF_F64)
+        return ns_forecast_t<double>(p, level, (double *)state, nb, nsteps, (double *)prev, ws, s);
+    return ns_forecast_t<float>(p, level, (float *)state, nb, nsteps, (float *)prev, ws, s);
+}
+
+template <typename T>
+static hipError_t ns_sweep_t(const Plan &p, const T *x, const T *xp, T *out, double alpha, const int32_t *info,
+                             hipStream_t s) {
+    const NSCoef<T> c = ns_coef<T>(p, MENKF_FINE, alpha);
+    using L = NSLauncher<T, NSTile<T>::TX, NSTile<T>::TY>;
+    return L::template stage<SWEEP>(x, xp, nullptr, nullptr, out, nullptr, p.nx, p.ny, 1, c, info, s);
+}
+
+hipError_t launch_ns_sweep(const Plan &p, const void *x, const void *xp, void *out, double alpha,
+                           const int32_t *info, hipStream_t s) {
+    if (p.cfg.precision == MENKF_F64)
+        return ns_sweep_t<double>(p, (const double *)x, (const double *)xp, (double *)out, alpha, info, s);
+    return ns_sweep_t<float>(p, (const float *)x, (const float *)xp, (float *)out, alpha, info, s);
+}
+
+}  // namespace menkf
