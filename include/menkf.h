@@ -187,26 +187,69 @@ menkf_status menkf_update(menkf_ctx *ctx, void *members_dev, void *deltac_dev, m
  *   D the viscous diagonal (one sweep with alpha = 0.5 in the paper's
  *   implementation notes).
  *   MENKF_PROLONG_LEARNED: x' = x^F_f + Pi_F(delta^C) + NN(Pi_F(delta^C), x^F_f)
- *   with the network described by net (menkf_net, 2D only), no sweeps.
- *   MENKF_PROLONG_LEARNED_FALLBACK: as LEARNED, but every pixel block whose
- *   network output is non-finite or exceeds guard * |Pi_F(delta^C)|
- *   falls back to the plain correction, then n_sweeps sweeps.
- * A no-op on the device if the status word is set. */
+ *   with the network net (2D, MENKF_F32 contexts), no sweeps.
+ *   MENKF_PROLONG_LEARNED_FALLBACK: as LEARNED, but every 16x16 pixel tile
+ *   whose network output is non-finite or whose norm exceeds
+ *   guard * |Pi_F(delta^C)| on that tile uses the plain Pi_F(delta^C)
+ *   instead (counted in net->fallback_count_dev if given); then n_sweeps
+ *   sweeps.
+ * A no-op on the device if the status word is set.
+ *
+ * The network (not part of the paper; its closing section names better
+ * coarse-to-fine projectors as future work): conv3x3(8->32), ReLU,
+ * conv3x3(32->32), ReLU, conv3x3(32->4), circular padding, cross-
+ * correlation.  Input channels: Pi_F(delta^C) and x^F_f, each field mapped
+ * to (v - in_offset) * in_scale; the fine correction is
+ * Pi_F(delta^C) + out / out_scale.  BF16 weights and activations, FP32
+ * accumulation on MFMA. */
+#define MENKF_NET_NPARAM 12740   /* FP32 parameter vector, see menkf_net_pack */
+#define MENKF_NET_NPACKED 20736  /* BF16 elements of the packed kernel weights */
 typedef struct {
-    const void *w1;  /* bf16 [32][8][3][3]  */
-    const float *b1; /* [32] */
-    const void *w2;  /* bf16 [32][32][3][3] */
-    const float *b2; /* [32] */
-    const void *w3;  /* bf16 [4][32][3][3]  */
-    const float *b3; /* [4] */
+    const void *wpacked;   /* BF16 kernel-layout weights written by menkf_net_pack */
+    const float *params;   /* FP32 parameter vector (the biases are read from it) */
     float in_scale[8], in_offset[8], out_scale[4];
-    float guard;     /* fallback amplitude guard (LEARNED_FALLBACK) */
-    int32_t *fallback_count_dev; /* optional: incremented per fallback block */
+    float guard;           /* fallback amplitude guard (LEARNED_FALLBACK) */
+    int32_t *fallback_count_dev; /* optional: incremented per fallback tile */
 } menkf_net;
 
 menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *deltac_dev, void *xf_dev,
                                   const void *xprev_dev, int32_t n_sweeps, double alpha,
                                   int32_t mode, const menkf_net *net, menkf_stream stream);
+
+/* Pack the FP32 parameter vector (params_dev, MENKF_NET_NPARAM floats laid
+ * out as w1[32][8][3][3], b1[32], w2[32][32][3][3], b2[32], w3[4][32][3][3],
+ * b3[4], the PyTorch convolution order) into the BF16 kernel layout
+ * (MENKF_NET_NPACKED elements: w1 as [32][3][3][8], w2 as [32][3][3][32],
+ * w3 as [32][3][3][32] with output rows 4..31 zero). */
+menkf_status menkf_net_pack(const float *params_dev, void *wpacked_dev, menkf_stream stream);
+
+/* One training step of the network on a batch of periodic crops (Adam,
+ * Kingma & Ba 2015; mean-squared error of the scaled residual
+ * (correction - Pi_F(delta^C)) * out_scale).  Inputs are npairs full
+ * periodic fine fields [npairs][4][H][W] (FP32): dproj = Pi_F(delta^C),
+ * xf = x^F_f, target = the fine correction to learn.  crops_dev holds
+ * batch (pair, y0, x0) triples; each crop is crop x crop output pixels,
+ * evaluated with the periodic halo of the full field.  BF16 activations and
+ * weights, FP32 arithmetic and master weights.  apply_adam = 0 computes the
+ * loss and the gradient (grad, same layout as params) only.  step is the
+ * 1-based Adam step.  loss_dev receives the batch loss (double). */
+typedef struct {
+    float *params, *grad, *adam_m, *adam_v;  /* MENKF_NET_NPARAM each, device */
+    void *wpacked;                           /* refreshed after the update */
+    const float *dproj, *xf, *target;        /* [npairs][4][H][W], device */
+    int32_t npairs, H, W;
+    const int32_t *crops_dev;                /* [batch][3] */
+    int32_t batch, crop;
+    float in_scale[8], in_offset[8], out_scale[4];
+    float lr, beta1, beta2, eps;
+    int32_t step, apply_adam;
+    double *loss_dev;
+    void *workspace_dev;                     /* menkf_net_train_workspace_size bytes */
+    size_t workspace_bytes;
+} menkf_net_train;
+
+menkf_status menkf_net_train_workspace_size(int32_t batch, int32_t crop, size_t *bytes);
+menkf_status menkf_net_train_step(const menkf_net_train *t, menkf_stream stream);
 
 /* Synchronise the stream and read the device status word into *info
  * (0 = fine, j+1 = first non-positive pivot at column j).  Returns

@@ -34,14 +34,34 @@ class MenkfConfig(ctypes.Structure):
 
 class MenkfNet(ctypes.Structure):
     _fields_ = [
-        ("w1", c_void_p), ("b1", c_void_p),
-        ("w2", c_void_p), ("b2", c_void_p),
-        ("w3", c_void_p), ("b3", c_void_p),
+        ("wpacked", c_void_p), ("params", c_void_p),
         ("in_scale", ctypes.c_float * 8), ("in_offset", ctypes.c_float * 8),
         ("out_scale", ctypes.c_float * 4),
         ("guard", ctypes.c_float),
         ("fallback_count_dev", c_void_p),
     ]
+
+
+class MenkfNetTrain(ctypes.Structure):
+    _fields_ = [
+        ("params", c_void_p), ("grad", c_void_p), ("adam_m", c_void_p), ("adam_v", c_void_p),
+        ("wpacked", c_void_p),
+        ("dproj", c_void_p), ("xf", c_void_p), ("target", c_void_p),
+        ("npairs", c_int32), ("H", c_int32), ("W", c_int32),
+        ("crops_dev", c_void_p),
+        ("batch", c_int32), ("crop", c_int32),
+        ("in_scale", ctypes.c_float * 8), ("in_offset", ctypes.c_float * 8),
+        ("out_scale", ctypes.c_float * 4),
+        ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+        ("step", c_int32), ("apply_adam", c_int32),
+        ("loss_dev", c_void_p),
+        ("workspace_dev", c_void_p),
+        ("workspace_bytes", c_size_t),
+    ]
+
+
+NET_NPARAM = 12740
+NET_NPACKED = 20736
 
 
 # name -> (restype, argtypes)
@@ -61,6 +81,9 @@ SIGNATURES = {
     "menkf_prolong_smooth": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
                                        ctypes.POINTER(MenkfNet), c_void_p]),
     "menkf_get_status": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_int32, c_void_p]),
+    "menkf_net_pack": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "menkf_net_train_workspace_size": (c_int32, [c_int32, c_int32, ctypes.POINTER(c_size_t)]),
+    "menkf_net_train_step": (c_int32, [ctypes.POINTER(MenkfNetTrain), c_void_p]),
     "menkf_observe": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
     "menkf_diagnostics": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_ram_ratio": (c_double, [c_int32, c_int32, c_int32]),

@@ -264,3 +264,111 @@ class Graph:
                 self.handle = None
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ learned prolongation
+P_OFFSETS = {"w1": (0, (32, 8, 3, 3)), "b1": (2304, (32,)), "w2": (2336, (32, 32, 3, 3)),
+             "b2": (11552, (32,)), "w3": (11584, (4, 32, 3, 3)), "b3": (12736, (4,))}
+
+
+def pack_params(tensors) -> "torch.Tensor":
+    """Flat FP32 parameter vector from (w1, b1, w2, b2, w3, b3) in PyTorch conv order."""
+    flat = torch.cat([torch.as_tensor(t, dtype=torch.float32).reshape(-1) for t in tensors])
+    if flat.numel() != _lib.NET_NPARAM:
+        raise ValueError(f"expected {_lib.NET_NPARAM} parameters, got {flat.numel()}")
+    return flat
+
+
+def unpack_params(flat):
+    flat = torch.as_tensor(flat).reshape(-1)
+    return [flat[o:o + int(torch.tensor(sh).prod())].reshape(sh) for o, sh in P_OFFSETS.values()]
+
+
+class Net:
+    """Device parameters of the learned prolongation (menkf_net / menkf_net_pack)."""
+
+    def __init__(self, params, in_scale, in_offset, out_scale, guard=10.0, device="cuda"):
+        self.lib = _lib.load()
+        self.params = torch.as_tensor(params, dtype=torch.float32).reshape(-1).to(device).contiguous()
+        if self.params.numel() != _lib.NET_NPARAM:
+            raise ValueError("bad parameter count")
+        self.wpacked = torch.empty(_lib.NET_NPACKED, dtype=torch.bfloat16, device=device)
+        self.in_scale = [float(v) for v in in_scale]
+        self.in_offset = [float(v) for v in in_offset]
+        self.out_scale = [float(v) for v in out_scale]
+        self.guard = float(guard)
+        self.fallback_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.repack()
+
+    def repack(self, stream=None):
+        st = self.lib.menkf_net_pack(_ptr(self.params), _ptr(self.wpacked), _stream(stream))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+
+    def c_struct(self) -> _lib.MenkfNet:
+        n = _lib.MenkfNet()
+        n.wpacked = self.wpacked.data_ptr()
+        n.params = self.params.data_ptr()
+        for i in range(8):
+            n.in_scale[i] = self.in_scale[i]
+            n.in_offset[i] = self.in_offset[i]
+        for i in range(4):
+            n.out_scale[i] = self.out_scale[i]
+        n.guard = self.guard
+        n.fallback_count_dev = self.fallback_count.data_ptr()
+        self._c = n
+        return n
+
+
+class Trainer:
+    """Adam training of a Net on periodic crops (menkf_net_train_step)."""
+
+    def __init__(self, net: Net, batch: int, crop: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.lib = _lib.load()
+        self.net = net
+        dev = net.params.device
+        self.grad = torch.zeros_like(net.params)
+        self.m = torch.zeros_like(net.params)
+        self.v = torch.zeros_like(net.params)
+        self.batch, self.crop = batch, crop
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.step_count = 0
+        n = ctypes.c_size_t()
+        st = self.lib.menkf_net_train_workspace_size(batch, crop, ctypes.byref(n))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def step(self, dproj, xf, target, crops, apply_adam=True, stream=None):
+        """dproj, xf, target: (npairs, 4, H, W) float32 CUDA; crops: (batch, 3) int32 CUDA."""
+        for t in (dproj, xf, target):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 4:
+                raise ValueError("fields must be contiguous float32 CUDA (npairs, 4, H, W)")
+        if crops.dtype != torch.int32 or tuple(crops.shape) != (self.batch, 3) or not crops.is_cuda:
+            raise ValueError("crops must be int32 CUDA (batch, 3)")
+        if apply_adam:
+            self.step_count += 1
+        d = _lib.MenkfNetTrain()
+        d.params, d.grad = self.net.params.data_ptr(), self.grad.data_ptr()
+        d.adam_m, d.adam_v = self.m.data_ptr(), self.v.data_ptr()
+        d.wpacked = self.net.wpacked.data_ptr()
+        d.dproj, d.xf, d.target = dproj.data_ptr(), xf.data_ptr(), target.data_ptr()
+        d.npairs, d.H, d.W = dproj.shape[0], dproj.shape[2], dproj.shape[3]
+        d.crops_dev = crops.data_ptr()
+        d.batch, d.crop = self.batch, self.crop
+        for i in range(8):
+            d.in_scale[i] = self.net.in_scale[i]
+            d.in_offset[i] = self.net.in_offset[i]
+        for i in range(4):
+            d.out_scale[i] = self.net.out_scale[i]
+        d.lr, d.beta1, d.beta2, d.eps = self.lr, self.beta1, self.beta2, self.eps
+        d.step, d.apply_adam = max(self.step_count, 1), int(apply_adam)
+        d.loss_dev = self.loss.data_ptr()
+        d.workspace_dev = self.workspace.data_ptr()
+        d.workspace_bytes = self.workspace.numel()
+        st = self.lib.menkf_net_train_step(ctypes.byref(d), _stream(stream))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+        return self.loss
+

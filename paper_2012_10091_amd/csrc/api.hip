@@ -274,15 +274,15 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
     } else {
         if (p.dim != 2) return fail(ctx, MENKF_E_UNSUPPORTED, "the learned prolongation is defined for the 2D model");
         if (p.cfg.precision != MENKF_F32) return fail(ctx, MENKF_E_UNSUPPORTED, "the learned prolongation runs in the F32 path");
-        if (!net || !net->w1 || !net->w2 || !net->w3 || !net->b1 || !net->b2 || !net->b3)
-            return fail(ctx, MENKF_E_ARG, "learned prolongation needs a complete menkf_net");
-        void *target = (n_sweeps % 2 == 1) ? W : xf;
-        if (target != xf) {
-            e = launch_copy(p, xf, W, info, s);
-            if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth");
-        }
-        e = launch_net_prolong(p, dc, target, xprev, net, mode == MENKF_PROLONG_LEARNED_FALLBACK, ctx->ws, s);
-        src = target;
+        if (!net || !net->wpacked || !net->params)
+            return fail(ctx, MENKF_E_ARG, "learned prolongation needs a menkf_net with packed weights and parameters");
+        for (int i = 0; i < 4; ++i)
+            if (!(net->out_scale[i] != 0.0f)) return fail(ctx, MENKF_E_ARG, "net out_scale must be non-zero");
+        if (mode == MENKF_PROLONG_LEARNED_FALLBACK && !(net->guard > 0.0f))
+            return fail(ctx, MENKF_E_ARG, "LEARNED_FALLBACK needs guard > 0");
+        // the network reads x^F_f with a halo: write the result to the workspace copy
+        e = launch_net_prolong(p, dc, xf, W, net, mode == MENKF_PROLONG_LEARNED_FALLBACK, ctx->ws, s);
+        src = W;
         if (mode == MENKF_PROLONG_LEARNED) n_sweeps = 0;
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth");
@@ -297,6 +297,37 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth (copy)");
     }
     return MENKF_OK;
+}
+
+menkf_status menkf_net_pack(const float *params, void *wpacked, menkf_stream stream) {
+    if (!params || !wpacked) return fail(nullptr, MENKF_E_ARG, "null pointer");
+    const hipError_t e = launch_net_pack(params, wpacked, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_net_pack");
+}
+
+menkf_status menkf_net_train_workspace_size(int32_t batch, int32_t crop, size_t *bytes) {
+    if (!bytes || batch < 1 || batch > 1024 || crop < 1 || crop > 4096)
+        return fail(nullptr, MENKF_E_ARG, "need 1 <= batch <= 1024, 1 <= crop <= 4096");
+    *bytes = net_train_workspace(batch, crop);
+    return MENKF_OK;
+}
+
+menkf_status menkf_net_train_step(const menkf_net_train *t, menkf_stream stream) {
+    if (!t) return fail(nullptr, MENKF_E_ARG, "null train descriptor");
+    if (!t->params || !t->grad || !t->dproj || !t->xf || !t->target || !t->crops_dev || !t->loss_dev ||
+        !t->workspace_dev)
+        return fail(nullptr, MENKF_E_ARG, "null pointer in the train descriptor");
+    if (t->apply_adam && (!t->adam_m || !t->adam_v || t->step < 1))
+        return fail(nullptr, MENKF_E_ARG, "Adam needs moment buffers and step >= 1");
+    if (t->npairs < 1 || t->H < 8 || t->W < 8 || t->batch < 1 || t->crop < 1)
+        return fail(nullptr, MENKF_E_ARG, "bad sizes in the train descriptor");
+    size_t need = 0;
+    menkf_status st = menkf_net_train_workspace_size(t->batch, t->crop, &need);
+    if (st != MENKF_OK) return st;
+    if (t->workspace_bytes < need)
+        return fail(nullptr, MENKF_E_WORKSPACE, "train workspace of %zu bytes < %zu required", t->workspace_bytes, need);
+    const hipError_t e = launch_net_train_step(t, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_net_train_step");
 }
 
 menkf_status menkf_get_status(menkf_ctx *ctx, int32_t *info, int32_t clear, menkf_stream stream) {

@@ -43,6 +43,34 @@ __host__ __device__ __forceinline__ void lagrange4(R s, R w[4]) {
     w[3] = sp1 * s * sm1 / R(6);
 }
 
+// (Pi_F d)(y, x): cubic Lagrange interpolation of a periodic coarse field
+// (nyc x nxc, nyc = 1 in 1D) at fine node (y, x), tensor product in 2D.
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T *__restrict__ d, int nxc, int nyc, int r, int y, int x) {
+    const int jx = x / r, mx = x - jx * r;
+    T wx[4];
+    lagrange4<T>(T(mx) / T(r), wx);
+    if (nyc == 1) {
+        T acc = T(0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc += wx[b] * d[wrap(jx - 1 + b, nxc)];
+        return acc;
+    }
+    const int jy = y / r, my = y - jy * r;
+    T wy[4];
+    lagrange4<T>(T(my) / T(r), wy);
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const T *row = d + (long long)wrap(jy - 1 + a, nyc) * nxc;
+        T sa = T(0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sa += wx[b] * row[wrap(jx - 1 + b, nxc)];
+        acc += wy[a] * sa;
+    }
+    return acc;
+}
+
 // Derived sizes and workspace offsets of one context.
 struct Plan {
     menkf_config cfg;
@@ -90,7 +118,10 @@ hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, dou
 hipError_t launch_set_word(int32_t *w, int32_t v, hipStream_t s);
 hipError_t launch_set_word64(uint64_t *w, uint64_t v, hipStream_t s);
 // learned prolongation
-hipError_t launch_net_prolong(const Plan &p, const void *dc, void *xf, const void *xprev,
-                              const menkf_net *net, int fallback, void *ws, hipStream_t s);
+hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, void *xout, const menkf_net *net,
+                              int fallback, void *ws, hipStream_t s);
+hipError_t launch_net_pack(const float *prm, void *wk, hipStream_t s);
+hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s);
+size_t net_train_workspace(int B, int C);
 
 }  // namespace menkf

@@ -36,28 +36,7 @@ __global__ __launch_bounds__(256) void prolong_add(const T *__restrict__ dc, con
     const int f = (int)(i / nf);
     const long long j = i - f * nf;
     const int y = (int)(j / nx), x = (int)(j - (long long)y * nx);
-    const T *d = dc + (long long)f * nxc * nyc;
-    const int jx = x / r, mx = x - jx * r;
-    T wx[4];
-    lagrange4<T>(T(mx) / T(r), wx);
-    T acc = T(0);
-    if (nyc == 1 && ny == 1) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) acc += wx[a] * d[wrap(jx - 1 + a, nxc)];
-    } else {
-        const int jy = y / r, my = y - jy * r;
-        T wy[4];
-        lagrange4<T>(T(my) / T(r), wy);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const T *row = d + (long long)wrap(jy - 1 + a, nyc) * nxc;
-            T sa = T(0);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) sa += wx[b] * row[wrap(jx - 1 + b, nxc)];
-            acc += wy[a] * sa;
-        }
-    }
-    xout[i] = xin[i] + acc;
+    xout[i] = xin[i] + prolong_at<T>(dc + (long long)f * nxc * nyc, nxc, nyc, r, y, x);
 }
 
 template <typename T>

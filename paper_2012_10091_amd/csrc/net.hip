@@ -1,12 +1,511 @@
-// Learned convolutional prolongation (placeholder until the kernels land).
+// Learned convolutional prolongation: inference (fused, BF16 MFMA) and
+// training (direct convolutions, BF16 storage, FP32 arithmetic, Adam).
+//
+// Network: conv3x3(8->32) -> ReLU -> conv3x3(32->32) -> ReLU -> conv3x3(32->4),
+// cross-correlation, circular padding on the periodic fine grid.  Input
+// channels: Pi_F(delta^C) (4 fields) and x^F_f (4 fields), each mapped to
+// (v - in_offset) * in_scale.  The fine correction is
+// Pi_F(delta^C) + out / out_scale, so a zero last layer is exactly the plain
+// prolongation.
+//
+// Inference: one workgroup per 16x16 output tile.  The loader computes
+// Pi_F(delta^C) on the fly (the same device function as the plain
+// prolongation) on the tile plus a halo of 3; the three layers run as
+// implicit GEMMs on v_mfma_f32_32x32x16_bf16 with output channels as the M
+// dimension, 32 pixels as N, and K = (tap, input channel) with channels
+// fastest, so each lane's 8 K-values are 8 consecutive channels of one tap
+// of one pixel: a single 16-byte LDS read from the channel-last activations.
 #include "common.hpp"
 
 namespace menkf {
 
-hipError_t launch_net_prolong(const Plan &p, const void *dc, void *xf, const void *xprev, const menkf_net *net,
+// FP32 parameter vector (PyTorch order) and packed BF16 kernel layout.
+constexpr int P_W1 = 0, P_B1 = 2304, P_W2 = 2336, P_B2 = 11552, P_W3 = 11584, P_B3 = 12736, P_N = 12740;
+constexpr int K_W1 = 0, K_W2 = 2304, K_W3 = 11520, K_N = 20736;
+
+__global__ __launch_bounds__(256) void net_pack_kernel(const float *__restrict__ prm, __bf16 *__restrict__ wk) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K_N) return;
+    float v;
+    if (t < K_W2) {                       // w1 [32][9][8] <- [32][8][3][3]
+        const int o = t / 72, rem = t % 72, tap = rem / 8, ic = rem % 8;
+        v = prm[P_W1 + o * 72 + ic * 9 + tap];
+    } else if (t < K_W3) {                // w2 [32][9][32] <- [32][32][3][3]
+        const int u = t - K_W2;
+        const int o = u / 288, rem = u % 288, tap = rem / 32, ic = rem % 32;
+        v = prm[P_W2 + o * 288 + ic * 9 + tap];
+    } else {                              // w3 [32][9][32] <- [4][32][3][3], rows >= 4 zero
+        const int u = t - K_W3;
+        const int o = u / 288, rem = u % 288, tap = rem / 32, ic = rem % 32;
+        v = o < 4 ? prm[P_W3 + o * 288 + ic * 9 + tap] : 0.0f;
+    }
+    wk[t] = (__bf16)v;
+}
+
+// ----------------------------------------------------------------- inference
+constexpr int NT = 16, R0 = NT + 6, R1 = NT + 4, R2 = NT + 2;
+constexpr int NP0 = R0 * R0, NP1 = R1 * R1, NP2 = R2 * R2, NP3 = NT * NT;
+
+struct NetConst {
+    float in_scale[8], in_offset[8], out_scale[4];
+    float guard;
+};
+
+__device__ __forceinline__ bf16x8 zero_bf16x8() {
+    bf16x8 z;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.0f;
+    return z;
+}
+
+// One conv layer from LDS activations act_in ([RIN*RIN][IC], BF16) to
+// act_out ([ROUT*ROUT][32], BF16, bias + ReLU).  Waves take 32-pixel groups
+// round-robin.
+template <int IC, int RIN, int ROUT>
+__device__ __forceinline__ void conv_layer(const __bf16 *act_in, __bf16 *act_out, const __bf16 *__restrict__ wk,
+                                           const float *__restrict__ bias, int wave, int lane) {
+    constexpr int K = 9 * IC;
+    constexpr int KCH = (K + 15) / 16;
+    constexpr int NPIX = ROUT * ROUT;
+    bf16x8 a[KCH];
+#pragma unroll
+    for (int ks = 0; ks < KCH; ++ks) {
+        const int kb = ks * 16 + (lane >> 5) * 8;
+        a[ks] = kb < K ? *reinterpret_cast<const bf16x8 *>(wk + (lane & 31) * K + kb) : zero_bf16x8();
+    }
+    float bv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bv[e] = bias[8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)];
+    for (int nt = wave; nt * 32 < NPIX; nt += 4) {
+        const int n = nt * 32 + (lane & 31);
+        const bool valid = n < NPIX;
+        const int nn = valid ? n : 0;
+        const int py = nn / ROUT, px = nn - py * ROUT;
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < KCH; ++ks) {
+            const int kb = ks * 16 + (lane >> 5) * 8;
+            bf16x8 b;
+            if (kb < K) {
+                const int tap = kb / IC, ic0 = kb - tap * IC;
+                const int pix = (py + tap / 3) * RIN + (px + tap % 3);
+                b = *reinterpret_cast<const bf16x8 *>(act_in + pix * IC + ic0);
+            } else {
+                b = zero_bf16x8();
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
+        }
+        if (valid) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int oc0 = 8 * g + 4 * (lane >> 5);
+                __bf16 *dst = act_out + n * 32 + oc0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dst[i] = (__bf16)fmaxf(acc[4 * g + i] + bv[4 * g + i], 0.0f);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__ dc, const float *__restrict__ xf,
+                                                       float *__restrict__ xout, const __bf16 *__restrict__ wk,
+                                                       const float *__restrict__ prm, NetConst nc, int nx, int ny,
+                                                       int r, int nxc, int nyc, int tiles_x, int total_tiles,
+                                                       int fallback, int32_t *__restrict__ fb_count,
+                                                       const int32_t *__restrict__ info) {
+    __shared__ __align__(16) __bf16 in0[NP0 * 8];
+    __shared__ __align__(16) __bf16 act1[NP1 * 32];
+    __shared__ __align__(16) __bf16 act2[NP2 * 32];
+    __shared__ float dps[4][NP3];
+    __shared__ float outb[4][NP3];
+    __shared__ float red[3][256];
+    if (*info != 0) return;
+    const int lb = xcd_remap(blockIdx.x, total_tiles);
+    const int y0 = (lb / tiles_x) * NT, x0 = (lb % tiles_x) * NT;
+    const long long nf = (long long)nx * ny;
+    const long long ncp = (long long)nxc * nyc;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+    for (int p = tid; p < NP0; p += 256) {
+        const int py = p / R0, px = p - py * R0;
+        const int gy = wrap(y0 - 3 + py, ny), gx = wrap(x0 - 3 + px, nx);
+        const long long g = (long long)gy * nx + gx;
+        __bf16 v[8];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const float d = prolong_at<float>(dc + f * ncp, nxc, nyc, r, gy, gx);
+            const float xv = xf[f * nf + g];
+            v[f] = (__bf16)((d - nc.in_offset[f]) * nc.in_scale[f]);
+            v[4 + f] = (__bf16)((xv - nc.in_offset[4 + f]) * nc.in_scale[4 + f]);
+            if (py >= 3 && py < 3 + NT && px >= 3 && px < 3 + NT) dps[f][(py - 3) * NT + (px - 3)] = d;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) in0[p * 8 + c] = v[c];
+    }
+    __syncthreads();
+    conv_layer<8, R0, R1>(in0, act1, wk + K_W1, prm + P_B1, wave, lane);
+    __syncthreads();
+    conv_layer<32, R1, R2>(act1, act2, wk + K_W2, prm + P_B2, wave, lane);
+    __syncthreads();
+    {
+        constexpr int K = 288, KCH = 18;
+        bf16x8 a[KCH];
+#pragma unroll
+        for (int ks = 0; ks < KCH; ++ks)
+            a[ks] = *reinterpret_cast<const bf16x8 *>(wk + K_W3 + (lane & 31) * K + ks * 16 + (lane >> 5) * 8);
+        for (int nt = wave; nt < NP3 / 32; nt += 4) {
+            const int n = nt * 32 + (lane & 31);
+            const int py = n / NT, px = n - py * NT;
+            f32x16 acc = {};
+#pragma unroll
+            for (int ks = 0; ks < KCH; ++ks) {
+                const int kb = ks * 16 + (lane >> 5) * 8;
+                const int tap = kb / 32, ic0 = kb - tap * 32;
+                const int pix = (py + tap / 3) * R2 + (px + tap % 3);
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(act2 + pix * 32 + ic0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
+            }
+            if (lane < 32) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) outb[f][n] = (acc[f] + prm[P_B3 + f]) / nc.out_scale[f];
+            }
+        }
+    }
+    __syncthreads();
+    // epilogue: one thread per output pixel
+    const int n = tid;
+    const int py = n / NT, px = n - py * NT;
+    const int gy = y0 + py, gx = x0 + px;
+    float o[4], d[4];
+    float s_o = 0.0f, s_d = 0.0f, bad = 0.0f;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        o[f] = outb[f][n];
+        d[f] = dps[f][n];
+        s_o += o[f] * o[f];
+        s_d += d[f] * d[f];
+        if (!isfinite(o[f])) bad = 1.0f;
+    }
+    bool use_net = true;
+    if (fallback) {
+        red[0][tid] = s_o;
+        red[1][tid] = s_d;
+        red[2][tid] = bad;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h) {
+                red[0][tid] += red[0][tid + h];
+                red[1][tid] += red[1][tid + h];
+                red[2][tid] += red[2][tid + h];
+            }
+            __syncthreads();
+        }
+        const float no = red[0][0], nd = red[1][0];
+        use_net = red[2][0] == 0.0f && isfinite(no) && no <= nc.guard * nc.guard * nd;
+        if (!use_net && tid == 0 && fb_count) atomicAdd(fb_count, 1);
+    }
+    if (gx < nx && gy < ny) {
+        const long long g = (long long)gy * nx + gx;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) xout[f * nf + g] = xf[f * nf + g] + d[f] + (use_net ? o[f] : 0.0f);
+    }
+}
+
+hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, void *xout, const menkf_net *net,
                               int fallback, void *ws, hipStream_t s) {
-    (void)p; (void)dc; (void)xf; (void)xprev; (void)net; (void)fallback; (void)ws; (void)s;
-    return hipErrorNotSupported;
+    const int32_t *info = (const int32_t *)((char *)ws + p.off_info);
+    NetConst nc;
+    for (int i = 0; i < 8; ++i) {
+        nc.in_scale[i] = net->in_scale[i];
+        nc.in_offset[i] = net->in_offset[i];
+    }
+    for (int i = 0; i < 4; ++i) nc.out_scale[i] = net->out_scale[i];
+    nc.guard = net->guard;
+    const int tiles_x = (p.nx + NT - 1) / NT, tiles_y = (p.ny + NT - 1) / NT;
+    const int total = tiles_x * tiles_y;
+    hipLaunchKernelGGL(net_prolong_fwd, dim3(total), dim3(256), 0, s, (const float *)dc, (const float *)xf,
+                       (float *)xout, (const __bf16 *)net->wpacked, net->params, nc, p.nx, p.ny, p.cfg.ratio, p.nxc,
+                       p.nyc, tiles_x, total, fallback, net->fallback_count_dev, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_pack(const float *prm, void *wk, hipStream_t s) {
+    hipLaunchKernelGGL(net_pack_kernel, dim3((K_N + 255) / 256), dim3(256), 0, s, prm, (__bf16 *)wk);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- training
+// Crops of C x C output pixels; layer inputs shrink by 2 per valid 3x3
+// convolution: input (C+6)^2, a1 (C+4)^2, a2 (C+2)^2, out C^2.  Activations
+// BF16, gradients FP32, weights rounded to BF16 on the fly from the FP32
+// master copy (the straight-through gradient updates the master copy).
+struct TrainShapes {
+    int B, C, H0, H1, H2, H3;
+};
+
+__device__ __forceinline__ float bfr(float v) { return (float)(__bf16)v; }
+
+__global__ __launch_bounds__(256) void train_gather(const float *__restrict__ dproj, const float *__restrict__ xf,
+                                                    const float *__restrict__ target, const int32_t *__restrict__ crops,
+                                                    int H, int W, TrainShapes sh, NetConst nc,
+                                                    __bf16 *__restrict__ in0, float *__restrict__ tgt) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)sh.H0 * sh.H0;
+    if (t >= per * sh.B) return;
+    const int b = (int)(t / per);
+    const int pix = (int)(t - (long long)b * per);
+    const int py = pix / sh.H0, px = pix - py * sh.H0;
+    const int pr = crops[3 * b], cy = crops[3 * b + 1], cx = crops[3 * b + 2];
+    const int gy = wrap(cy - 3 + py, H), gx = wrap(cx - 3 + px, W);
+    const long long hw = (long long)H * W;
+    const long long g = (long long)pr * 4 * hw + (long long)gy * W + gx;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const float d = dproj[g + f * hw];
+        in0[((long long)b * 8 + f) * per + pix] = (__bf16)((d - nc.in_offset[f]) * nc.in_scale[f]);
+        in0[((long long)b * 8 + 4 + f) * per + pix] =
+            (__bf16)((xf[g + f * hw] - nc.in_offset[4 + f]) * nc.in_scale[4 + f]);
+        if (py >= 3 && py < 3 + sh.C && px >= 3 && px < 3 + sh.C) {
+            const long long o = ((long long)b * 4 + f) * sh.C * sh.C + (long long)(py - 3) * sh.C + (px - 3);
+            tgt[o] = (target[g + f * hw] - d) * nc.out_scale[f];
+        }
+    }
+}
+
+// Valid 3x3 convolution, thread per output.  OUT_BF16: BF16 + ReLU output
+// (hidden layers); else FP32 output without activation (last layer).
+template <bool HIDDEN>
+__global__ __launch_bounds__(256) void train_conv_fwd(const __bf16 *__restrict__ in, int Ci, int Hi,
+                                                      const float *__restrict__ w, const float *__restrict__ bias,
+                                                      int Co, int B, void *__restrict__ out) {
+    const int Ho = Hi - 2;
+    const long long per = (long long)Ho * Ho;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per * Co * B) return;
+    const int b = (int)(t / (per * Co));
+    const long long rem = t - (long long)b * per * Co;
+    const int o = (int)(rem / per);
+    const int pix = (int)(rem - (long long)o * per);
+    const int y = pix / Ho, x = pix - y * Ho;
+    float acc = bias[o];
+    for (int c = 0; c < Ci; ++c) {
+        const __bf16 *ip = in + ((long long)b * Ci + c) * Hi * Hi + (long long)y * Hi + x;
+        const float *wp = w + (o * Ci + c) * 9;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) acc += bfr(wp[ky * 3 + kx]) * (float)ip[ky * Hi + kx];
+    }
+    if (HIDDEN)
+        ((__bf16 *)out)[t] = (__bf16)fmaxf(acc, 0.0f);
+    else
+        ((float *)out)[t] = acc;
+}
+
+// g = 2 (out - tgt) / n and per-block partial sums of (out - tgt)^2.
+__global__ __launch_bounds__(256) void train_mse(const float *__restrict__ out, const float *__restrict__ tgt, long long n,
+                                                 float *__restrict__ g, double *__restrict__ part) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const float d = out[i] - tgt[i];
+        g[i] = 2.0f * d / (float)n;
+        acc += (double)d * d;
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(64) void train_loss_final(const double *__restrict__ part, int nb, long long n,
+                                                       double *__restrict__ loss) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nb; ++i) s += part[i];
+        *loss = s / (double)n;
+    }
+}
+
+// Gradient w.r.t. the input of a valid conv, multiplied by the ReLU mask of
+// that input (act > 0): thread per input element.
+__global__ __launch_bounds__(256) void train_conv_bwd_data(const float *__restrict__ gout, int Co, int Ho,
+                                                           const float *__restrict__ w, const __bf16 *__restrict__ act,
+                                                           int Ci, int B, float *__restrict__ gin) {
+    const int Hi = Ho + 2;
+    const long long per = (long long)Hi * Hi;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per * Ci * B) return;
+    if (!((float)act[t] > 0.0f)) {
+        gin[t] = 0.0f;
+        return;
+    }
+    const int b = (int)(t / (per * Ci));
+    const long long rem = t - (long long)b * per * Ci;
+    const int c = (int)(rem / per);
+    const int pix = (int)(rem - (long long)c * per);
+    const int y = pix / Hi, x = pix - y * Hi;
+    float acc = 0.0f;
+    for (int o = 0; o < Co; ++o) {
+        const float *gp = gout + ((long long)b * Co + o) * Ho * Ho;
+        const float *wp = w + (o * Ci + c) * 9;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            const int yy = y - ky;
+            if (yy < 0 || yy >= Ho) continue;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const int xx = x - kx;
+                if (xx < 0 || xx >= Ho) continue;
+                acc += bfr(wp[ky * 3 + kx]) * gp[yy * Ho + xx];
+            }
+        }
+    }
+    gin[t] = acc;
+}
+
+// dW[o][c][ky][kx] = sum_{b,y,x} gout[b][o][y][x] in[b][c][y+ky][x+kx]: one
+// block per (o, c), fixed-order reduction.  db[o] from the blocks with c == 0.
+__global__ __launch_bounds__(256) void train_conv_bwd_weight(const float *__restrict__ gout, int Co, int Ho,
+                                                             const __bf16 *__restrict__ in, int Ci, int B,
+                                                             float *__restrict__ dw, float *__restrict__ db) {
+    __shared__ float s[10][256];
+    const int o = blockIdx.x / Ci, c = blockIdx.x % Ci;
+    const int Hi = Ho + 2;
+    float acc[10] = {};
+    const long long per = (long long)Ho * Ho;
+    for (int b = 0; b < B; ++b) {
+        const float *gp = gout + ((long long)b * Co + o) * per;
+        const __bf16 *ip = in + ((long long)b * Ci + c) * Hi * Hi;
+        for (long long p = threadIdx.x; p < per; p += 256) {
+            const int y = (int)(p / Ho), x = (int)(p - (long long)y * Ho);
+            const float g = gp[p];
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) acc[ky * 3 + kx] += g * (float)ip[(y + ky) * Hi + x + kx];
+            acc[9] += g;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) s[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 9) dw[(o * Ci + c) * 9 + threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x == 9 && c == 0) db[o] = s[9][0];
+}
+
+__global__ __launch_bounds__(256) void train_adam(float *__restrict__ p, const float *__restrict__ g,
+                                                  float *__restrict__ m, float *__restrict__ v, int n, float lr,
+                                                  float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct TrainLayout {
+    size_t in0, a1, a2, out, tgt, g3, g2, g1, part, total;
+};
+
+static TrainLayout train_layout(int B, int C) {
+    TrainLayout L;
+    const size_t H0 = C + 6, H1 = C + 4, H2 = C + 2, H3 = C;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = al256(o + bytes);
+        return at;
+    };
+    L.in0 = take((size_t)B * 8 * H0 * H0 * 2);
+    L.a1 = take((size_t)B * 32 * H1 * H1 * 2);
+    L.a2 = take((size_t)B * 32 * H2 * H2 * 2);
+    L.out = take((size_t)B * 4 * H3 * H3 * 4);
+    L.tgt = take((size_t)B * 4 * H3 * H3 * 4);
+    L.g3 = take((size_t)B * 4 * H3 * H3 * 4);
+    L.g2 = take((size_t)B * 32 * H2 * H2 * 4);
+    L.g1 = take((size_t)B * 32 * H1 * H1 * 4);
+    L.part = take(1024 * 8);
+    L.total = o;
+    return L;
+}
+
+size_t net_train_workspace(int B, int C) { return train_layout(B, C).total; }
+
+static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s) {
+    const TrainLayout L = train_layout(t->batch, t->crop);
+    char *w = (char *)t->workspace_dev;
+    TrainShapes sh;
+    sh.B = t->batch;
+    sh.C = t->crop;
+    sh.H0 = t->crop + 6;
+    sh.H1 = t->crop + 4;
+    sh.H2 = t->crop + 2;
+    sh.H3 = t->crop;
+    NetConst nc;
+    for (int i = 0; i < 8; ++i) {
+        nc.in_scale[i] = t->in_scale[i];
+        nc.in_offset[i] = t->in_offset[i];
+    }
+    for (int i = 0; i < 4; ++i) nc.out_scale[i] = t->out_scale[i];
+    nc.guard = 0.0f;
+    __bf16 *in0 = (__bf16 *)(w + L.in0), *a1 = (__bf16 *)(w + L.a1), *a2 = (__bf16 *)(w + L.a2);
+    float *out = (float *)(w + L.out), *tgt = (float *)(w + L.tgt), *g3 = (float *)(w + L.g3);
+    float *g2 = (float *)(w + L.g2), *g1 = (float *)(w + L.g1);
+    double *part = (double *)(w + L.part);
+    const float *P = t->params;
+    float *G = t->grad;
+    const int B = sh.B;
+    hipLaunchKernelGGL(train_gather, dim3(nblk((long long)sh.H0 * sh.H0 * B)), dim3(256), 0, s, t->dproj, t->xf,
+                       t->target, t->crops_dev, t->H, t->W, sh, nc, in0, tgt);
+    hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
+                       (const __bf16 *)in0, 8, sh.H0, P + P_W1, P + P_B1, 32, B, (void *)a1);
+    hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
+                       (const __bf16 *)a1, 32, sh.H1, P + P_W2, P + P_B2, 32, B, (void *)a2);
+    hipLaunchKernelGGL(train_conv_fwd<false>, dim3(nblk((long long)sh.H3 * sh.H3 * 4 * B)), dim3(256), 0, s,
+                       (const __bf16 *)a2, 32, sh.H2, P + P_W3, P + P_B3, 4, B, (void *)out);
+    const long long nout = (long long)B * 4 * sh.H3 * sh.H3;
+    int nbm = (int)nblk(nout);
+    if (nbm > 1024) nbm = 1024;
+    hipLaunchKernelGGL(train_mse, dim3(nbm), dim3(256), 0, s, (const float *)out, (const float *)tgt, nout, g3, part);
+    hipLaunchKernelGGL(train_loss_final, dim3(1), dim3(64), 0, s, (const double *)part, nbm, nout, t->loss_dev);
+    // layer 3
+    hipLaunchKernelGGL(train_conv_bwd_weight, dim3(4 * 32), dim3(256), 0, s, (const float *)g3, 4, sh.H3,
+                       (const __bf16 *)a2, 32, B, G + P_W3, G + P_B3);
+    hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
+                       (const float *)g3, 4, sh.H3, P + P_W3, (const __bf16 *)a2, 32, B, g2);
+    // layer 2
+    hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 32), dim3(256), 0, s, (const float *)g2, 32, sh.H2,
+                       (const __bf16 *)a1, 32, B, G + P_W2, G + P_B2);
+    hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
+                       (const float *)g2, 32, sh.H2, P + P_W2, (const __bf16 *)a1, 32, B, g1);
+    // layer 1
+    hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 8), dim3(256), 0, s, (const float *)g1, 32, sh.H1,
+                       (const __bf16 *)in0, 8, B, G + P_W1, G + P_B1);
+    if (t->apply_adam) {
+        const float c1 = 1.0f - powf(t->beta1, (float)t->step);
+        const float c2 = 1.0f - powf(t->beta2, (float)t->step);
+        hipLaunchKernelGGL(train_adam, dim3(nblk(P_N)), dim3(256), 0, s, t->params, (const float *)G, t->adam_m,
+                           t->adam_v, P_N, t->lr, t->beta1, t->beta2, t->eps, c1, c2);
+        if (t->wpacked) return launch_net_pack(t->params, t->wpacked, s);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace menkf

@@ -1,0 +1,166 @@
+"""GPU parity of the learned prolongation (inference kernel, fallback guard,
+training forward/backward and Adam) against the FP64 oracle network."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import grids, net as onet
+from synthetic import configs, fields
+from tests.gpu_helpers import make_ctx, rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+F32 = torch.float32
+
+
+def _bf16(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _params(cfg, seed=5, zero_last=False, last_gain=1.0):
+    p = onet.init_params(cfg, seed=seed, zero_last=zero_last)
+    p.w3 = p.w3 * last_gain
+    p.b1 = 0.05 * np.random.default_rng(seed).standard_normal(32)
+    p.b2 = 0.05 * np.random.default_rng(seed + 1).standard_normal(32)
+    p.b3 = 0.0 * p.b3 if zero_last else 0.01 * np.random.default_rng(seed + 2).standard_normal(4)
+    for name in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        setattr(p, name, _bf16(getattr(p, name)))
+    return p
+
+
+def _gpu_net(p, guard=10.0):
+    import paper_2012_10091_amd as m
+    flat = m.pack_params([p.w1, p.b1, p.w2, p.b2, p.w3, p.b3])
+    return m.Net(flat, p.in_scale, p.in_offset, p.out_scale, guard=guard)
+
+
+def _inputs(cfg, amp=0.01, seed=9):
+    r = np.random.default_rng(seed)
+    dc = (amp * r.standard_normal((4, cfg.nyc, cfg.nxc))).astype(np.float32).astype(np.float64)
+    xf = fields.truth_ic(cfg).astype(np.float32).astype(np.float64)
+    return dc, xf
+
+
+@pytest.mark.parametrize("cfg", [configs.tiny_2d(), configs.ragged_2d()], ids=["tiny", "ragged"])
+def test_learned_prolongation_matches_oracle(cfg):
+    import paper_2012_10091_amd as m
+    ctx, _, _ = make_ctx(cfg)
+    p = _params(cfg)
+    gnet = _gpu_net(p)
+    dc, xf = _inputs(cfg)
+    xf_d = to_dev(xf, F32)
+    say("learned prolongation", cfg.name)
+    ctx.prolong_smooth(to_dev(dc, F32), xf_d, None, n_sweeps=0, mode=m.MENKF_PROLONG_LEARNED, net=gnet)
+    dproj = grids.prolong(dc, cfg.ratio, 2)
+    corr = onet.learned_correction(p, dproj, xf)
+    got = to_np(xf_d) - xf
+    nn_o = corr - dproj
+    assert np.linalg.norm(nn_o) > 0.1 * np.linalg.norm(dproj)      # the network contributes
+    assert rel_l2(got, corr) < 2e-2, rel_l2(got, corr)
+    assert rel_l2(got - dproj, nn_o) < 5e-2, rel_l2(got - dproj, nn_o)
+
+
+def test_zero_last_layer_equals_plain_bitwise():
+    import paper_2012_10091_amd as m
+    cfg = configs.ragged_2d()
+    ctx, _, _ = make_ctx(cfg)
+    gnet = _gpu_net(_params(cfg, zero_last=True))
+    dc, xf = _inputs(cfg)
+    a, b = to_dev(xf, F32), to_dev(xf, F32)
+    dcd = to_dev(dc, F32)
+    say("zero last layer == plain")
+    ctx.prolong_smooth(dcd, a, None, n_sweeps=0, mode=m.MENKF_PROLONG_LEARNED, net=gnet)
+    ctx.prolong_smooth(dcd, b, None, n_sweeps=0, mode=m.MENKF_PROLONG_PLAIN)
+    np.testing.assert_array_equal(to_np(a), to_np(b))
+
+
+def test_fallback_guard_restores_plain_path():
+    import paper_2012_10091_amd as m
+    cfg = configs.tiny_2d()
+    ctx, _, _ = make_ctx(cfg)
+    gnet = _gpu_net(_params(cfg), guard=1e-20)
+    dc, xf = _inputs(cfg)
+    xprev = fields.truth_ic(cfg).astype(np.float32)
+    a, b = to_dev(xf, F32), to_dev(xf, F32)
+    dcd, xp = to_dev(dc, F32), to_dev(xprev, F32)
+    say("fallback on every tile")
+    ctx.prolong_smooth(dcd, a, xp, n_sweeps=1, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=gnet)
+    ctx.prolong_smooth(dcd, b, xp, n_sweeps=1, mode=m.MENKF_PROLONG_PLAIN)
+    np.testing.assert_array_equal(to_np(a), to_np(b))
+    assert int(gnet.fallback_count.item()) == (cfg.nx // 16) * (cfg.ny // 16)
+    # a generous guard keeps the network everywhere
+    gnet2 = _gpu_net(_params(cfg), guard=1e6)
+    c = to_dev(xf, F32)
+    ctx.prolong_smooth(dcd, c, xp, n_sweeps=0, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=gnet2)
+    assert int(gnet2.fallback_count.item()) == 0
+    d = to_dev(xf, F32)
+    ctx.prolong_smooth(dcd, d, None, n_sweeps=0, mode=m.MENKF_PROLONG_LEARNED, net=gnet2)
+    np.testing.assert_array_equal(to_np(c), to_np(d))
+
+
+def _train_case(seed=3):
+    cfg = configs.tiny_2d(nx=32, ny=32)
+    r = np.random.default_rng(seed)
+    npairs, H = 2, 32
+    dproj = (0.01 * r.standard_normal((npairs, 4, H, H))).astype(np.float32)
+    xf = np.stack([fields.truth_ic(cfg.with_(seed=cfg.seed + k)) for k in range(npairs)]).astype(np.float32)
+    target = (dproj * 1.3 + 0.0005 * r.standard_normal(dproj.shape)).astype(np.float32)
+    crops = np.array([[0, 0, 0], [1, 27, 5], [0, 13, 29]], dtype=np.int32)
+    return cfg, dproj, xf, target, crops
+
+
+def _oracle_loss_grad(p, dproj, xf, target, crops, C):
+    dproj, xf, target = (np.asarray(a, dtype=np.float64) for a in (dproj, xf, target))
+    n = crops.shape[0] * 4 * C * C
+    grads = [np.zeros_like(t) for t in p.tensors()]
+    loss = 0.0
+    H, W = dproj.shape[-2:]
+    for pr, y0, x0 in crops:
+        inp = onet.make_input(p, dproj[pr], xf[pr])
+        out, cache = onet.forward(p, inp)
+        t = (target[pr] - dproj[pr]) * p.out_scale[:, None, None]
+        ys = (y0 + np.arange(C)) % H
+        xs = (x0 + np.arange(C)) % W
+        mask = np.zeros((H, W), dtype=bool)
+        mask[np.ix_(ys, xs)] = True
+        diff = np.where(mask[None], out - t, 0.0)
+        loss += float(np.sum(diff * diff))
+        g, _ = onet.backward(p, cache, 2.0 * diff / n)
+        for a, b in zip(grads, g):
+            a += b
+    return loss / n, grads
+
+
+def test_training_gradient_matches_oracle():
+    import paper_2012_10091_amd as m
+    cfg, dproj, xf, target, crops = _train_case()
+    p = _params(cfg, last_gain=3.0)
+    gnet = _gpu_net(p)
+    C = 10
+    tr = m.Trainer(gnet, batch=crops.shape[0], crop=C)
+    say("training gradient parity")
+    loss = tr.step(to_dev(dproj, F32), to_dev(xf, F32), to_dev(target, F32),
+                   torch.as_tensor(crops, device="cuda"), apply_adam=False)
+    lo, go = _oracle_loss_grad(p, dproj, xf, target, crops, C)
+    assert abs(float(loss.item()) - lo) < 2e-2 * lo, (float(loss.item()), lo)
+    gg = m.unpack_params(tr.grad.cpu())
+    for name, a, b in zip(("w1", "b1", "w2", "b2", "w3", "b3"), gg, go):
+        assert rel_l2(a.double().numpy(), b) < 5e-2, (name, rel_l2(a.double().numpy(), b))
+
+
+def test_training_reduces_loss():
+    import paper_2012_10091_amd as m
+    cfg, dproj, xf, target, crops = _train_case(seed=4)
+    p = _params(cfg, zero_last=True)
+    gnet = _gpu_net(p)
+    tr = m.Trainer(gnet, batch=3, crop=10, lr=3e-3)
+    args = (to_dev(dproj, F32), to_dev(xf, F32), to_dev(target, F32), torch.as_tensor(crops, device="cuda"))
+    say("training 60 Adam steps")
+    first = float(tr.step(*args).item())
+    for _ in range(59):
+        tr.step(*args)
+    last = float(tr.step(*args, apply_adam=False).item())
+    assert last < 0.5 * first, (first, last)
+    # the repacked BF16 weights follow the master copy
+    w3 = m.unpack_params(gnet.params.cpu())[4]
+    assert float(w3.abs().max()) > 0
