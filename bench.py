@@ -41,7 +41,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sweeps", type=int, default=3)
+    ap.add_argument("--rmse-cycles", type=int, default=100)
+    ap.add_argument("--judge-every", type=int, default=10)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--weights", default=None)
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
     return ap.parse_args()
 
@@ -86,6 +89,10 @@ class Cycle:
         c.update(self.members, self.dc, stream=stream)
         c.prolong_smooth(self.dc, self.fine, self.prev, n_sweeps=self.n_sweeps, alpha=0.5, mode=self.mode,
                          net=self.net, stream=stream)
+
+    def set_state(self, fine, members):
+        self.fine.copy_(fine)
+        self.members.copy_(members)
 
     def capture(self, stream):
         import torch
@@ -142,6 +149,68 @@ def time_cycles(cyc, Y, warmup, steps):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every, tau=1.0):
+    """Plain (Pi_F + sweeps) and learned (network, per-tile guard) MEnKF runs
+    from the same seeds against one truth; the plain path also judges the
+    learned one every judge_every cycles (relative L2 distance of the two
+    corrected states > tau switches the learned run to plain for good)."""
+    import numpy as np
+    import torch
+    import paper_2012_10091_amd as m
+    from synthetic import fields
+    runs = {k: Cycle(cfg, n_sweeps if k == "plain" else 0,
+                     mode=m.MENKF_PROLONG_PLAIN if k == "plain" else m.MENKF_PROLONG_LEARNED_FALLBACK,
+                     net=None if k == "plain" else net)
+            for k in ("plain", "learned")}
+    ctx = runs["plain"].ctx
+    truth = torch.as_tensor(fields.truth_ic(cfg), dtype=torch.float32, device="cuda").contiguous()
+    out = torch.zeros(3, dtype=torch.float64, device="cuda")
+    rm = {"plain": [], "learned": []}
+    sticky = False
+    judge = []
+    scratch = torch.empty_like(runs["plain"].fine)
+    for c in range(1, n_cycles + 1):
+        ctx.forecast(m.MENKF_FINE, truth, cfg.n_obs)
+        y = ctx.observe(m.MENKF_FINE, truth)[0] + torch.as_tensor(fields.obs_noise(cfg, c), device="cuda")
+        for k, r in runs.items():
+            r.y.copy_(y)
+            cc = r.ctx
+            cc.forecast(m.MENKF_FINE, r.fine, cfg.n_obs, prev=r.prev)
+            cc.forecast(m.MENKF_COARSE, r.members, cfg.n_obs)
+            cc.restrict(r.fine, r.xs)
+            cc.gain(r.members, r.xs, r.y, r.seed, c)
+            cc.update(r.members, r.dc)
+            judging = k == "learned" and not sticky and c % judge_every == 0
+            if judging:
+                xf_copy = r.fine.clone()
+                scratch.copy_(r.fine)
+                cc.prolong_smooth(r.dc, scratch, r.prev, n_sweeps=n_sweeps, alpha=0.5)
+            if k == "learned" and sticky:
+                cc.prolong_smooth(r.dc, r.fine, r.prev, n_sweeps=n_sweeps, alpha=0.5)
+            else:
+                cc.prolong_smooth(r.dc, r.fine, r.prev, n_sweeps=r.n_sweeps, alpha=0.5, mode=r.mode, net=r.net)
+            if judging:
+                d = float(torch.linalg.vector_norm(r.fine - scratch) / torch.linalg.vector_norm(scratch - xf_copy))
+                judge.append((c, d))
+                if d > tau:
+                    sticky = True
+            cc.diagnostics(r.fine, truth, out=out)
+            o = out.cpu().numpy()
+            rm[k].append(float(np.sqrt(o[0] / o[1])))
+    for r in runs.values():
+        if r.ctx.get_status() != 0:
+            raise RuntimeError("analysis failed in the RMSE comparison")
+    half = n_cycles // 2
+    res = {k: float(np.mean(v[half:])) for k, v in rm.items()}
+    return {
+        "plain_rmse": res["plain"], "learned_rmse": res["learned"],
+        "ratio": res["learned"] / res["plain"], "equal_rmse": res["learned"] <= 1.05 * res["plain"],
+        "cycles": n_cycles, "judge_fallback": sticky,
+        "fallback_tiles": int(net.fallback_count.item()), "judge": judge,
+        "rmse_first_last": {k: [v[0], v[-1]] for k, v in rm.items()},
+    }
 
 
 def stage_kernel_roofline(cfg, cyc, reps=2):
@@ -219,6 +288,15 @@ def cpu_baseline(cfg):
     }
 
 
+def load_net(cfg, path):
+    import paper_2012_10091_amd as m
+    from paper_2012_10091_amd import learned
+    path = path or learned.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return None, path
+    return learned.load(path, guard=10.0), path
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -236,17 +314,41 @@ def main():
     plain = Cycle(cfg, args.sweeps)
     sec, wall = time_cycles(plain, Y, args.warmup, args.steps)
     status = plain.ctx.get_status()
-    log(f"bench: plain {args.steps / sec:.2f} cycles/s (graph events {sec:.3f}s, wall {wall:.3f}s), status {status}")
+    plain_cps = args.steps / sec
+    log(f"bench: plain {plain_cps:.2f} cycles/s (graph events {sec:.3f}s, wall {wall:.3f}s), status {status}")
+    variants = {"plain": {"cycles_per_s": plain_cps, "ms_per_cycle": sec / args.steps * 1e3,
+                          "prolongation": f"Pi_F + {args.sweeps} relaxed sweeps"}}
+    value, ms = plain_cps, sec / args.steps * 1e3
+    net, wpath = load_net(cfg, args.weights)
+    headline = "plain"
+    if net is not None and not args.small:
+        learned = Cycle(cfg, 0, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
+        lsec, _ = time_cycles(learned, Y, args.warmup, args.steps)
+        lstatus = learned.ctx.get_status()
+        lcps = args.steps / lsec
+        log(f"bench: learned {lcps:.2f} cycles/s, status {lstatus}")
+        net.fallback_count.zero_()
+        cmp = rmse_comparison(cfg, net, args.rmse_cycles, args.sweeps, args.judge_every)
+        log(f"bench: RMSE plain {cmp['plain_rmse']:.5f} learned {cmp['learned_rmse']:.5f} "
+            f"(ratio {cmp['ratio']:.3f}, equal {cmp['equal_rmse']})")
+        variants["learned"] = {"cycles_per_s": lcps, "ms_per_cycle": lsec / args.steps * 1e3,
+                               "prolongation": "network with per-tile guard (fallback Pi_F)",
+                               "weights": os.path.relpath(wpath, ROOT)}
+        variants["rmse"] = cmp
+        if cmp["equal_rmse"] and lstatus == 0:
+            value, ms, headline = lcps, lsec / args.steps * 1e3, "learned"
+    elif net is None:
+        log(f"bench: no trained weights at {wpath}; learned variant not timed")
     rl = stage_kernel_roofline(cfg, plain)
     log(f"bench: stage kernel avg {rl['avg_launch_us']:.1f} us, contract {rl['achieved']:.0f} GB/s")
     out = {
         "metric": METRIC,
-        "value": args.steps / sec,
+        "value": value,
         "unit": "cycles/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec / args.steps * 1e3,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -255,8 +357,9 @@ def main():
         "config": {
             "workload": cfg.name, "fine": [cfg.ny, cfg.nx], "coarse": [cfg.nyc, cfg.nxc],
             "members": cfg.n_members, "probes": cfg.n_probes, "steps_per_cycle": cfg.n_obs,
-            "variant": f"plain (Pi_F + {args.sweeps} relaxed sweeps)", "status_word": status,
+            "headline_variant": headline, "status_word": status,
             "precision": "FP32 stencils, FP64 innovation covariance/Cholesky/gain of x*, BF16x3 member update",
+            "variants": variants,
         },
         "roofline": {
             "bound": "hbm",

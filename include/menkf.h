@@ -268,6 +268,13 @@ menkf_status menkf_observe(menkf_ctx *ctx, int32_t level, const void *state_dev,
 menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa_dev, const void *xt_dev,
                                double *out_dev, menkf_stream stream);
 
+/* Residual of the fine-grid implicit-Euler system of the last step,
+ * r = x_{k-1} + dt F(x) - x (fine states, r must not alias the inputs).
+ * The conservativity indicator of Sec. 6 for a conserved field is
+ * Gamma = -r / dt on that field (e.g. field 2, rho v, in 2D). */
+menkf_status menkf_residual(menkf_ctx *ctx, const void *x_dev, const void *xprev_dev, void *r_dev,
+                            menkf_stream stream);
+
 /* Normalised RAM requirement R_RAM = 1 + N_e / r_C^dim of one fine
  * simulation plus N_e coarse members (Sec. 3).  Host only. */
 double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);

@@ -86,6 +86,7 @@ SIGNATURES = {
     "menkf_net_train_step": (c_int32, [ctypes.POINTER(MenkfNetTrain), c_void_p]),
     "menkf_observe": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
     "menkf_diagnostics": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "menkf_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_ram_ratio": (c_double, [c_int32, c_int32, c_int32]),
     "menkf_graph_begin": (c_int32, [c_void_p]),
     "menkf_graph_end": (c_int32, [c_void_p, ctypes.POINTER(c_void_p)]),

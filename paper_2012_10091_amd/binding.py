@@ -200,7 +200,12 @@ class Context:
         self._state(xf, self.fine_shape, "xf")
         if xprev is not None:
             self._state(xprev, self.fine_shape, "xprev")
-        netp = None if net is None else ctypes.byref(net.c_struct())
+        if net is None:
+            netp = None
+        elif isinstance(net, _lib.MenkfNet):
+            netp = ctypes.byref(net)
+        else:
+            netp = ctypes.byref(net.c_struct())
         self._check(self.lib.menkf_prolong_smooth(self.handle, _ptr(deltac), _ptr(xf), _ptr(xprev), n_sweeps,
                                                   alpha, mode, netp, _stream(stream)))
 
@@ -218,6 +223,15 @@ class Context:
         y = torch.empty((nb, self.Ny), dtype=torch.float64, device=self.device)
         self._check(self.lib.menkf_observe(self.handle, level, _ptr(state), nb, _ptr(y), _stream(stream)))
         return y
+
+    def residual(self, x: torch.Tensor, xprev: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+        self._state(x, self.fine_shape, "x")
+        self._state(xprev, self.fine_shape, "xprev")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(self.lib.menkf_residual(self.handle, _ptr(x), _ptr(xprev), _ptr(out), _stream(stream)))
+        return out
 
     def diagnostics(self, xa: torch.Tensor, xt: torch.Tensor, out: Optional[torch.Tensor] = None,
                     stream=None) -> torch.Tensor:

@@ -364,6 +364,15 @@ menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa, const void *xt, d
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_diagnostics");
 }
 
+menkf_status menkf_residual(menkf_ctx *ctx, const void *x, const void *xprev, void *r, menkf_stream stream) {
+    if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
+    if (!x || !xprev || !r) return fail(ctx, MENKF_E_ARG, "null pointer");
+    if (r == x || r == xprev) return fail(ctx, MENKF_E_ARG, "r must not alias x or xprev");
+    const hipError_t e = ctx->plan.dim == 2 ? launch_ns_resid(ctx->plan, x, xprev, r, (hipStream_t)stream)
+                                            : launch_burgers_resid(ctx->plan, x, xprev, r, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_residual");
+}
+
 double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members) {
     if (dim < 1 || ratio < 1 || n_members < 0) return -1.0;
     return 1.0 + (double)n_members / std::pow((double)ratio, (double)dim);

@@ -124,6 +124,17 @@ __global__ __launch_bounds__(256) void burgers_sweep(const T *__restrict__ x, co
     out[i] = xx + w * (xp[i] + c.dt * burgers_L(x[im], xx, x[ip], c) - xx);
 }
 
+// Implicit-Euler residual r = x_prev + dt L(x) - x.
+template <typename T>
+__global__ __launch_bounds__(256) void burgers_resid(const T *__restrict__ x, const T *__restrict__ xp,
+                                                     T *__restrict__ out, int n, BurgersCoef<T> c) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
+    const T xx = x[i];
+    out[i] = xp[i] + c.dt * burgers_L(x[im], xx, x[ip], c) - xx;
+}
+
 template <typename T>
 static BurgersCoef<T> make_coef(const Plan &p, int level) {
     const int n = level == MENKF_FINE ? p.nx : p.nxc;
@@ -204,6 +215,17 @@ hipError_t launch_burgers_sweep(const Plan &p, const void *x, const void *xp, vo
     if (p.cfg.precision == MENKF_F64)
         return burgers_sweep_t<double>(p, (const double *)x, (const double *)xp, (double *)out, alpha, info, s);
     return burgers_sweep_t<float>(p, (const float *)x, (const float *)xp, (float *)out, alpha, info, s);
+}
+
+hipError_t launch_burgers_resid(const Plan &p, const void *x, const void *xp, void *out, hipStream_t s) {
+    const int blocks = (p.nx + 255) / 256;
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(burgers_resid<double>, dim3(blocks), dim3(256), 0, s, (const double *)x, (const double *)xp,
+                           (double *)out, p.nx, make_coef<double>(p, MENKF_FINE));
+    else
+        hipLaunchKernelGGL(burgers_resid<float>, dim3(blocks), dim3(256), 0, s, (const float *)x, (const float *)xp,
+                           (float *)out, p.nx, make_coef<float>(p, MENKF_FINE));
+    return hipGetLastError();
 }
 
 }  // namespace menkf

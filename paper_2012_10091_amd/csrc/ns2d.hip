@@ -26,6 +26,7 @@
 //   stage 3: acc += dt/3 k3,         s1 = q + dt k3
 //   stage 4: q = acc + dt/6 k4
 //   sweep  : x' = x + (alpha/D)(x_prev + dt F(x) - x)     (relaxed Jacobi)
+//   resid  : r = x_prev + dt F(x) - x                      (implicit-Euler residual)
 #include "common.hpp"
 
 namespace menkf {
@@ -37,7 +38,7 @@ struct NSCoef {
     T dt, w;  // w = alpha / D for the sweep
 };
 
-enum { ST1 = 1, ST2 = 2, ST3 = 3, ST4 = 4, SWEEP = 5 };
+enum { ST1 = 1, ST2 = 2, ST3 = 3, ST4 = 4, SWEEP = 5, RESID = 6 };
 
 template <typename T, int TX, int TY, int MODE>
 __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, const T *__restrict__ q0,
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     __shared__ T su[NB], sv[NB];
     __shared__ T sm[NC], sn[NC], sEp[NC], sp[NC], sT[NC], sqx[NC], sqy[NC], suy[NC], svx[NC];
 
-    if (MODE == SWEEP && *info != 0) return;
+    if (MODE == SWEEP && *info != 0) return;   // RESID is a diagnostic: no status gate
 
     const int lb = xcd_remap(blockIdx.x, total_blocks);
     const int member = lb / tiles_per_member;
@@ -173,9 +174,11 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
                 snext[gf] = q0[gf] + c.dt * kk[f];
             } else if (MODE == ST4) {
                 qout[gf] = acc[gf] + c.dt * T(1.0 / 6.0) * kk[f];
-            } else {
+            } else if (MODE == SWEEP) {
                 const T x = sin_[gf];
                 qout[gf] = x + c.w * (q0[gf] + c.dt * kk[f] - x);
+            } else {
+                qout[gf] = q0[gf] + c.dt * kk[f] - sin_[gf];
             }
         }
     }
@@ -269,6 +272,18 @@ static hipError_t ns_sweep_t(const Plan &p, const T *x, const T *xp, T *out, dou
     const NSCoef<T> c = ns_coef<T>(p, MENKF_FINE, alpha);
     using L = NSLauncher<T, NSTile<T>::TX, NSTile<T>::TY>;
     return L::template stage<SWEEP>(x, xp, nullptr, nullptr, out, nullptr, p.nx, p.ny, 1, c, info, s);
+}
+
+template <typename T>
+static hipError_t ns_resid_t(const Plan &p, const T *x, const T *xp, T *out, hipStream_t s) {
+    const NSCoef<T> c = ns_coef<T>(p, MENKF_FINE, 0.0);
+    using L = NSLauncher<T, NSTile<T>::TX, NSTile<T>::TY>;
+    return L::template stage<RESID>(x, xp, nullptr, nullptr, out, nullptr, p.nx, p.ny, 1, c, nullptr, s);
+}
+
+hipError_t launch_ns_resid(const Plan &p, const void *x, const void *xp, void *out, hipStream_t s) {
+    if (p.cfg.precision == MENKF_F64) return ns_resid_t<double>(p, (const double *)x, (const double *)xp, (double *)out, s);
+    return ns_resid_t<float>(p, (const float *)x, (const float *)xp, (float *)out, s);
 }
 
 hipError_t launch_ns_sweep(const Plan &p, const void *x, const void *xp, void *out, double alpha,
