@@ -222,20 +222,22 @@ constexpr int LDP = 65;  // padded LDS row (doubles)
 // other threads: their owners publish them to a double-buffered LDS slot,
 // so each pivot costs one barrier.  The step loop is unrolled at compile
 // time so that register indices are static.
-__global__ __launch_bounds__(256) void chol_diag(double *__restrict__ A, int ld, int k, double *__restrict__ Linv,
-                                                 int32_t *__restrict__ info) {
+// The block is read from src (row stride lds_: global A or an LDS copy) and
+// the factor written to Ak (row stride ld).  256 threads; must be entered by
+// the whole workgroup.
+__device__ __forceinline__ void chol_diag_block(const double *src, long long lds_, double *__restrict__ Ak,
+                                                long long ld, int k, double *__restrict__ Linv,
+                                                int32_t *__restrict__ info) {
     __shared__ double colbuf[2][64];
     __shared__ double rowbuf[2][64];
     __shared__ double dsq[64];
-    if (*info != 0) return;
     const int t = threadIdx.x;
     const int r = t >> 2, q = t & 3;
-    double *Ak = A + (long long)(k * 64) * ld + k * 64;
     double w[16], x[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int c = 4 * i + q;
-        w[i] = c <= r ? Ak[(long long)r * ld + c] : 0.0;
+        w[i] = c <= r ? src[(long long)r * lds_ + c] : 0.0;
         x[i] = c == r ? 1.0 : 0.0;
     }
     int bad = 0;
@@ -288,6 +290,13 @@ __global__ __launch_bounds__(256) void chol_diag(double *__restrict__ A, int ld,
         if (c <= r) Ak[(long long)r * ld + c] = c == r ? dr : w[i] / dsq[c];
         Linv[r * 64 + c] = c <= r ? x[i] / dr : 0.0;
     }
+}
+
+__global__ __launch_bounds__(256) void chol_diag(double *__restrict__ A, int ld, int k, double *__restrict__ Linv,
+                                                 int32_t *__restrict__ info) {
+    if (*info != 0) return;
+    double *Ak = A + (long long)(k * 64) * ld + k * 64;
+    chol_diag_block(Ak, ld, Ak, ld, k, Linv, info);
 }
 
 // acc += P Q^T for 64-row blocks P (rows of length K at ldp) and Q, K a
@@ -381,18 +390,36 @@ __global__ __launch_bounds__(256) void chol_panel(double *__restrict__ A, int ld
     gemm_nt_64(Aik, ld, Linv, 64, Aik, ld, 0.0, 1.0, smem_d, smem_d + 64 * LDP, false);
 }
 
-__global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int ld, int k, int nblk,
-                                                   const int32_t *__restrict__ info) {
+// Trailing update of step k.  Workgroup 0 owns the next diagonal block
+// (k+1, k+1): when k+1 < nbs it keeps its updated block in LDS and
+// factors it right away (look-ahead), overlapping the latency-bound pivot
+// chain of step k+1 with the other blocks of step k.
+__global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int ld, int k, int nbs,
+                                                   double *__restrict__ Linv, int32_t *__restrict__ info) {
     extern __shared__ double smem_d[];
     if (*info != 0) return;
     int bi, bj;
     tri_index(blockIdx.x, bi, bj);
     const int i = k + 1 + bi, j = k + 1 + bj;
-    (void)nblk;
     const double *Lik = A + (long long)(i * 64) * ld + k * 64;
     const double *Ljk = A + (long long)(j * 64) * ld + k * 64;
     double *Aij = A + (long long)(i * 64) * ld + j * 64;
-    gemm_nt_64(Lik, ld, Ljk, ld, Aij, ld, 1.0, -1.0, smem_d, smem_d + 64 * LDP, i == j);
+    const bool lookahead = blockIdx.x == 0 && k + 1 < nbs;
+    f64x4 acc[2][2] = {};
+    mfma_nt_64_acc(Lik, ld, Ljk, ld, 64, acc, smem_d, smem_d + 64 * LDP);
+    __syncthreads();   // the staging buffers are reused below
+    double *tile = smem_d;
+    for_each_acc(acc, [&](int r, int c, double v) {
+        if (i == j && c > r) return;
+        double *dst = Aij + (long long)r * ld + c;
+        const double nv = *dst - v;
+        *dst = nv;
+        if (lookahead) tile[r * LDP + c] = nv;
+    });
+    if (lookahead) {
+        __syncthreads();
+        chol_diag_block(tile, LDP, Aij, ld, k + 1, Linv, info);
+    }
 }
 
 // ----------------------------------------------------------------- Z from the Schur block
@@ -598,13 +625,15 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 5. blocked Cholesky of the first nyp columns, Schur complement on the rest
     const int nblk = p.ld / CHOL_NB;
+    hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, p.ld, 0, Linv, info);
     for (int k = 0; k < nbs; ++k) {
-        hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, p.ld, k, Linv, info);
         const int below = nblk - k - 1;
         if (below > 0) {
             hipLaunchKernelGGL(chol_panel, dim3(below), dim3(256), lds, s, A, p.ld, k, (const double *)Linv, info);
-            hipLaunchKernelGGL(chol_update, dim3(below * (below + 1) / 2), dim3(256), lds, s, A, p.ld, k, nblk,
+            hipLaunchKernelGGL(chol_update, dim3(below * (below + 1) / 2), dim3(256), lds, s, A, p.ld, k, nbs, Linv,
                                info);
+        } else if (k + 1 < nbs) {
+            hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, p.ld, k + 1, Linv, info);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
