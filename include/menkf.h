@@ -136,6 +136,42 @@ menkf_status menkf_set_probes(menkf_ctx *ctx, const int32_t *idx_dev, const int3
 menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state_dev, int32_t nb,
                             int32_t nsteps, void *prev_dev, menkf_stream stream);
 
+/* Forecast schedule of one grid level: how the explicit stencil of the
+ * state-evolution equation is tiled and ordered on the GPU.  It changes
+ * speed only, never results: every tile shape and chunking evaluates the
+ * same arithmetic per grid point, so forecasts are bitwise identical.
+ *   tile_x, tile_y  grid points per 256-thread workgroup of the 2D stencil,
+ *                   one of 32x16, 64x8, 32x8, 16x16, 64x4 (FP32) or
+ *                   32x8, 16x8, 16x16, 64x4 (FP64); 0, 0 = the first of
+ *                   the list.  Ignored by the 1D model.
+ *   member_chunk    states advanced together through a whole forecast
+ *                   window, chunk after chunk, so that a chunk's state and
+ *                   Runge-Kutta temporaries stay in the last-level cache;
+ *                   0 = all nb states at once.  Ignored by the 1D model. */
+typedef struct {
+    int32_t tile_x, tile_y;
+    int32_t member_chunk;
+    int32_t reserved;
+} menkf_schedule;
+
+/* Set / read the schedule of level MENKF_FINE or MENKF_COARSE (host only;
+ * applies to forecasts issued afterwards, also the relaxed sweeps and the
+ * residual for MENKF_FINE).  Unknown tile shapes or a negative chunk give
+ * MENKF_E_ARG and leave the schedule unchanged. */
+menkf_status menkf_set_schedule(menkf_ctx *ctx, int32_t level, const menkf_schedule *sched);
+menkf_status menkf_get_schedule(const menkf_ctx *ctx, int32_t level, menkf_schedule *sched);
+
+/* Autotuner of the forecast schedule: times every tile shape of the
+ * context's precision against member chunks nb, nb/2, nb/4, ... (coarse
+ * level), each as one warm-up and reps timed forecasts of nsteps steps of
+ * nb states held in scratch_dev (overwritten: pass a copy of real states,
+ * the timing depends only on the shape), with HIP events on stream.  The
+ * fastest schedule becomes the level's schedule and is returned in *best
+ * with its time per forecast in *best_ms (either may be NULL).  A set-up
+ * call: it synchronises the stream and must not be captured into a graph. */
+menkf_status menkf_autotune(menkf_ctx *ctx, int32_t level, void *scratch_dev, int32_t nb, int32_t nsteps,
+                            int32_t reps, menkf_schedule *best, float *best_ms, menkf_stream stream);
+
 /* x* = Pi_C(x^F_f) (Algo. 4 step 4): the fourth-order Lagrange restriction
  * of Sec. 2.2 on nested vertex-centred grids, i.e. injection of every
  * ratio-th node.  xf_dev: one fine state; xc_dev: one coarse state. */

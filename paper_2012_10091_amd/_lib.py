@@ -60,6 +60,10 @@ class MenkfNetTrain(ctypes.Structure):
     ]
 
 
+class MenkfSchedule(ctypes.Structure):
+    _fields_ = [("tile_x", c_int32), ("tile_y", c_int32), ("member_chunk", c_int32), ("reserved", c_int32)]
+
+
 NET_NPARAM = 12740
 NET_NPACKED = 20736
 
@@ -73,6 +77,10 @@ SIGNATURES = {
     "menkf_set_workspace": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "menkf_set_probes": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "menkf_forecast": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "menkf_set_schedule": (c_int32, [c_void_p, c_int32, ctypes.POINTER(MenkfSchedule)]),
+    "menkf_get_schedule": (c_int32, [c_void_p, c_int32, ctypes.POINTER(MenkfSchedule)]),
+    "menkf_autotune": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_int32,
+                                 ctypes.POINTER(MenkfSchedule), ctypes.POINTER(ctypes.c_float), c_void_p]),
     "menkf_restrict": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_gain": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_uint64, c_uint64, c_void_p, c_void_p]),
     "menkf_get_gain": (c_int32, [c_void_p, c_void_p, c_void_p]),

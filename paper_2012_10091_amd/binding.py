@@ -161,6 +161,26 @@ class Context:
         self._check(self.lib.menkf_forecast(self.handle, level, _ptr(state), nb, nsteps, _ptr(prev),
                                             _stream(stream)))
 
+    def set_schedule(self, level: int, tile=(0, 0), member_chunk: int = 0):
+        sc = _lib.MenkfSchedule(int(tile[0]), int(tile[1]), int(member_chunk), 0)
+        self._check(self.lib.menkf_set_schedule(self.handle, level, ctypes.byref(sc)))
+
+    def get_schedule(self, level: int) -> dict:
+        sc = _lib.MenkfSchedule()
+        self._check(self.lib.menkf_get_schedule(self.handle, level, ctypes.byref(sc)))
+        return {"tile": (sc.tile_x, sc.tile_y), "member_chunk": sc.member_chunk}
+
+    def autotune(self, level: int, scratch: torch.Tensor, nsteps: int, reps: int = 2, stream=None) -> dict:
+        """Time every forecast schedule of `level` on `scratch` (overwritten) and keep the fastest."""
+        shape = self.fine_shape if level == MENKF_FINE else self.coarse_shape
+        self._state(scratch, shape, "scratch")
+        nb = 1 if scratch.dim() == len(shape) else scratch.shape[0]
+        sc = _lib.MenkfSchedule()
+        ms = ctypes.c_float()
+        self._check(self.lib.menkf_autotune(self.handle, level, _ptr(scratch), nb, nsteps, reps, ctypes.byref(sc),
+                                            ctypes.byref(ms), _stream(stream)))
+        return {"tile": (sc.tile_x, sc.tile_y), "member_chunk": sc.member_chunk, "ms": ms.value}
+
     def restrict(self, xf: torch.Tensor, xc: torch.Tensor, stream=None):
         self._state(xf, self.fine_shape, "xf")
         self._state(xc, self.coarse_shape, "xc")

@@ -241,9 +241,10 @@ __device__ __forceinline__ void chol_diag_block(const double *src, long long lds
         x[i] = c == r ? 1.0 : 0.0;
     }
     int bad = 0;
-    // Branch-free pivot step: every thread reads one published value per
-    // owned column (row j of Xw for c <= j, column j of W otherwise) and
-    // applies the update through selects; rows r <= j use m = 0.
+    // Pivot step: every thread reads one published value per owned column
+    // (row j of Xw for c <= j, column j of W otherwise); the side of j of
+    // each column group is known at compile time except for one group, and
+    // rows r <= j skip the update.
 #define MENKF_DIAG_STEP(J)                                                   \
     if (!bad) {                                                              \
         constexpr int b_ = (J) & 1, ji_ = (J) >> 2, jq_ = (J) & 3;           \
@@ -256,15 +257,23 @@ __device__ __forceinline__ void chol_diag_block(const double *src, long long lds
         const double piv = colbuf[b_][J];                                    \
         if (t == 0) dsq[J] = piv;                                            \
         bad = (piv > 0.0) ? 0 : (J) + 1;                                     \
-        const double inv = 1.0 / piv;                                        \
-        const double m = r > (J) ? colbuf[b_][r] * inv : 0.0;                \
-        _Pragma("unroll") for (int i = 0; i < 16; ++i) {                     \
-            const int c = 4 * i + q;                                         \
-            const bool lo = c <= (J);                                        \
-            const double v = lo ? rowbuf[b_][c] : colbuf[b_][c];             \
-            const double nv = (lo ? x[i] : w[i]) - m * v;                    \
-            x[i] = lo ? nv : x[i];                                           \
-            w[i] = (!lo && c <= r) ? nv : w[i];                              \
+        if (r > (J)) {                                                       \
+            const double m = colbuf[b_][r] / piv;                            \
+            _Pragma("unroll") for (int i = 0; i < 16; ++i) {                 \
+                const int c = 4 * i + q;                                     \
+                if (4 * i + 3 <= (J)) {          /* whole group left of J */ \
+                    x[i] -= m * rowbuf[b_][c];                               \
+                } else if (4 * i > (J)) {        /* whole group right of J */\
+                    const double nv = w[i] - m * colbuf[b_][c];              \
+                    w[i] = c <= r ? nv : w[i];                               \
+                } else {                         /* the group holding J */   \
+                    const bool lo = c <= (J);                                \
+                    const double v = lo ? rowbuf[b_][c] : colbuf[b_][c];     \
+                    const double nv = (lo ? x[i] : w[i]) - m * v;            \
+                    x[i] = lo ? nv : x[i];                                   \
+                    w[i] = (!lo && c <= r) ? nv : w[i];                      \
+                }                                                            \
+            }                                                                \
         }                                                                    \
     }
 #define MENKF_DIAG_STEP4(J) MENKF_DIAG_STEP(J) MENKF_DIAG_STEP(J + 1) MENKF_DIAG_STEP(J + 2) MENKF_DIAG_STEP(J + 3)

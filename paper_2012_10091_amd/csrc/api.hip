@@ -123,6 +123,10 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     if (scratch < 4096 * 8) scratch = 4096 * 8;
     p->off_scratch = take(scratch);
     p->ws_bytes = o;
+    for (int l = 0; l < 2; ++l) {
+        ns_tile_shape(cfg->precision, 0, &p->sched[l].tile_x, &p->sched[l].tile_y);
+        p->sched[l].member_chunk = 0;
+    }
     return MENKF_OK;
 }
 
@@ -208,6 +212,96 @@ menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state, int32_t 
     const hipError_t e = p.dim == 1 ? launch_burgers_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream)
                                     : launch_ns_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream);
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_forecast");
+}
+
+static menkf_status check_schedule(menkf_ctx *ctx, int level, const menkf_schedule *sc) {
+    if (level != MENKF_FINE && level != MENKF_COARSE) return fail(ctx, MENKF_E_ARG, "bad level %d", level);
+    if (!sc) return fail(ctx, MENKF_E_ARG, "schedule is NULL");
+    if (sc->member_chunk < 0) return fail(ctx, MENKF_E_ARG, "member_chunk must be >= 0 (got %d)", sc->member_chunk);
+    if (ns_tile_index(ctx->plan.cfg.precision, sc->tile_x, sc->tile_y) < 0)
+        return fail(ctx, MENKF_E_ARG, "tile %dx%d is not in the tile list of this precision", sc->tile_x, sc->tile_y);
+    return MENKF_OK;
+}
+
+menkf_status menkf_set_schedule(menkf_ctx *ctx, int32_t level, const menkf_schedule *sched) {
+    if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
+    const menkf_status st = check_schedule(ctx, level, sched);
+    if (st != MENKF_OK) return st;
+    menkf_schedule sc = *sched;
+    if (sc.tile_x == 0 && sc.tile_y == 0) ns_tile_shape(ctx->plan.cfg.precision, 0, &sc.tile_x, &sc.tile_y);
+    sc.reserved = 0;
+    ctx->plan.sched[level == MENKF_FINE ? 0 : 1] = sc;
+    return MENKF_OK;
+}
+
+menkf_status menkf_get_schedule(const menkf_ctx *ctx, int32_t level, menkf_schedule *sched) {
+    if (!ctx || !sched) return fail(nullptr, MENKF_E_ARG, "null argument");
+    if (level != MENKF_FINE && level != MENKF_COARSE) return fail(nullptr, MENKF_E_ARG, "bad level %d", level);
+    *sched = ctx->plan.sched[level == MENKF_FINE ? 0 : 1];
+    return MENKF_OK;
+}
+
+menkf_status menkf_autotune(menkf_ctx *ctx, int32_t level, void *scratch, int32_t nb, int32_t nsteps, int32_t reps,
+                            menkf_schedule *best, float *best_ms, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!scratch) return fail(ctx, MENKF_E_ARG, "scratch state is NULL");
+    if (reps < 1 || reps > 1000) return fail(ctx, MENKF_E_ARG, "reps must be in [1, 1000]");
+    Plan &p = ctx->plan;
+    const int li = level == MENKF_FINE ? 0 : 1;
+    // candidate list
+    std::vector<menkf_schedule> cand;
+    const int ntiles = p.dim == 2 ? ns_tile_count(p.cfg.precision) : 1;
+    std::vector<int> chunks{0};
+    if (p.dim == 2 && level == MENKF_COARSE)
+        for (int c = (nb + 1) / 2; c >= 1; c = (c == 1 ? 0 : (c + 1) / 2)) {
+            chunks.push_back(c);
+            if ((long long)c * p.nc * p.F * (long long)p.tsize < (2LL << 20)) break;   // below 2 MiB per chunk
+        }
+    for (int t = 0; t < ntiles; ++t)
+        for (int c : chunks) {
+            menkf_schedule sc{};
+            ns_tile_shape(p.cfg.precision, t, &sc.tile_x, &sc.tile_y);
+            sc.member_chunk = c;
+            cand.push_back(sc);
+        }
+    const menkf_schedule keep = p.sched[li];
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float tbest = 0.0f;
+    int ibest = -1;
+    for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+        p.sched[li] = cand[i];
+        const menkf_status st = menkf_forecast(ctx, level, scratch, nb, nsteps, nullptr, stream);   // warm-up
+        if (st != MENKF_OK) {
+            p.sched[li] = keep;
+            if (e0) hipEventDestroy(e0);
+            if (e1) hipEventDestroy(e1);
+            return st;
+        }
+        e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            if (menkf_forecast(ctx, level, scratch, nb, nsteps, nullptr, stream) != MENKF_OK) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && (ibest < 0 || ms < tbest)) {
+            tbest = ms;
+            ibest = (int)i;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (e != hipSuccess || ibest < 0) {
+        p.sched[li] = keep;
+        return hip_fail(ctx, e == hipSuccess ? hipErrorUnknown : e, "menkf_autotune");
+    }
+    p.sched[li] = cand[ibest];
+    if (best) *best = cand[ibest];
+    if (best_ms) *best_ms = tbest / reps;
+    return MENKF_OK;
 }
 
 menkf_status menkf_restrict(menkf_ctx *ctx, const void *xf, void *xc, menkf_stream stream) {

@@ -89,6 +89,7 @@ struct Plan {
     size_t off_info, off_f1, off_f2, off_facc, off_c1, off_c2, off_cacc;
     size_t off_yb, off_a, off_linv, off_z, off_zt, off_zstar, off_scratch;
     size_t ws_bytes;
+    menkf_schedule sched[2];   // forecast schedule per level (0 fine, 1 coarse)
 };
 
 constexpr int CHOL_NB = 64;
@@ -97,6 +98,10 @@ constexpr int CHOL_NB = 64;
 // forecast
 hipError_t launch_burgers_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
                                    void *prev, void *ws, hipStream_t s);
+// stencil tile table of the 2D model
+int ns_tile_count(int precision);
+void ns_tile_shape(int precision, int i, int *tx, int *ty);
+int ns_tile_index(int precision, int tx, int ty);   // -1 if not in the table
 hipError_t launch_ns_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
                               void *prev, void *ws, hipStream_t s);
 // grids

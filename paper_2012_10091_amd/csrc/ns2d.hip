@@ -219,44 +219,133 @@ struct NSLauncher {
                            prev, nx, ny, tiles_x, tpm, total, c, info);
         return hipGetLastError();
     }
+    // nb states advanced member_chunk at a time through the whole window:
+    // a chunk's state and RK temporaries stay resident in the last-level
+    // cache across its 4 * nsteps stage launches.
     static hipError_t forecast(T *state, T *s1, T *s2, T *acc, T *prev, int nx, int ny, int nb, int nsteps,
-                               const NSCoef<T> &c, hipStream_t st) {
+                               int chunk, const NSCoef<T> &c, hipStream_t st) {
         hipError_t e = hipSuccess;
-        for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
-            T *pv = (prev && step == nsteps - 1) ? prev : nullptr;
-            e = stage<ST1>(state, nullptr, acc, s1, nullptr, pv, nx, ny, nb, c, nullptr, st);
-            if (e == hipSuccess) e = stage<ST2>(s1, state, acc, s2, nullptr, nullptr, nx, ny, nb, c, nullptr, st);
-            if (e == hipSuccess) e = stage<ST3>(s2, state, acc, s1, nullptr, nullptr, nx, ny, nb, c, nullptr, st);
-            if (e == hipSuccess) e = stage<ST4>(s1, nullptr, acc, nullptr, state, nullptr, nx, ny, nb, c, nullptr, st);
+        const long long msz = 4LL * nx * ny;
+        if (chunk < 1 || chunk > nb) chunk = nb;
+        for (int m0 = 0; m0 < nb && e == hipSuccess; m0 += chunk) {
+            const int cb = nb - m0 < chunk ? nb - m0 : chunk;
+            T *q = state + m0 * msz;
+            T *a = acc + m0 * msz, *t1 = s1 + m0 * msz, *t2 = s2 + m0 * msz;
+            T *pchunk = prev ? prev + m0 * msz : nullptr;
+            for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
+                T *pv = step == nsteps - 1 ? pchunk : nullptr;
+                e = stage<ST1>(q, nullptr, a, t1, nullptr, pv, nx, ny, cb, c, nullptr, st);
+                if (e == hipSuccess) e = stage<ST2>(t1, q, a, t2, nullptr, nullptr, nx, ny, cb, c, nullptr, st);
+                if (e == hipSuccess) e = stage<ST3>(t2, q, a, t1, nullptr, nullptr, nx, ny, cb, c, nullptr, st);
+                if (e == hipSuccess) e = stage<ST4>(t1, nullptr, a, nullptr, q, nullptr, nx, ny, cb, c, nullptr, st);
+            }
         }
         return e;
     }
 };
 
-// Tile shape per precision: 32 x 16 (FP32, ~34 KB LDS) and 32 x 8 (FP64, ~41 KB LDS).
-template <typename T>
-struct NSTile;
-template <>
-struct NSTile<float> {
-    static constexpr int TX = 32, TY = 16;
+// Stencil tile shapes (TX x TY points per 256-thread workgroup).  LDS per
+// workgroup: (2 (TX+8)(TY+8) + 9 (TX+4)(TY+4)) elements, e.g. 33.6 KB for
+// 32 x 16 in FP32.  The first entry of each list is the default.
+static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}};
+static const int kTilesF64[][2] = {{32, 8}, {16, 8}, {16, 16}, {64, 4}};
+
+int ns_tile_count(int precision) {
+    return precision == MENKF_F64 ? (int)(sizeof(kTilesF64) / sizeof(kTilesF64[0]))
+                                  : (int)(sizeof(kTilesF32) / sizeof(kTilesF32[0]));
+}
+
+void ns_tile_shape(int precision, int i, int *tx, int *ty) {
+    const int(*tab)[2] = precision == MENKF_F64 ? kTilesF64 : kTilesF32;
+    *tx = tab[i][0];
+    *ty = tab[i][1];
+}
+
+int ns_tile_index(int precision, int tx, int ty) {
+    if (tx == 0 && ty == 0) return 0;
+    for (int i = 0; i < ns_tile_count(precision); ++i) {
+        int a, b;
+        ns_tile_shape(precision, i, &a, &b);
+        if (a == tx && b == ty) return i;
+    }
+    return -1;
+}
+
+// Calls f.template run<TX, TY>() for the tile with index ti of the list of
+// the functor's precision.
+template <typename Fn>
+static hipError_t with_tile(int ti, const Fn &f) {
+    if constexpr (sizeof(typename Fn::T) == 8) {
+        switch (ti) {
+        case 1: return f.template run<16, 8>();
+        case 2: return f.template run<16, 16>();
+        case 3: return f.template run<64, 4>();
+        default: return f.template run<32, 8>();
+        }
+    } else {
+        switch (ti) {
+        case 1: return f.template run<64, 8>();
+        case 2: return f.template run<32, 8>();
+        case 3: return f.template run<16, 16>();
+        case 4: return f.template run<64, 4>();
+        default: return f.template run<32, 16>();
+        }
+    }
+}
+
+template <typename TT>
+struct NSForecastFn {
+    using T = TT;
+    T *state, *s1, *s2, *acc, *prev;
+    int nx, ny, nb, nsteps, chunk;
+    NSCoef<T> c;
+    hipStream_t s;
+    template <int TX, int TY>
+    hipError_t run() const {
+        return NSLauncher<T, TX, TY>::forecast(state, s1, s2, acc, prev, nx, ny, nb, nsteps, chunk, c, s);
+    }
 };
-template <>
-struct NSTile<double> {
-    static constexpr int TX = 32, TY = 8;
+
+template <typename TT, int MODE>
+struct NSSingleFn {
+    using T = TT;
+    const T *x, *xp;
+    T *out;
+    int nx, ny;
+    NSCoef<T> c;
+    const int32_t *info;
+    hipStream_t s;
+    template <int TX, int TY>
+    hipError_t run() const {
+        return NSLauncher<T, TX, TY>::template stage<MODE>(x, xp, nullptr, nullptr, out, nullptr, nx, ny, 1, c, info, s);
+    }
 };
+
+static int sched_tile(const Plan &p, int level) {
+    const menkf_schedule &sc = p.sched[level == MENKF_FINE ? 0 : 1];
+    const int ti = ns_tile_index(p.cfg.precision, sc.tile_x, sc.tile_y);
+    return ti < 0 ? 0 : ti;
+}
 
 template <typename T>
 static hipError_t ns_forecast_t(const Plan &p, int level, T *state, int nb, int nsteps, T *prev, void *ws,
                                 hipStream_t s) {
     char *w = (char *)ws;
     const bool fine = level == MENKF_FINE;
-    T *s1 = (T *)(w + (fine ? p.off_f1 : p.off_c1));
-    T *s2 = (T *)(w + (fine ? p.off_f2 : p.off_c2));
-    T *acc = (T *)(w + (fine ? p.off_facc : p.off_cacc));
-    const int nx = fine ? p.nx : p.nxc, ny = fine ? p.ny : p.nyc;
-    const NSCoef<T> c = ns_coef<T>(p, level, 0.0);
-    using L = NSLauncher<T, NSTile<T>::TX, NSTile<T>::TY>;
-    return L::forecast(state, s1, s2, acc, prev, nx, ny, nb, nsteps, c, s);
+    NSForecastFn<T> f;
+    f.state = state;
+    f.s1 = (T *)(w + (fine ? p.off_f1 : p.off_c1));
+    f.s2 = (T *)(w + (fine ? p.off_f2 : p.off_c2));
+    f.acc = (T *)(w + (fine ? p.off_facc : p.off_cacc));
+    f.prev = prev;
+    f.nx = fine ? p.nx : p.nxc;
+    f.ny = fine ? p.ny : p.nyc;
+    f.nb = nb;
+    f.nsteps = nsteps;
+    f.chunk = p.sched[fine ? 0 : 1].member_chunk;
+    f.c = ns_coef<T>(p, level, 0.0);
+    f.s = s;
+    return with_tile(sched_tile(p, level), f);
 }
 
 hipError_t launch_ns_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev, void *ws,
@@ -269,16 +358,14 @@ hipError_t launch_ns_forecast(const Plan &p, int level, void *state, int nb, int
 template <typename T>
 static hipError_t ns_sweep_t(const Plan &p, const T *x, const T *xp, T *out, double alpha, const int32_t *info,
                              hipStream_t s) {
-    const NSCoef<T> c = ns_coef<T>(p, MENKF_FINE, alpha);
-    using L = NSLauncher<T, NSTile<T>::TX, NSTile<T>::TY>;
-    return L::template stage<SWEEP>(x, xp, nullptr, nullptr, out, nullptr, p.nx, p.ny, 1, c, info, s);
+    NSSingleFn<T, SWEEP> f{x, xp, out, p.nx, p.ny, ns_coef<T>(p, MENKF_FINE, alpha), info, s};
+    return with_tile(sched_tile(p, MENKF_FINE), f);
 }
 
 template <typename T>
 static hipError_t ns_resid_t(const Plan &p, const T *x, const T *xp, T *out, hipStream_t s) {
-    const NSCoef<T> c = ns_coef<T>(p, MENKF_FINE, 0.0);
-    using L = NSLauncher<T, NSTile<T>::TX, NSTile<T>::TY>;
-    return L::template stage<RESID>(x, xp, nullptr, nullptr, out, nullptr, p.nx, p.ny, 1, c, nullptr, s);
+    NSSingleFn<T, RESID> f{x, xp, out, p.nx, p.ny, ns_coef<T>(p, MENKF_FINE, 0.0), nullptr, s};
+    return with_tile(sched_tile(p, MENKF_FINE), f);
 }
 
 hipError_t launch_ns_resid(const Plan &p, const void *x, const void *xp, void *out, hipStream_t s) {

@@ -98,3 +98,32 @@ def test_sample_mode_accepts_small_observation_count():
     st, h, lib = _create(gain_mode=1, n_probes=14, n_members=8)
     assert st == 0
     lib.menkf_destroy(h)
+
+
+def test_schedule_defaults_and_validation():
+    import paper_2012_10091_amd as m
+    from paper_2012_10091_amd import _lib as L
+    for prec, default in ((m.MENKF_F32, (32, 16)), (m.MENKF_F64, (32, 8))):
+        st, h, lib = _create(precision=prec)
+        assert st == 0
+        sc = L.MenkfSchedule()
+        for level in (0, 1):
+            assert lib.menkf_get_schedule(h, level, ctypes.byref(sc)) == 0
+            assert (sc.tile_x, sc.tile_y, sc.member_chunk) == (*default, 0)
+        assert lib.menkf_set_schedule(h, 1, ctypes.byref(L.MenkfSchedule(16, 16, 3, 0))) == 0
+        assert lib.menkf_get_schedule(h, 1, ctypes.byref(sc)) == 0
+        assert (sc.tile_x, sc.tile_y, sc.member_chunk) == (16, 16, 3)
+        # zero tile = default of the precision; unknown shapes and negative chunks are refused
+        assert lib.menkf_set_schedule(h, 0, ctypes.byref(L.MenkfSchedule(0, 0, 0, 0))) == 0
+        assert lib.menkf_get_schedule(h, 0, ctypes.byref(sc)) == 0
+        assert (sc.tile_x, sc.tile_y) == default
+        assert lib.menkf_set_schedule(h, 1, ctypes.byref(L.MenkfSchedule(48, 16, 0, 0))) == -1
+        assert lib.menkf_set_schedule(h, 1, ctypes.byref(L.MenkfSchedule(32, 8, -1, 0))) == -1
+        assert lib.menkf_set_schedule(h, 2, ctypes.byref(L.MenkfSchedule(32, 8, 0, 0))) == -1
+        assert lib.menkf_get_schedule(h, 1, ctypes.byref(sc)) == 0
+        assert (sc.tile_x, sc.tile_y, sc.member_chunk) == (16, 16, 3)
+        # the 64x8 FP32 tile exceeds nothing but is FP32-only
+        assert lib.menkf_set_schedule(h, 1, ctypes.byref(L.MenkfSchedule(64, 8, 0, 0))) == (0 if prec == 0 else -1)
+        # the autotuner needs a workspace
+        assert lib.menkf_autotune(h, 1, ctypes.c_void_p(1), 8, 1, 1, None, None, None) == -7
+        lib.menkf_destroy(h)
