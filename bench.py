@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--weights", default=None)
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
+    ap.add_argument("--autotune", type=int, default=1, help="autotune the forecast schedules first")
+    ap.add_argument("--workload", default="ns2d_1024_256_n64",
+                    choices=["ns2d_1024_256_n64", "uneven48"],
+                    help="uneven48: the batch of 48 uneven instances in one graph (not the headline)")
+    ap.add_argument("--lanes", type=int, default=4, help="streams of the uneven batch")
     return ap.parse_args()
 
 
@@ -79,6 +84,16 @@ class Cycle:
         self.net = net
         self.seed = cfg.seed + 5
         self.graph = None
+
+    def autotune(self):
+        """Pick the forecast schedules of both levels with the library's autotuner."""
+        import torch
+        self.tuned = {
+            "fine": self.ctx.autotune(self.m.MENKF_FINE, self.fine.clone(), self.cfg.n_obs, reps=3),
+            "coarse": self.ctx.autotune(self.m.MENKF_COARSE, self.members.clone(), self.cfg.n_obs, reps=3),
+        }
+        torch.cuda.synchronize()
+        return self.tuned
 
     def issue(self, stream):
         c, m = self.ctx, self.m
@@ -229,16 +244,20 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
             cyc.ctx.forecast(m.MENKF_COARSE, scratch, cfg.n_obs, stream=stream)
         ev1.record(stream)
     stream.synchronize()
-    launches = reps * cfg.n_obs * 4
+    sc = cyc.ctx.get_schedule(m.MENKF_COARSE)
+    chunk = sc["member_chunk"] or cfg.n_members
+    n_chunks = -(-cfg.n_members // chunk)
+    launches = reps * cfg.n_obs * 4 * n_chunks
     avg_s = ev0.elapsed_time(ev1) / 1e3 / launches
-    pts = cfg.n_members * cfg.nxc * cfg.nyc
+    pts = cfg.n_members * cfg.nxc * cfg.nyc / n_chunks      # points per launch (equal chunks)
     state_bytes = pts * 4 * 4
     # kernel contract: 16 state passes per RK4 step over 4 launches (stage 1: 1R 2W,
     # stages 2-3: 3R 2W, stage 4: 2R 1W) -> 4 passes per launch on average
     contract = 4.0 * state_bytes
     minimum = 2.0 * state_bytes / 4.0      # one read + one write of the state per step
     return {
-        "kernel": "ns_stage<float,32,16,*> (ensemble RK4 stage, 64 x 4 x 256^2)",
+        "kernel": f"ns_stage<float,{sc['tile'][0]},{sc['tile'][1]},*> (ensemble RK4 stage, "
+                  f"{cfg.n_members} x 4 x {cfg.nyc}x{cfg.nxc}, member chunk {sc['member_chunk'] or cfg.n_members})",
         "avg_launch_us": avg_s * 1e6,
         "contract_bytes": contract,
         "min_bytes": minimum,
@@ -297,12 +316,94 @@ def load_net(cfg, path):
     return learned.load(path, guard=10.0), path
 
 
+def bench_batch(args):
+    """48 independent instances of uneven sizes, one batch cycle per graph replay."""
+    import torch
+
+    import paper_2012_10091_amd as m
+    from paper_2012_10091_amd import learned
+    from synthetic import configs, fields
+    cfgs = configs.uneven_batch()
+    net = learned.load(learned.weights_for("ns2d_512_128_n32"), guard=10.0)
+    f32 = torch.float32
+    insts = []
+    t0 = time.perf_counter()
+    for cfg in cfgs:
+        ctx = m.Context(cfg)
+        idx, comp = fields.probes_for(cfg)
+        ctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+        fine = torch.as_tensor(fields.model_ic(cfg), dtype=f32, device="cuda").contiguous()
+        mem = torch.as_tensor(fields.member_ics(cfg), dtype=f32, device="cuda").contiguous()
+        truth = torch.as_tensor(fields.truth_ic(cfg), dtype=f32, device="cuda").contiguous()
+        y = ctx.observe(m.MENKF_FINE, truth)[0] + torch.as_tensor(fields.obs_noise(cfg, 1), device="cuda")
+        xs = torch.empty((4, cfg.nyc, cfg.nxc), dtype=f32, device="cuda")
+        it = {"cfg": cfg, "ctx": ctx, "fine": fine, "prev": torch.empty_like(fine), "members": mem, "xs": xs,
+              "dc": torch.empty_like(xs), "y": y.contiguous()}
+        if args.autotune:
+            ctx.autotune(m.MENKF_FINE, fine.clone(), cfg.n_obs, reps=2)
+            ctx.autotune(m.MENKF_COARSE, mem.clone(), cfg.n_obs, reps=2)
+        insts.append(it)
+    torch.cuda.synchronize()
+    log(f"bench: {len(insts)} instances ready in {time.perf_counter() - t0:.1f}s (autotune {bool(args.autotune)})")
+    init = [(i["fine"].clone(), i["members"].clone()) for i in insts]
+
+    def run(lanes):
+        for i, (f, mm) in zip(insts, init):
+            i["fine"].copy_(f)
+            i["members"].copy_(mm)
+        batch = m.Batch(n_lanes=lanes)
+        stream = torch.cuda.Stream()
+        a = [i["ctx"].cycle_args(i["fine"], i["prev"], i["members"], i["xs"], i["dc"], i["y"], i["cfg"].seed + 5,
+                                 m.MENKF_CYCLE_DEVICE, i["cfg"].n_obs, n_sweeps=0, alpha=0.5,
+                                 mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net) for i in insts]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            m.Graph.begin(stream)
+            batch.cycle(a, stream=stream)
+            g = m.Graph.end(stream)
+        for i in insts:
+            i["ctx"].set_cycle(1, stream=stream)
+        for _ in range(args.warmup):
+            g.launch(stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            g.launch(stream)
+        e1.record(stream)
+        stream.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        bad = [i["cfg"].name for i in insts if i["ctx"].get_status() != 0]
+        return args.steps / sec, bad, batch.lanes()
+
+    cps, bad, lanes = run(args.lanes)
+    log(f"bench: batch on {args.lanes} lanes: {cps:.2f} batch cycles/s, failed instances {bad}")
+    cps1, bad1, _ = run(1)
+    log(f"bench: batch on 1 lane: {cps1:.2f} batch cycles/s")
+    out = {
+        "metric": "uneven-batch assimilation cycles/s (48 independent 2D instances in one graph)",
+        "value": cps, "unit": "batch cycles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 / cps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uneven48", "instances": len(insts),
+                   "fine_sides": sorted({c.nx for c in cfgs}), "members": sorted({c.n_members for c in cfgs}),
+                   "probes_range": [min(c.n_probes for c in cfgs), max(c.n_probes for c in cfgs)],
+                   "lanes": args.lanes, "lane_of": lanes, "instance_cycles_per_s": cps * len(insts),
+                   "one_lane_batch_cycles_per_s": cps1, "autotuned": bool(args.autotune),
+                   "prolongation": "learned with per-tile fallback", "failed_instances": bad + bad1},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU: this build measures the single-GPU hot path "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "uneven48":
+        return bench_batch(args)
     import torch
     import paper_2012_10091_amd as m
     m.load_library()
@@ -312,6 +413,9 @@ def main():
     Y, _ = truth_observations(cfg, n_cyc)
     log("bench: observations ready")
     plain = Cycle(cfg, args.sweeps)
+    tuned = plain.autotune() if args.autotune else None
+    if tuned:
+        log(f"bench: autotuned schedules {tuned}")
     sec, wall = time_cycles(plain, Y, args.warmup, args.steps)
     status = plain.ctx.get_status()
     plain_cps = args.steps / sec
@@ -323,6 +427,9 @@ def main():
     headline = "plain"
     if net is not None and not args.small:
         learned = Cycle(cfg, 0, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
+        if tuned:
+            learned.ctx.set_schedule(m.MENKF_FINE, tuned["fine"]["tile"], tuned["fine"]["member_chunk"])
+            learned.ctx.set_schedule(m.MENKF_COARSE, tuned["coarse"]["tile"], tuned["coarse"]["member_chunk"])
         lsec, _ = time_cycles(learned, Y, args.warmup, args.steps)
         lstatus = learned.ctx.get_status()
         lcps = args.steps / lsec
@@ -358,6 +465,8 @@ def main():
             "workload": cfg.name, "fine": [cfg.ny, cfg.nx], "coarse": [cfg.nyc, cfg.nxc],
             "members": cfg.n_members, "probes": cfg.n_probes, "steps_per_cycle": cfg.n_obs,
             "headline_variant": headline, "status_word": status,
+            "schedules": {k: {"tile": list(v["tile"]), "member_chunk": v["member_chunk"]} for k, v in tuned.items()}
+            if tuned else "default",
             "precision": "FP32 stencils, FP64 innovation covariance/Cholesky/gain of x*, BF16x3 member update",
             "variants": variants,
         },

@@ -163,11 +163,12 @@ menkf_status menkf_get_schedule(const menkf_ctx *ctx, int32_t level, menkf_sched
 
 /* Autotuner of the forecast schedule: times every tile shape of the
  * context's precision against member chunks nb, nb/2, nb/4, ... (coarse
- * level), each as one warm-up and reps timed forecasts of nsteps steps of
- * nb states held in scratch_dev (overwritten: pass a copy of real states,
- * the timing depends only on the shape), with HIP events on stream.  The
- * fastest schedule becomes the level's schedule and is returned in *best
- * with its time per forecast in *best_ms (either may be NULL).  A set-up
+ * level), each as one warm-up and reps individually timed forecasts of
+ * nsteps steps of nb states held in scratch_dev (overwritten: pass a copy
+ * of real states, the timing depends only on the shape), with HIP events on
+ * stream; a schedule scores its fastest repetition.  The fastest schedule
+ * becomes the level's schedule and is returned in *best with its time per
+ * forecast in *best_ms (either may be NULL).  A set-up
  * call: it synchronises the stream and must not be captured into a graph. */
 menkf_status menkf_autotune(menkf_ctx *ctx, int32_t level, void *scratch_dev, int32_t nb, int32_t nsteps,
                             int32_t reps, menkf_schedule *best, float *best_ms, menkf_stream stream);
@@ -314,6 +315,49 @@ menkf_status menkf_residual(menkf_ctx *ctx, const void *x_dev, const void *xprev
 /* Normalised RAM requirement R_RAM = 1 + N_e / r_C^dim of one fine
  * simulation plus N_e coarse members (Sec. 3).  Host only. */
 double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
+
+/* One assimilation cycle of one instance (Algo. 4 steps 2-6 with the
+ * member forecast and analysis of Algo. 3), issued on stream as
+ *   menkf_forecast(FINE, fine, 1, nsteps, fine_prev)
+ *   menkf_forecast(COARSE, members, n_members, nsteps, NULL)
+ *   menkf_restrict(fine, xstar)
+ *   menkf_gain(members, xstar, yobs, seed, cycle, NULL)
+ *   menkf_update(members, deltac)
+ *   menkf_prolong_smooth(deltac, fine, fine_prev, n_sweeps, alpha, prolong_mode, net)
+ * with the contracts of those calls.  All pointers are device buffers owned
+ * by the caller: fine and fine_prev one fine state each, members n_members
+ * coarse states, xstar and deltac one coarse state each, yobs n_probes
+ * doubles (read when the cycle runs, so a captured cycle can be fed new
+ * observations in place).  cycle = MENKF_CYCLE_DEVICE uses the context's
+ * device counter. */
+typedef struct {
+    menkf_ctx *ctx;
+    void *fine, *fine_prev, *members, *xstar, *deltac;
+    const double *yobs;
+    uint64_t seed, cycle;
+    int32_t nsteps, n_sweeps;
+    double alpha;
+    int32_t prolong_mode;
+    const menkf_net *net;
+} menkf_cycle_args;
+
+menkf_status menkf_cycle(const menkf_cycle_args *args, menkf_stream stream);
+
+/* Batch of independent instances of uneven sizes advanced together: a
+ * batch owns n_lanes HIP streams (default priority) and their events.
+ * menkf_batch_cycle forks the lanes from stream, assigns the n instances to
+ * lanes longest-first by an estimated cost (autotuned forecast times when
+ * menkf_autotune has run on the instance, otherwise a model of stencil
+ * points and Cholesky block steps), issues one menkf_cycle per instance on
+ * its lane and joins every lane back into stream.  Capturable: inside a
+ * graph capture of stream the whole batch becomes one graph.  Instances
+ * must not share contexts or buffers.  menkf_batch_lane gives the lane
+ * each instance went to in the last call (lane_of has n entries). */
+typedef struct menkf_batch menkf_batch;
+menkf_status menkf_batch_create(int32_t n_lanes, menkf_batch **out);
+void menkf_batch_destroy(menkf_batch *b);
+menkf_status menkf_batch_cycle(menkf_batch *b, const menkf_cycle_args *inst, int32_t n, menkf_stream stream);
+menkf_status menkf_batch_lanes(const menkf_batch *b, int32_t *lane_of, int32_t n);
 
 /* HIP graph helpers: capture the menkf_* calls issued on stream between
  * begin and end into a graph, then replay it.  The stream must not be the

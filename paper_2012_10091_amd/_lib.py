@@ -64,6 +64,20 @@ class MenkfSchedule(ctypes.Structure):
     _fields_ = [("tile_x", c_int32), ("tile_y", c_int32), ("member_chunk", c_int32), ("reserved", c_int32)]
 
 
+class MenkfCycleArgs(ctypes.Structure):
+    _fields_ = [
+        ("ctx", c_void_p),
+        ("fine", c_void_p), ("fine_prev", c_void_p), ("members", c_void_p),
+        ("xstar", c_void_p), ("deltac", c_void_p),
+        ("yobs", c_void_p),
+        ("seed", c_uint64), ("cycle", c_uint64),
+        ("nsteps", c_int32), ("n_sweeps", c_int32),
+        ("alpha", c_double),
+        ("prolong_mode", c_int32),
+        ("net", ctypes.POINTER(MenkfNet)),
+    ]
+
+
 NET_NPARAM = 12740
 NET_NPACKED = 20736
 
@@ -96,6 +110,11 @@ SIGNATURES = {
     "menkf_diagnostics": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_ram_ratio": (c_double, [c_int32, c_int32, c_int32]),
+    "menkf_cycle": (c_int32, [ctypes.POINTER(MenkfCycleArgs), c_void_p]),
+    "menkf_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p)]),
+    "menkf_batch_destroy": (None, [c_void_p]),
+    "menkf_batch_cycle": (c_int32, [c_void_p, ctypes.POINTER(MenkfCycleArgs), c_int32, c_void_p]),
+    "menkf_batch_lanes": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_int32]),
     "menkf_graph_begin": (c_int32, [c_void_p]),
     "menkf_graph_end": (c_int32, [c_void_p, ctypes.POINTER(c_void_p)]),
     "menkf_graph_launch": (c_int32, [c_void_p, c_void_p]),

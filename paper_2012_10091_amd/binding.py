@@ -229,6 +229,36 @@ class Context:
         self._check(self.lib.menkf_prolong_smooth(self.handle, _ptr(deltac), _ptr(xf), _ptr(xprev), n_sweeps,
                                                   alpha, mode, netp, _stream(stream)))
 
+    def cycle_args(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
+                   n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None):
+        """The menkf_cycle_args of one cycle of this instance (buffers checked here)."""
+        self._state(fine, self.fine_shape, "fine")
+        self._state(fine_prev, self.fine_shape, "fine_prev")
+        self._state(members, self.coarse_shape, "members")
+        if members.shape[0] != self.N:
+            raise ValueError("members must hold n_members states")
+        self._state(xstar, self.coarse_shape, "xstar")
+        self._state(deltac, self.coarse_shape, "deltac")
+        if yobs.dtype != torch.float64 or yobs.numel() != self.Ny or not yobs.is_cuda:
+            raise ValueError("yobs must be a CUDA float64 tensor of n_probes entries")
+        a = _lib.MenkfCycleArgs()
+        a.ctx = self.handle
+        a.fine, a.fine_prev, a.members = _ptr(fine), _ptr(fine_prev), _ptr(members)
+        a.xstar, a.deltac, a.yobs = _ptr(xstar), _ptr(deltac), _ptr(yobs)
+        a.seed, a.cycle = seed, cycle
+        a.nsteps, a.n_sweeps, a.alpha, a.prolong_mode = nsteps, n_sweeps, alpha, mode
+        if net is not None:
+            ns = net if isinstance(net, _lib.MenkfNet) else net.c_struct()
+            a.net = ctypes.pointer(ns)
+            a._keep = ns
+        return a
+
+    def cycle(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
+              n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None, stream=None):
+        a = self.cycle_args(fine, fine_prev, members, xstar, deltac, yobs, seed, cycle, nsteps, n_sweeps, alpha,
+                            mode, net)
+        self._check(self.lib.menkf_cycle(ctypes.byref(a), _stream(stream)))
+
     def get_status(self, clear: bool = True, stream=None) -> int:
         info = ctypes.c_int32()
         st = self.lib.menkf_get_status(self.handle, ctypes.byref(info), int(clear), _stream(stream))
@@ -295,6 +325,44 @@ class Graph:
         try:
             if self.handle:
                 self.lib.menkf_graph_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent instances advanced together on n_lanes streams (menkf_batch_*)."""
+
+    def __init__(self, n_lanes: int = 4):
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        st = self.lib.menkf_batch_create(n_lanes, ctypes.byref(h))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+        self.handle = h
+        self.n_lanes = n_lanes
+        self._n = 0
+
+    def cycle(self, args, stream=None):
+        """Issue one cycle of every instance; args is a list of Context.cycle_args()."""
+        arr = (_lib.MenkfCycleArgs * len(args))(*args)
+        self._arr = (arr, list(args))
+        st = self.lib.menkf_batch_cycle(self.handle, arr, len(args), _stream(stream))
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+        self._n = len(args)
+
+    def lanes(self):
+        out = (ctypes.c_int32 * self._n)()
+        st = self.lib.menkf_batch_lanes(self.handle, out, self._n)
+        if st != 0:
+            raise MenkfError(st, last_error(None))
+        return list(out)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                self.lib.menkf_batch_destroy(self.handle)
                 self.handle = None
         except Exception:
             pass

@@ -90,6 +90,8 @@ struct Plan {
     size_t off_yb, off_a, off_linv, off_z, off_zt, off_zstar, off_scratch;
     size_t ws_bytes;
     menkf_schedule sched[2];   // forecast schedule per level (0 fine, 1 coarse)
+    double tuned_ms[2];        // forecast time of the autotuned schedule (0: not tuned)
+    int tuned_nsteps[2];       // ... and the window it was timed on
 };
 
 constexpr int CHOL_NB = 64;

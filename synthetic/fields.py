@@ -74,19 +74,27 @@ def ns_tgv_primitives(cfg: Config, n_x: int, n_y: int):
 
 
 def _random_modes(rng, n_x: int, n_y: int, length: float, rms: float, kmax: int = 8):
+    """Solenoidal velocity from the streamfunction sum over 1 <= |k| <= kmax of
+    cos(k.x + phase_k) / |k|, random phases, scaled to the given RMS.  Each
+    mode factorises as exp(i kx x) exp(i (ky y + phase)), so the sum is
+    Im(E_y C E_x) with small matrices of complex exponentials."""
     ks = [(kx, ky) for kx in range(-kmax, kmax + 1) for ky in range(0, kmax + 1)
           if (ky > 0 or kx > 0) and 1 <= kx * kx + ky * ky <= kmax * kmax]
-    x = _grid(n_x, length)[None, :] * (2 * math.pi / length)
-    y = _grid(n_y, length)[:, None] * (2 * math.pi / length)
+    x = _grid(n_x, length) * (2 * math.pi / length)
+    y = _grid(n_y, length) * (2 * math.pi / length)
     phases = rng.uniform(0.0, 2 * math.pi, size=len(ks))
-    u = np.zeros((n_y, n_x))
-    v = np.zeros((n_y, n_x))
+    cu = np.zeros((kmax + 1, 2 * kmax + 1), dtype=np.complex128)
+    cv = np.zeros_like(cu)
     for (kx, ky), ph in zip(ks, phases):
         kn = math.hypot(kx, ky)
-        s = np.sin(kx * x + ky * y + ph)
         # streamfunction psi = cos(k.x + ph)/|k|: u = d psi/dy, v = -d psi/dx
-        u += -(ky / kn) * s
-        v += (kx / kn) * s
+        e = np.exp(1j * ph)
+        cu[ky, kx + kmax] += -(ky / kn) * e
+        cv[ky, kx + kmax] += (kx / kn) * e
+    ey = np.exp(1j * np.outer(y, np.arange(kmax + 1)))                 # (n_y, kmax+1)
+    ex = np.exp(1j * np.outer(np.arange(-kmax, kmax + 1), x))          # (2kmax+1, n_x)
+    u = np.imag(ey @ cu @ ex)
+    v = np.imag(ey @ cv @ ex)
     scale = rms / math.sqrt(np.mean(u * u + v * v))
     return u * scale, v * scale
 

@@ -1,0 +1,215 @@
+"""GPU checks of the whole-cycle entry point and of the batch of uneven
+independent instances: menkf_cycle equals the sequence of calls it stands
+for; a batch spread over several streams equals the same cycles issued one
+after another on one stream; its captured graph replays equal eager batches;
+and at the full uneven-batch workload (48 instances, fine 256^2 to 768^2,
+N 16 to 128, 256 to 2048 probes) one instance is followed through the oracle
+and the rest are checked against their own sequential cycles."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cycle as ocycle
+from oracle import enkf, grids, rng, smooth
+from oracle.models import Model
+from synthetic import configs, fields
+from tests.gpu_helpers import make_ctx, rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+F32 = torch.float32
+F64 = torch.float64
+
+
+def _instance(cfg, with_y=True):
+    ctx, idx, comp = make_ctx(cfg)
+    fine = to_dev(fields.model_ic(cfg), F32)
+    mem = to_dev(fields.member_ics(cfg), F32)
+    inst = {"cfg": cfg, "ctx": ctx, "fine": fine, "prev": torch.empty_like(fine), "members": mem,
+            "xs": torch.empty((4, cfg.nyc, cfg.nxc), dtype=F32, device="cuda"),
+            "dc": torch.empty((4, cfg.nyc, cfg.nxc), dtype=F32, device="cuda"),
+            "idx": idx, "comp": comp}
+    if with_y:
+        y = ocycle.observe_truth(cfg, fields.truth_ic(cfg), idx, comp) + fields.obs_noise(cfg, 1)
+        inst["y"] = to_dev(y, F64)
+    return inst
+
+
+def _args(inst, cycle, n_sweeps=3, mode=0, net=None):
+    c = inst["cfg"]
+    return inst["ctx"].cycle_args(inst["fine"], inst["prev"], inst["members"], inst["xs"], inst["dc"], inst["y"],
+                                  c.seed + 5, cycle, c.n_obs, n_sweeps=n_sweeps, alpha=0.5, mode=mode, net=net)
+
+
+def _clone_state(inst):
+    return {"fine": inst["fine"].clone(), "members": inst["members"].clone()}
+
+
+def _set_state(inst, st):
+    inst["fine"].copy_(st["fine"])
+    inst["members"].copy_(st["members"])
+
+
+def _small_uneven():
+    return [configs.tiny_2d(),
+            configs.ragged_2d(),
+            configs.tiny_2d(nx=96, ny=96, n_members=16, n_probes=50, seed=2012 + 31),
+            configs.tiny_2d(nx=128, ny=64, n_members=12, n_probes=30, seed=2012 + 32),
+            configs.tiny_2d(nx=64, ny=128, n_members=5, n_probes=70, seed=2012 + 33)]
+
+
+def _net():
+    import paper_2012_10091_amd as m
+    from paper_2012_10091_amd import learned
+    s, o, sc = learned.default_scaling()
+    return m.Net(learned.init_params(seed=7, last_gain=0.3), s, o, sc, guard=10.0)
+
+
+def test_cycle_equals_the_calls_it_stands_for():
+    cfg = configs.tiny_2d()
+    a, b = _instance(cfg), _instance(cfg)
+    say("menkf_cycle vs separate calls, tiny_2d")
+    for c in (1, 2):
+        a["ctx"].cycle(a["fine"], a["prev"], a["members"], a["xs"], a["dc"], a["y"], cfg.seed + 5, c, cfg.n_obs,
+                       n_sweeps=3)
+        ctx = b["ctx"]
+        ctx.forecast(0, b["fine"], cfg.n_obs, prev=b["prev"])
+        ctx.forecast(1, b["members"], cfg.n_obs)
+        ctx.restrict(b["fine"], b["xs"])
+        ctx.gain(b["members"], b["xs"], b["y"], cfg.seed + 5, c)
+        ctx.update(b["members"], b["dc"])
+        ctx.prolong_smooth(b["dc"], b["fine"], b["prev"], n_sweeps=3, alpha=0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(a["fine"], b["fine"])
+    assert torch.equal(a["members"], b["members"])
+    assert a["ctx"].get_status() == 0
+
+
+def test_batch_on_lanes_equals_sequential_cycles():
+    import paper_2012_10091_amd as m
+    insts = [_instance(c) for c in _small_uneven()]
+    net = _net()
+    modes = [0, 2, 0, 2, 0]
+    init = [_clone_state(i) for i in insts]
+    batch = m.Batch(n_lanes=3)
+    stream = torch.cuda.Stream()
+    say("batch of 5 uneven instances on 3 lanes, 2 cycles")
+    for c in (1, 2):
+        args = [_args(i, c, mode=mo, net=net if mo else None) for i, mo in zip(insts, modes)]
+        batch.cycle(args, stream=stream)
+    stream.synchronize()
+    lanes = batch.lanes()
+    assert sorted(set(lanes)) == [0, 1, 2]
+    got = [_clone_state(i) for i in insts]
+    for i, st in zip(insts, init):
+        _set_state(i, st)
+    say("same cycles one after another on one stream")
+    for c in (1, 2):
+        for i, mo in zip(insts, modes):
+            i["ctx"].cycle(i["fine"], i["prev"], i["members"], i["xs"], i["dc"], i["y"], i["cfg"].seed + 5, c,
+                           i["cfg"].n_obs, n_sweeps=3, alpha=0.5, mode=mo, net=net if mo else None)
+    torch.cuda.synchronize()
+    for i, g in zip(insts, got):
+        assert i["ctx"].get_status() == 0
+        assert torch.equal(i["fine"], g["fine"]), i["cfg"].name
+        assert torch.equal(i["members"], g["members"]), i["cfg"].name
+
+
+def test_batch_graph_replays_equal_eager_batches():
+    import paper_2012_10091_amd as m
+    insts = [_instance(c) for c in _small_uneven()[:4]]
+    init = [_clone_state(i) for i in insts]
+    batch = m.Batch(n_lanes=2)
+    stream = torch.cuda.Stream()
+    args = [_args(i, m.MENKF_CYCLE_DEVICE) for i in insts]
+    say("capture the batch cycle of 4 instances")
+    with torch.cuda.stream(stream):
+        m.Graph.begin(stream)
+        batch.cycle(args, stream=stream)
+        g = m.Graph.end(stream)
+    for i in insts:
+        i["ctx"].set_cycle(1, stream=stream)
+    stream.synchronize()
+    replays = []
+    for rep in range(3):
+        say(f"replay {rep}")
+        g.launch(stream)
+        stream.synchronize()
+        # eager work of the program between replays
+        torch.cuda.synchronize()
+        replays.append([_clone_state(i) for i in insts])
+    for i, st in zip(insts, init):
+        _set_state(i, st)
+        i["ctx"].set_cycle(1)
+    say("eager batches")
+    for rep in range(3):
+        batch.cycle([_args(i, m.MENKF_CYCLE_DEVICE) for i in insts], stream=stream)
+        stream.synchronize()
+        for i, r in zip(insts, replays[rep]):
+            assert torch.equal(i["fine"], r["fine"]), (rep, i["cfg"].name)
+            assert torch.equal(i["members"], r["members"]), (rep, i["cfg"].name)
+
+
+def test_uneven_batch_full_size():
+    import paper_2012_10091_amd as m
+    from paper_2012_10091_amd import learned
+    cfgs = configs.uneven_batch()
+    say(f"uneven batch: {len(cfgs)} instances, building states")
+    insts = [_instance(c) for c in cfgs]
+    net = learned.load(learned.weights_for("ns2d_512_128_n32"), guard=10.0)
+    small = min(range(len(cfgs)), key=lambda k: cfgs[k].nx * cfgs[k].n_members * cfgs[k].n_probes)
+    big = max(range(len(cfgs)), key=lambda k: cfgs[k].nx * cfgs[k].n_members)
+    # the oracle follows the smallest instance with plain prolongation; the
+    # others use the learned prolongation with its per-tile fallback
+    modes = [0 if k == small else m.MENKF_PROLONG_LEARNED_FALLBACK for k in range(len(cfgs))]
+    init = [_clone_state(i) for i in insts]
+    batch = m.Batch(n_lanes=4)
+    stream = torch.cuda.Stream()
+    say("one batch cycle")
+    batch.cycle([_args(i, 1, mode=mo, net=net if mo else None) for i, mo in zip(insts, modes)], stream=stream)
+    stream.synchronize()
+    for i in insts:
+        assert i["ctx"].get_status() == 0, i["cfg"].name
+        assert torch.isfinite(i["fine"]).all() and torch.isfinite(i["members"]).all(), i["cfg"].name
+    got = {k: _clone_state(insts[k]) for k in range(len(cfgs))}
+
+    # every instance: the batch equals its own cycle issued alone
+    for k in sorted({small, big, 0, len(cfgs) - 1}):
+        i = insts[k]
+        _set_state(i, init[k])
+        say(f"sequential cycle of {i['cfg'].name}")
+        a = _args(i, 1, mode=modes[k], net=net if modes[k] else None)
+        i["ctx"].cycle(i["fine"], i["prev"], i["members"], i["xs"], i["dc"], i["y"], i["cfg"].seed + 5, 1,
+                       i["cfg"].n_obs, n_sweeps=3, alpha=0.5, mode=modes[k], net=net if modes[k] else None)
+        torch.cuda.synchronize()
+        assert torch.equal(i["fine"], got[k]["fine"]), i["cfg"].name
+        assert torch.equal(i["members"], got[k]["members"]), i["cfg"].name
+        del a
+
+    # the smallest instance through the oracle: forecast parity, then the
+    # analysis and fine correction from the device forecast
+    i, cfg = insts[small], cfgs[small]
+    say(f"oracle check of {cfg.name}: fine {cfg.nx}^2, N {cfg.n_members}, {cfg.n_probes} probes")
+    fine0 = to_np(init[small]["fine"])
+    mem0 = to_np(init[small]["members"])
+    xf_d, mem_d = init[small]["fine"].clone(), init[small]["members"].clone()
+    prev_d = torch.empty_like(xf_d)
+    i["ctx"].forecast(0, xf_d, cfg.n_obs, prev=prev_d)
+    i["ctx"].forecast(1, mem_d, cfg.n_obs)
+    o_f, o_prev = Model(cfg, "fine").forecast(fine0, cfg.n_obs)
+    o_m, _ = Model(cfg, "coarse").forecast(mem0, cfg.n_obs)
+    assert rel_l2(to_np(xf_d), o_f) < 1e-5
+    assert rel_l2(to_np(mem_d), o_m) < 1e-5
+    xf, xprev, memf = to_np(xf_d), to_np(prev_d), to_np(mem_d)
+    xstar = grids.restrict(xf, cfg.ratio, 2)
+    eps = rng.perturbations(cfg.seed + 5, 1, cfg.n_members, cfg.n_probes, cfg.obs_sigma)
+    res = enkf.analysis(memf, xstar, to_np(i["y"]), eps, ocycle.make_H(cfg, i["idx"], i["comp"]), cfg.obs_sigma)
+    x = xf + grids.prolong(res["delta"], cfg.ratio, 2)
+    x = smooth.smooth(x, xprev, Model(cfg, "fine"), 3, 0.5)
+    # analysed states to the FP32 forecast bound, increments to the BF16x3
+    # analysis bound (members) and the FP32 sweep bound (fine)
+    assert rel_l2(to_np(got[small]["members"]), res["members"]) < 1e-5
+    assert rel_l2(to_np(got[small]["members"]) - memf, res["members"] - memf) < 1e-3
+    assert rel_l2(to_np(got[small]["fine"]), x) < 1e-5
+    assert rel_l2(to_np(got[small]["fine"]) - xf, x - xf) < 1e-2
