@@ -51,6 +51,10 @@ def parse():
                     choices=["ns2d_1024_256_n64", "uneven48"],
                     help="uneven48: the batch of 48 uneven instances in one graph (not the headline)")
     ap.add_argument("--lanes", type=int, default=4, help="streams of the uneven batch")
+    ap.add_argument("--schedule", default=None,
+                    help="fixed forecast schedules instead of autotuning, e.g. fine=64x8:0,coarse=32x8:32")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="for hardware-counter runs: a 1 GiB device copy (calibration) and one eager cycle")
     return ap.parse_args()
 
 
@@ -396,6 +400,53 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def parse_schedule(text):
+    """'fine=64x8:0,coarse=32x8:32' -> {"fine": ((64, 8), 0), "coarse": ((32, 8), 32)}"""
+    out = {}
+    for part in text.split(","):
+        level, spec = part.split("=")
+        tile, chunk = spec.split(":")
+        tx, ty = tile.split("x")
+        out[level.strip()] = ((int(tx), int(ty)), int(chunk))
+    return out
+
+
+def apply_schedule(ctx, sched):
+    import paper_2012_10091_amd as m
+    for level, ((tx, ty), chunk) in sched.items():
+        ctx.set_schedule(m.MENKF_FINE if level == "fine" else m.MENKF_COARSE, (tx, ty), chunk)
+
+
+def traffic_probe(args):
+    """Kernels for hardware-counter passes (FETCH_SIZE / WRITE_SIZE): a plain
+    1 GiB device-to-device copy of known size to calibrate the counters, then
+    one eager (not graph-captured) cycle of the headline workload."""
+    import torch
+
+    import paper_2012_10091_amd as m
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    cfg = make_cfg(args.small)
+    cyc = Cycle(cfg, args.sweeps)
+    if args.schedule:
+        apply_schedule(cyc.ctx, parse_schedule(args.schedule))
+    elif args.autotune:
+        cyc.autotune()
+    stream = torch.cuda.Stream()
+    cyc.ctx.set_cycle(1, stream=stream)
+    with torch.cuda.stream(stream):
+        cyc.issue(stream)
+    stream.synchronize()
+    sc = cyc.ctx.get_schedule(m.MENKF_COARSE)
+    print(json.dumps({"probe": "traffic", "copy_bytes": n * 4, "workload": cfg.name,
+                      "coarse_schedule": sc, "status": cyc.ctx.get_status()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -404,6 +455,8 @@ def main():
         sys.exit(2)
     if args.workload == "uneven48":
         return bench_batch(args)
+    if args.traffic_probe:
+        return traffic_probe(args)
     import torch
     import paper_2012_10091_amd as m
     m.load_library()
@@ -413,7 +466,13 @@ def main():
     Y, _ = truth_observations(cfg, n_cyc)
     log("bench: observations ready")
     plain = Cycle(cfg, args.sweeps)
-    tuned = plain.autotune() if args.autotune else None
+    tuned = None
+    if args.schedule:
+        apply_schedule(plain.ctx, parse_schedule(args.schedule))
+        tuned = {k: plain.ctx.get_schedule(m.MENKF_FINE if k == "fine" else m.MENKF_COARSE)
+                 for k in ("fine", "coarse")}
+    elif args.autotune:
+        tuned = plain.autotune()
     if tuned:
         log(f"bench: autotuned schedules {tuned}")
     sec, wall = time_cycles(plain, Y, args.warmup, args.steps)

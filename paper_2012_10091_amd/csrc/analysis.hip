@@ -242,9 +242,11 @@ __device__ __forceinline__ void chol_diag_block(const double *src, long long lds
     }
     int bad = 0;
     // Pivot step: every thread reads one published value per owned column
-    // (row j of Xw for c <= j, column j of W otherwise); the side of j of
-    // each column group is known at compile time except for one group, and
-    // rows r <= j skip the update.
+    // (row j of Xw for c <= j, column j of W otherwise).  Which of the two a
+    // column group takes is known at compile time except for the group that
+    // holds column j.  Rows r <= j use m = 0.  W is updated above its
+    // diagonal too: those entries are never read, and leaving out the mask
+    // keeps the step free of per-column selects.
 #define MENKF_DIAG_STEP(J)                                                   \
     if (!bad) {                                                              \
         constexpr int b_ = (J) & 1, ji_ = (J) >> 2, jq_ = (J) & 3;           \
@@ -257,22 +259,20 @@ __device__ __forceinline__ void chol_diag_block(const double *src, long long lds
         const double piv = colbuf[b_][J];                                    \
         if (t == 0) dsq[J] = piv;                                            \
         bad = (piv > 0.0) ? 0 : (J) + 1;                                     \
-        if (r > (J)) {                                                       \
-            const double m = colbuf[b_][r] / piv;                            \
-            _Pragma("unroll") for (int i = 0; i < 16; ++i) {                 \
-                const int c = 4 * i + q;                                     \
-                if (4 * i + 3 <= (J)) {          /* whole group left of J */ \
-                    x[i] -= m * rowbuf[b_][c];                               \
-                } else if (4 * i > (J)) {        /* whole group right of J */\
-                    const double nv = w[i] - m * colbuf[b_][c];              \
-                    w[i] = c <= r ? nv : w[i];                               \
-                } else {                         /* the group holding J */   \
-                    const bool lo = c <= (J);                                \
-                    const double v = lo ? rowbuf[b_][c] : colbuf[b_][c];     \
-                    const double nv = (lo ? x[i] : w[i]) - m * v;            \
-                    x[i] = lo ? nv : x[i];                                   \
-                    w[i] = (!lo && c <= r) ? nv : w[i];                      \
-                }                                                            \
+        const double inv = 1.0 / piv;                                        \
+        const double m = r > (J) ? colbuf[b_][r] * inv : 0.0;                \
+        _Pragma("unroll") for (int i = 0; i < 16; ++i) {                     \
+            const int c = 4 * i + q;                                         \
+            if (4 * i + 3 <= (J)) {                                          \
+                x[i] -= m * rowbuf[b_][c];                                   \
+            } else if (4 * i > (J)) {                                        \
+                w[i] -= m * colbuf[b_][c];                                   \
+            } else {                                                         \
+                const bool lo = c <= (J);                                    \
+                const double v = lo ? rowbuf[b_][c] : colbuf[b_][c];         \
+                const double nv = (lo ? x[i] : w[i]) - m * v;                \
+                x[i] = lo ? nv : x[i];                                       \
+                w[i] = lo ? w[i] : nv;                                       \
             }                                                                \
         }                                                                    \
     }

@@ -40,6 +40,10 @@ struct NSCoef {
 
 enum { ST1 = 1, ST2 = 2, ST3 = 3, ST4 = 4, SWEEP = 5, RESID = 6 };
 
+// 1/rho: the hardware reciprocal in FP32 (within 1 ulp), exact division in FP64.
+__device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+
 template <typename T, int TX, int TY, int MODE>
 __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, const T *__restrict__ q0,
                                                 T *__restrict__ acc, T *__restrict__ snext,
@@ -49,8 +53,10 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     constexpr int BX = TX + 8, BY = TY + 8;   // box with halo 4
     constexpr int CX = TX + 4, CY = TY + 4;   // inner box with halo 2
     constexpr int NB = BX * BY, NC = CX * CY;
+    static_assert(BX + BY <= 256, "box coordinate tables are filled by one pass of the workgroup");
     __shared__ T su[NB], sv[NB];
     __shared__ T sm[NC], sn[NC], sEp[NC], sp[NC], sT[NC], sqx[NC], sqy[NC], suy[NC], svx[NC];
+    __shared__ int s_col[BX], s_row[BY];   // periodic global column / row offset of the box
 
     if (MODE == SWEEP && *info != 0) return;   // RESID is a diagnostic: no status gate
 
@@ -66,25 +72,76 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     const T *q_n = q_m + nxy;
     const T *q_E = q_n + nxy;
 
-    // phase 1
-    for (int i = threadIdx.x; i < NB; i += 256) {
-        const int by = i / BX, bx = i - by * BX;
-        const int gx = wrap(tx0 - 4 + bx, nx), gy = wrap(ty0 - 4 + by, ny);
-        const long long g = (long long)gy * nx + gx;
-        const T rho = q_rho[g], m = q_m[g], n = q_n[g];
-        const T ir = T(1) / rho;
-        const T u = m * ir, v = n * ir;
-        su[i] = u;
-        sv[i] = v;
-        if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) {
-            const T E = q_E[g];
-            const T p = c.gm1 * (E - T(0.5) * (m * u + n * v));
-            const int ci = (by - 2) * CX + (bx - 2);
-            sm[ci] = m;
-            sn[ci] = n;
-            sEp[ci] = E + p;
-            sp[ci] = p;
-            sT[ci] = c.tfac * p * ir;
+    // operands of the Runge-Kutta combination at the owned points, fetched
+    // first so that their latency overlaps the stencil phases
+    constexpr int IT3 = (TX * TY + 255) / 256;
+    constexpr int NPRE = (MODE == ST1 || MODE == ST4) ? 1 : 2;
+    T pre[IT3][NPRE][4];
+#pragma unroll
+    for (int k = 0; k < IT3; ++k) {
+        const int i = threadIdx.x + k * 256;
+        const int ty = i / TX, tx = i - ty * TX;
+        const int gx = tx0 + tx, gy = ty0 + ty;
+        if (i < TX * TY && gx < nx && gy < ny) {
+            const long long g = mbase + (long long)gy * nx + gx;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const long long gf = g + f * nxy;
+                if (MODE == ST1) {
+                    pre[k][0][f] = sin_[gf];
+                } else if (MODE == ST4) {
+                    pre[k][0][f] = acc[gf];
+                } else if (MODE == ST2 || MODE == ST3) {
+                    pre[k][0][f] = acc[gf];
+                    pre[k][NPRE - 1][f] = q0[gf];
+                } else {
+                    pre[k][0][f] = sin_[gf];
+                    pre[k][NPRE - 1][f] = q0[gf];
+                }
+            }
+        }
+    }
+
+    // periodic wrap of the box coordinates, once per tile
+    if (threadIdx.x < BX) s_col[threadIdx.x] = wrap(tx0 - 4 + (int)threadIdx.x, nx);
+    else if (threadIdx.x < BX + BY) s_row[threadIdx.x - BX] = wrap(ty0 - 4 + (int)threadIdx.x - BX, ny) * nx;
+    __syncthreads();
+
+    // phase 1: all loads of the box are issued before any is consumed
+    constexpr int IT1 = (NB + 255) / 256;
+    T r_rho[IT1], r_m[IT1], r_n[IT1], r_E[IT1];
+#pragma unroll
+    for (int k = 0; k < IT1; ++k) {
+        const int i = threadIdx.x + k * 256;
+        if (i < NB) {
+            const int by = i / BX, bx = i - by * BX;
+            const int g = s_row[by] + s_col[bx];
+            r_rho[k] = q_rho[g];
+            r_m[k] = q_m[g];
+            r_n[k] = q_n[g];
+            if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) r_E[k] = q_E[g];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < IT1; ++k) {
+        const int i = threadIdx.x + k * 256;
+        if (i < NB) {
+            const int by = i / BX, bx = i - by * BX;
+            const T rho = r_rho[k], m = r_m[k], n = r_n[k];
+            const T ir = recip(rho);
+            const T u = m * ir, v = n * ir;
+            su[i] = u;
+            sv[i] = v;
+            if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) {
+                const T E = r_E[k];
+                const T p = c.gm1 * (E - T(0.5) * (m * u + n * v));
+                const int ci = (by - 2) * CX + (bx - 2);
+                sm[ci] = m;
+                sn[ci] = n;
+                sEp[ci] = E + p;
+                sp[ci] = p;
+                sT[ci] = c.tfac * p * ir;
+            }
         }
     }
     __syncthreads();
@@ -110,10 +167,12 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     __syncthreads();
 
     // phase 3
-    for (int i = threadIdx.x; i < TX * TY; i += 256) {
+#pragma unroll
+    for (int k3 = 0; k3 < IT3; ++k3) {
+        const int i = threadIdx.x + k3 * 256;
         const int ty = i / TX, tx = i - ty * TX;
         const int gx = tx0 + tx, gy = ty0 + ty;
-        if (gx >= nx || gy >= ny) continue;
+        if (i >= TX * TY || gx >= nx || gy >= ny) continue;
         const int ci = (ty + 2) * CX + (tx + 2);
         const int b = (ty + 4) * BX + (tx + 4);
 #define D1X(A) ((A[ci - 2] - T(8) * A[ci - 1] + T(8) * A[ci + 1] - A[ci + 2]) * c.i12hx)
@@ -161,24 +220,23 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const long long gf = g + f * nxy;
+            const T a0 = pre[k3][0][f], a1 = pre[k3][NPRE - 1][f];
             if (MODE == ST1) {
-                const T q = sin_[gf];
-                acc[gf] = q + c.dt * T(1.0 / 6.0) * kk[f];
-                snext[gf] = q + c.dt * T(0.5) * kk[f];
-                if (prev) prev[gf] = q;
+                acc[gf] = a0 + c.dt * T(1.0 / 6.0) * kk[f];
+                snext[gf] = a0 + c.dt * T(0.5) * kk[f];
+                if (prev) prev[gf] = a0;
             } else if (MODE == ST2) {
-                acc[gf] = acc[gf] + c.dt * T(1.0 / 3.0) * kk[f];
-                snext[gf] = q0[gf] + c.dt * T(0.5) * kk[f];
+                acc[gf] = a0 + c.dt * T(1.0 / 3.0) * kk[f];
+                snext[gf] = a1 + c.dt * T(0.5) * kk[f];
             } else if (MODE == ST3) {
-                acc[gf] = acc[gf] + c.dt * T(1.0 / 3.0) * kk[f];
-                snext[gf] = q0[gf] + c.dt * kk[f];
+                acc[gf] = a0 + c.dt * T(1.0 / 3.0) * kk[f];
+                snext[gf] = a1 + c.dt * kk[f];
             } else if (MODE == ST4) {
-                qout[gf] = acc[gf] + c.dt * T(1.0 / 6.0) * kk[f];
+                qout[gf] = a0 + c.dt * T(1.0 / 6.0) * kk[f];
             } else if (MODE == SWEEP) {
-                const T x = sin_[gf];
-                qout[gf] = x + c.w * (q0[gf] + c.dt * kk[f] - x);
+                qout[gf] = a0 + c.w * (a1 + c.dt * kk[f] - a0);
             } else {
-                qout[gf] = q0[gf] + c.dt * kk[f] - sin_[gf];
+                qout[gf] = a1 + c.dt * kk[f] - a0;
             }
         }
     }
