@@ -88,6 +88,7 @@ class Cycle:
         self.net = net
         self.seed = cfg.seed + 5
         self.graph = None
+        self.aux = torch.cuda.Stream()
 
     def autotune(self):
         """Pick the forecast schedules of both levels with the library's autotuner."""
@@ -100,14 +101,10 @@ class Cycle:
         return self.tuned
 
     def issue(self, stream):
-        c, m = self.ctx, self.m
-        c.forecast(m.MENKF_FINE, self.fine, self.cfg.n_obs, prev=self.prev, stream=stream)
-        c.forecast(m.MENKF_COARSE, self.members, self.cfg.n_obs, stream=stream)
-        c.restrict(self.fine, self.xs, stream=stream)
-        c.gain(self.members, self.xs, self.y, self.seed, m.MENKF_CYCLE_DEVICE, stream=stream)
-        c.update(self.members, self.dc, stream=stream)
-        c.prolong_smooth(self.dc, self.fine, self.prev, n_sweeps=self.n_sweeps, alpha=0.5, mode=self.mode,
-                         net=self.net, stream=stream)
+        """One cycle (menkf_cycle); the fine forecast runs on a second stream beside the members'."""
+        self.ctx.cycle(self.fine, self.prev, self.members, self.xs, self.dc, self.y, self.seed,
+                       self.m.MENKF_CYCLE_DEVICE, self.cfg.n_obs, n_sweeps=self.n_sweeps, alpha=0.5, mode=self.mode,
+                       net=self.net, stream=stream, aux_stream=self.aux)
 
     def set_state(self, fine, members):
         self.fine.copy_(fine)

@@ -329,7 +329,10 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  * coarse states, xstar and deltac one coarse state each, yobs n_probes
  * doubles (read when the cycle runs, so a captured cycle can be fed new
  * observations in place).  cycle = MENKF_CYCLE_DEVICE uses the context's
- * device counter. */
+ * device counter.  aux_stream (optional, NULL = none): the fine forecast is
+ * issued there, forked from and joined back into stream with two events
+ * the context owns, so it overlaps the member forecast; results are the
+ * same as without it. */
 typedef struct {
     menkf_ctx *ctx;
     void *fine, *fine_prev, *members, *xstar, *deltac;
@@ -339,6 +342,7 @@ typedef struct {
     double alpha;
     int32_t prolong_mode;
     const menkf_net *net;
+    menkf_stream aux_stream;
 } menkf_cycle_args;
 
 menkf_status menkf_cycle(const menkf_cycle_args *args, menkf_stream stream);

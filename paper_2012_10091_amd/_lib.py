@@ -75,6 +75,7 @@ class MenkfCycleArgs(ctypes.Structure):
         ("alpha", c_double),
         ("prolong_mode", c_int32),
         ("net", ctypes.POINTER(MenkfNet)),
+        ("aux_stream", c_void_p),
     ]
 
 

@@ -230,7 +230,8 @@ class Context:
                                                   alpha, mode, netp, _stream(stream)))
 
     def cycle_args(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
-                   n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None):
+                   n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None,
+                   aux_stream=None):
         """The menkf_cycle_args of one cycle of this instance (buffers checked here)."""
         self._state(fine, self.fine_shape, "fine")
         self._state(fine_prev, self.fine_shape, "fine_prev")
@@ -251,12 +252,15 @@ class Context:
             ns = net if isinstance(net, _lib.MenkfNet) else net.c_struct()
             a.net = ctypes.pointer(ns)
             a._keep = ns
+        if aux_stream is not None:
+            a.aux_stream = aux_stream.cuda_stream
         return a
 
     def cycle(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
-              n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None, stream=None):
+              n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None, stream=None,
+              aux_stream=None):
         a = self.cycle_args(fine, fine_prev, members, xstar, deltac, yobs, seed, cycle, nsteps, n_sweeps, alpha,
-                            mode, net)
+                            mode, net, aux_stream)
         self._check(self.lib.menkf_cycle(ctypes.byref(a), _stream(stream)))
 
     def get_status(self, clear: bool = True, stream=None) -> int:

@@ -20,7 +20,12 @@ struct menkf_ctx {
     size_t ws_bytes = 0;
     const int32_t *idx = nullptr;
     const int32_t *comp = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // menkf_cycle with an aux stream
     char err[512] = {0};
+    ~menkf_ctx() {
+        if (ev_fork) hipEventDestroy(ev_fork);
+        if (ev_join) hipEventDestroy(ev_join);
+    }
 };
 
 struct menkf_batch {
@@ -174,7 +179,10 @@ menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws, size_t bytes) {
                     ctx->plan.ws_bytes);
     ctx->ws = ws;
     ctx->ws_bytes = bytes;
-    hipError_t e = launch_set_word((int32_t *)((char *)ws + ctx->plan.off_info), 0, nullptr);
+    hipError_t e = hipSuccess;
+    if (!ctx->ev_fork) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess && !ctx->ev_join) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = launch_set_word((int32_t *)((char *)ws + ctx->plan.off_info), 0, nullptr);
     if (e == hipSuccess) e = launch_set_word64((uint64_t *)((char *)ws + ctx->plan.off_info + 64), 1, nullptr);
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_set_workspace");
     return MENKF_OK;
@@ -495,8 +503,23 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
     if (!a->fine || !a->fine_prev || !a->members || !a->xstar || !a->deltac || !a->yobs)
         return fail(ctx, MENKF_E_ARG, "menkf_cycle: null buffer");
     if (a->nsteps < 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: nsteps must be >= 1");
-    menkf_status st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, stream);
-    if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, stream);
+    menkf_status st;
+    if (a->aux_stream && a->aux_stream != stream) {
+        hipStream_t s0 = (hipStream_t)stream, s1 = (hipStream_t)a->aux_stream;
+        hipError_t e = hipEventRecord(ctx->ev_fork, s0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
+        st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
+        if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, stream);
+        // join also after a failed issue, so that a capture stays well formed
+        e = hipEventRecord(ctx->ev_join, s1);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s0, ctx->ev_join, 0);
+        if (st != MENKF_OK) return st;
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (join)");
+    } else {
+        st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, stream);
+        if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, stream);
+    }
     if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, stream);
     if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);
     if (st == MENKF_OK) st = menkf_update(ctx, a->members, a->deltac, stream);

@@ -66,13 +66,15 @@ def _net():
     return m.Net(learned.init_params(seed=7, last_gain=0.3), s, o, sc, guard=10.0)
 
 
-def test_cycle_equals_the_calls_it_stands_for():
+@pytest.mark.parametrize("aux", [False, True], ids=["one-stream", "aux-stream"])
+def test_cycle_equals_the_calls_it_stands_for(aux):
     cfg = configs.tiny_2d()
     a, b = _instance(cfg), _instance(cfg)
-    say("menkf_cycle vs separate calls, tiny_2d")
+    side = torch.cuda.Stream() if aux else None
+    say(f"menkf_cycle vs separate calls, tiny_2d, aux stream {aux}")
     for c in (1, 2):
         a["ctx"].cycle(a["fine"], a["prev"], a["members"], a["xs"], a["dc"], a["y"], cfg.seed + 5, c, cfg.n_obs,
-                       n_sweeps=3)
+                       n_sweeps=3, aux_stream=side)
         ctx = b["ctx"]
         ctx.forecast(0, b["fine"], cfg.n_obs, prev=b["prev"])
         ctx.forecast(1, b["members"], cfg.n_obs)
