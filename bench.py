@@ -261,10 +261,32 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
                   f"{cfg.n_members} x 4 x {cfg.nyc}x{cfg.nxc}, member chunk {sc['member_chunk'] or cfg.n_members})",
         "avg_launch_us": avg_s * 1e6,
         "contract_bytes": contract,
+        "traffic": measured_traffic(sc),
         "min_bytes": minimum,
         "achieved": contract / avg_s / 1e9,
         "achieved_min": minimum / avg_s / 1e9,
     }
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ns_stage_64x4x256sq_traffic.md")
+
+
+def measured_traffic(schedule):
+    """HBM bytes per launch of the stage kernel from the committed counter
+    summary, or None when the kernel source or the schedule differs from the
+    one the counters were taken on."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and " " not in line.split(": ")[0])
+    src = os.path.join(ROOT, "paper_2012_10091_amd", "csrc", "ns2d.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    tag = f"{schedule['tile'][0]}x{schedule['tile'][1]}:{schedule['member_chunk']}"
+    if vals.get("kernel_source_sha256") != h or vals.get("profiled_coarse_schedule") != tag:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(cfg):
@@ -532,7 +554,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": rl["achieved"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": rl["traffic"],
             "kernel": rl["kernel"],
             "avg_launch_us": rl["avg_launch_us"],
             "bytes_per_launch": rl["contract_bytes"],

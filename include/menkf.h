@@ -166,9 +166,11 @@ menkf_status menkf_get_schedule(const menkf_ctx *ctx, int32_t level, menkf_sched
  * level), each as one warm-up and reps individually timed forecasts of
  * nsteps steps of nb states held in scratch_dev (overwritten: pass a copy
  * of real states, the timing depends only on the shape), with HIP events on
- * stream; a schedule scores its fastest repetition.  The fastest schedule
- * becomes the level's schedule and is returned in *best with its time per
- * forecast in *best_ms (either may be NULL).  A set-up
+ * stream; a schedule scores its fastest repetition.  The level's current
+ * schedule is timed first and is replaced only by a candidate at least 3 %
+ * faster (so timing noise does not flip it); the winner becomes the
+ * level's schedule and is returned in *best with its time per forecast in
+ * *best_ms (either may be NULL).  A set-up
  * call: it synchronises the stream and must not be captured into a graph. */
 menkf_status menkf_autotune(menkf_ctx *ctx, int32_t level, void *scratch_dev, int32_t nb, int32_t nsteps,
                             int32_t reps, menkf_schedule *best, float *best_ms, menkf_stream stream);
