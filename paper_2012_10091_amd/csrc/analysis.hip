@@ -320,11 +320,20 @@ __device__ __forceinline__ void mfma_nt_64_acc(const double *__restrict__ P, lon
     const int w = tid >> 6, l = tid & 63;
     const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
     for (int k0 = 0; k0 < K; k0 += 64) {
+        // all 32 loads of this thread are issued before the first LDS store
+        double pv[16], qv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int r = (tid >> 6) + 4 * j, c = tid & 63;
+            pv[j] = P[r * ldp + k0 + c];
+            qv[j] = Q[r * ldq + k0 + c];
+        }
         __syncthreads();
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int r = e >> 6, c = e & 63;
-            Ps[r * LDP + c] = P[r * ldp + k0 + c];
-            Qs[r * LDP + c] = Q[r * ldq + k0 + c];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int r = (tid >> 6) + 4 * j, c = tid & 63;
+            Ps[r * LDP + c] = pv[j];
+            Qs[r * LDP + c] = qv[j];
         }
         __syncthreads();
         for (int kk = 0; kk < 64; kk += 4) {
@@ -342,6 +351,21 @@ __device__ __forceinline__ void mfma_nt_64_acc(const double *__restrict__ P, lon
                     acc[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[u], acc[s][u], 0, 0, 0);
         }
     }
+}
+
+// The (row, col) positions of this thread's accumulator entries, in the
+// order for_each_acc visits them.
+template <typename Fn>
+__device__ __forceinline__ void for_each_pos(Fn f) {
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
+    const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) f(r0 + s * 16 + 4 * e + (l >> 4), c0 + u * 16 + (l & 15));
 }
 
 // Visit the accumulator entries: f(row, col, value) within the 64x64 block.
@@ -364,11 +388,23 @@ __device__ __forceinline__ void gemm_nt_64(const double *__restrict__ P, long lo
                                            double sgn, double *Ps, double *Qs, bool lower_only) {
     f64x4 acc[2][2] = {};
     mfma_nt_64_acc(P, ldp, Q, ldq, 64, acc, Ps, Qs);
-    for_each_acc(acc, [&](int r, int c, double v) {
-        if (lower_only && c > r) return;
-        double *dst = C + (long long)r * ldc + c;
-        *dst = (beta != 0.0 ? beta * *dst : 0.0) + sgn * v;
-    });
+    if (beta != 0.0) {
+        // read the 16 old values of this thread before any store
+        double old[16];
+        int n = 0;
+        for_each_pos([&](int r, int c) { old[n++] = (lower_only && c > r) ? 0.0 : C[(long long)r * ldc + c]; });
+        n = 0;
+        for_each_acc(acc, [&](int r, int c, double v) {
+            const double o = old[n++];
+            if (lower_only && c > r) return;
+            C[(long long)r * ldc + c] = beta * o + sgn * v;
+        });
+    } else {
+        for_each_acc(acc, [&](int r, int c, double v) {
+            if (lower_only && c > r) return;
+            C[(long long)r * ldc + c] = sgn * v;
+        });
+    }
 }
 
 // S = Yk Yk^T + R on the lower 64x64 blocks (identity on the padding rows).
@@ -414,15 +450,22 @@ __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int l
     const double *Ljk = A + (long long)(j * 64) * ld + k * 64;
     double *Aij = A + (long long)(i * 64) * ld + j * 64;
     const bool lookahead = blockIdx.x == 0 && k + 1 < nbs;
+    // the 16 entries of A_ij this thread updates, loaded while the MFMA runs
+    double old[16];
+    {
+        int n = 0;
+        for_each_pos([&](int r, int c) { old[n++] = (i == j && c > r) ? 0.0 : Aij[(long long)r * ld + c]; });
+    }
     f64x4 acc[2][2] = {};
     mfma_nt_64_acc(Lik, ld, Ljk, ld, 64, acc, smem_d, smem_d + 64 * LDP);
     __syncthreads();   // the staging buffers are reused below
     double *tile = smem_d;
+    int n = 0;
     for_each_acc(acc, [&](int r, int c, double v) {
+        const double o = old[n++];
         if (i == j && c > r) return;
-        double *dst = Aij + (long long)r * ld + c;
-        const double nv = *dst - v;
-        *dst = nv;
+        const double nv = o - v;
+        Aij[(long long)r * ld + c] = nv;
         if (lookahead) tile[r * LDP + c] = nv;
     });
     if (lookahead) {

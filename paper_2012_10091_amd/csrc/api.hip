@@ -81,8 +81,9 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     p->nyc = p->dim == 2 ? cfg->ny / r : 1;
     if (p->nxc < 4 || (p->dim == 2 && p->nyc < 4))
         return fail(nullptr, MENKF_E_SHAPE, "coarse grid %dx%d too small (cubic prolongation and the stencils need >= 4 nodes per direction)", p->nxc, p->nyc);
-    if (p->dim == 2 && (long long)cfg->nx * cfg->ny >= (1LL << 31))
-        return fail(nullptr, MENKF_E_SHAPE, "fine grid too large for 32-bit node indices");
+    if (p->dim == 2 && 4LL * cfg->nx * cfg->ny * (cfg->precision == MENKF_F64 ? 8 : 4) >= (1LL << 31))
+        return fail(nullptr, MENKF_E_SHAPE, "fine grid too large: one state (4 fields) must stay below 2 GiB "
+                                            "(32-bit byte offsets)");
     p->nf = (long long)p->nx * p->ny;
     p->nc = (long long)p->nxc * p->nyc;
     if (cfg->n_members < 2 || cfg->n_members > 256)

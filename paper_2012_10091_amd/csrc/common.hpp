@@ -33,6 +33,32 @@ __device__ __forceinline__ int wrap(int v, int n) {
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return __float2bfloat16(v); }
 
+// Raw buffer access: a 128-bit resource (base, size in bytes) and 32-bit
+// byte offsets, one in a VGPR and one uniform in an SGPR, so per-element
+// addressing costs one 32-bit multiply-add instead of 64-bit pointer
+// arithmetic.  Accesses outside [0, bytes) read 0 and write nothing.
+typedef __amdgpu_buffer_rsrc_t buf_t;
+__device__ __forceinline__ buf_t buf_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld(buf_t r, int voff, int soff, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double buf_ld(buf_t r, int voff, int soff, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(buf_t r, int voff, int soff) {
+    return buf_ld(r, voff, soff, T());
+}
+__device__ __forceinline__ void buf_store(float v, buf_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(double v, buf_t r, int voff, int soff) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
 // Four-point Lagrange basis on nodes -1, 0, 1, 2 evaluated at s in [0, 1).
 template <typename R>
 __host__ __device__ __forceinline__ void lagrange4(R s, R w[4]) {

@@ -65,12 +65,15 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     const int t = lb - member * tiles_per_member;
     const int ty0 = (t / tiles_x) * TY;
     const int tx0 = (t % tiles_x) * TX;
-    const long long nxy = (long long)nx * ny;
+    // this member's 4 fields of every array as buffer resources; element
+    // (f, y, x) at byte offset ((f nx ny) + y nx + x) * sizeof(T)
+    const int nxy = nx * ny;
     const long long mbase = (long long)member * 4 * nxy;
-    const T *q_rho = sin_ + mbase;
-    const T *q_m = q_rho + nxy;
-    const T *q_n = q_m + nxy;
-    const T *q_E = q_n + nxy;
+    const uint32_t mbytes = 4u * (uint32_t)nxy * sizeof(T);
+    const int fstride = nxy * (int)sizeof(T);   // SGPR offset between fields
+    const buf_t b_in = buf_rsrc(sin_ + mbase, mbytes);
+    const buf_t b_q0 = buf_rsrc(q0 ? q0 + mbase : sin_, mbytes);
+    const buf_t b_acc = buf_rsrc(acc ? acc + mbase : sin_, mbytes);
 
     // operands of the Runge-Kutta combination at the owned points, fetched
     // first so that their latency overlaps the stencil phases
@@ -83,20 +86,19 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         const int ty = i / TX, tx = i - ty * TX;
         const int gx = tx0 + tx, gy = ty0 + ty;
         if (i < TX * TY && gx < nx && gy < ny) {
-            const long long g = mbase + (long long)gy * nx + gx;
+            const int vo = (gy * nx + gx) * (int)sizeof(T);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                const long long gf = g + f * nxy;
                 if (MODE == ST1) {
-                    pre[k][0][f] = sin_[gf];
+                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);
                 } else if (MODE == ST4) {
-                    pre[k][0][f] = acc[gf];
+                    pre[k][0][f] = buf_load<T>(b_acc, vo, f * fstride);
                 } else if (MODE == ST2 || MODE == ST3) {
-                    pre[k][0][f] = acc[gf];
-                    pre[k][NPRE - 1][f] = q0[gf];
+                    pre[k][0][f] = buf_load<T>(b_acc, vo, f * fstride);
+                    pre[k][NPRE - 1][f] = buf_load<T>(b_q0, vo, f * fstride);
                 } else {
-                    pre[k][0][f] = sin_[gf];
-                    pre[k][NPRE - 1][f] = q0[gf];
+                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);
+                    pre[k][NPRE - 1][f] = buf_load<T>(b_q0, vo, f * fstride);
                 }
             }
         }
@@ -115,11 +117,11 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         const int i = threadIdx.x + k * 256;
         if (i < NB) {
             const int by = i / BX, bx = i - by * BX;
-            const int g = s_row[by] + s_col[bx];
-            r_rho[k] = q_rho[g];
-            r_m[k] = q_m[g];
-            r_n[k] = q_n[g];
-            if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) r_E[k] = q_E[g];
+            const int vo = (s_row[by] + s_col[bx]) * (int)sizeof(T);
+            r_rho[k] = buf_load<T>(b_in, vo, 0);
+            r_m[k] = buf_load<T>(b_in, vo, fstride);
+            r_n[k] = buf_load<T>(b_in, vo, 2 * fstride);
+            if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) r_E[k] = buf_load<T>(b_in, vo, 3 * fstride);
         }
     }
 #pragma unroll
@@ -216,27 +218,30 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
 #undef D2XC
 #undef D2YC
         const T kk[4] = {k_rho, k_m, k_n, k_E};
-        const long long g = mbase + (long long)gy * nx + gx;
+        const int vo = (gy * nx + gx) * (int)sizeof(T);
+        const buf_t b_next = buf_rsrc(snext ? snext + mbase : sin_, mbytes);
+        const buf_t b_out = buf_rsrc(qout ? qout + mbase : sin_, mbytes);
+        const buf_t b_prev = buf_rsrc(prev ? prev + mbase : sin_, mbytes);
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const long long gf = g + f * nxy;
+            const int so = f * fstride;
             const T a0 = pre[k3][0][f], a1 = pre[k3][NPRE - 1][f];
             if (MODE == ST1) {
-                acc[gf] = a0 + c.dt * T(1.0 / 6.0) * kk[f];
-                snext[gf] = a0 + c.dt * T(0.5) * kk[f];
-                if (prev) prev[gf] = a0;
+                buf_store(a0 + c.dt * T(1.0 / 6.0) * kk[f], b_acc, vo, so);
+                buf_store(a0 + c.dt * T(0.5) * kk[f], b_next, vo, so);
+                if (prev) buf_store(a0, b_prev, vo, so);
             } else if (MODE == ST2) {
-                acc[gf] = a0 + c.dt * T(1.0 / 3.0) * kk[f];
-                snext[gf] = a1 + c.dt * T(0.5) * kk[f];
+                buf_store(a0 + c.dt * T(1.0 / 3.0) * kk[f], b_acc, vo, so);
+                buf_store(a1 + c.dt * T(0.5) * kk[f], b_next, vo, so);
             } else if (MODE == ST3) {
-                acc[gf] = a0 + c.dt * T(1.0 / 3.0) * kk[f];
-                snext[gf] = a1 + c.dt * kk[f];
+                buf_store(a0 + c.dt * T(1.0 / 3.0) * kk[f], b_acc, vo, so);
+                buf_store(a1 + c.dt * kk[f], b_next, vo, so);
             } else if (MODE == ST4) {
-                qout[gf] = a0 + c.dt * T(1.0 / 6.0) * kk[f];
+                buf_store(a0 + c.dt * T(1.0 / 6.0) * kk[f], b_out, vo, so);
             } else if (MODE == SWEEP) {
-                qout[gf] = a0 + c.w * (a1 + c.dt * kk[f] - a0);
+                buf_store(a0 + c.w * (a1 + c.dt * kk[f] - a0), b_out, vo, so);
             } else {
-                qout[gf] = a1 + c.dt * kk[f] - a0;
+                buf_store(a1 + c.dt * kk[f] - a0, b_out, vo, so);
             }
         }
     }
