@@ -146,27 +146,43 @@ __global__ __launch_bounds__(256) void obs_pack(const double *__restrict__ yraw,
                                                 uint64_t seed, uint64_t cycle, const uint64_t *__restrict__ dcycle,
                                                 double sigma, int sample_mode, double *__restrict__ Yk, int kdim,
                                                 double *__restrict__ A, int ld) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nyp) return;
+    // 16 probes per workgroup, the members of a probe split over 16 lanes
+    // (member i goes to group i % 16); the member means are reduced in a
+    // fixed order through LDS.
+    __shared__ double red[2][16][16];
+    const int pl = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int p = blockIdx.x * 16 + pl;
     if (dcycle) cycle = *dcycle;
+    const bool live = p < Ny;
+    double ys = 0.0, es = 0.0;
+    if (live) {
+        for (int i = g; i < N; i += 16) {
+            ys += yraw[(long long)i * ldy + p];
+            if (sample_mode) es += eps ? eps[(long long)i * Ny + p] : sigma * perturb_normal(seed, cycle, i, p);
+        }
+    }
+    red[0][g][pl] = ys;
+    red[1][g][pl] = es;
+    __syncthreads();
+    double ybar = 0.0, ebar = 0.0;
+#pragma unroll
+    for (int gg = 0; gg < 16; ++gg) {
+        ybar += red[0][gg][pl];
+        ebar += red[1][gg][pl];
+    }
+    ybar /= (double)N;
+    ebar /= (double)N;
+    if (p >= nyp) return;
     double *yk = Yk + (long long)p * kdim;
     double *B = A + (long long)nyp * ld + p;
-    if (p >= Ny) {
-        for (int k = 0; k < kdim; ++k) yk[k] = 0.0;
-        for (int j = 0; j <= 2 * N; ++j) B[(long long)j * ld] = 0.0;
+    if (!live) {   // padding probe
+        for (int k = g; k < kdim; k += 16) yk[k] = 0.0;
+        for (int j = g; j <= 2 * N; j += 16) B[(long long)j * ld] = 0.0;
         return;
     }
     const double scale = 1.0 / sqrt((double)(N - 1));
-    double ybar = 0.0, ebar = 0.0;
-    for (int i = 0; i < N; ++i) ybar += yraw[(long long)i * ldy + p];
-    ybar /= (double)N;
-    if (sample_mode) {
-        for (int i = 0; i < N; ++i)
-            ebar += eps ? eps[(long long)i * Ny + p] : sigma * perturb_normal(seed, cycle, i, p);
-        ebar /= (double)N;
-    }
     const double yo = yobs[p];
-    for (int i = 0; i < N; ++i) {
+    for (int i = g; i < N; i += 16) {
         const double yi = yraw[(long long)i * ldy + p];
         const double e = eps ? eps[(long long)i * Ny + p] : sigma * perturb_normal(seed, cycle, i, p);
         const double an = (yi - ybar) * scale;
@@ -175,8 +191,8 @@ __global__ __launch_bounds__(256) void obs_pack(const double *__restrict__ yraw,
         B[(long long)(N + 1 + i) * ld] = an;
         if (sample_mode) yk[N + i] = (e - ebar) * scale;
     }
-    for (int k = sample_mode ? 2 * N : N; k < kdim; ++k) yk[k] = 0.0;
-    B[(long long)N * ld] = yo - yraw[(long long)N * ldy + p];
+    for (int k = (sample_mode ? 2 * N : N) + g; k < kdim; k += 16) yk[k] = 0.0;
+    if (g == 0) B[(long long)N * ld] = yo - yraw[(long long)N * ldy + p];
 }
 
 // Zero the trailing (Schur) block and the padding rows of the extra block,
@@ -667,7 +683,7 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     hipLaunchKernelGGL(zero_extra, dim3(256), dim3(256), 0, s, A, p.ld, p.nyp, p.mext, info);
     // 3. anomalies, innovations, perturbations (FP64)
     uint64_t *dcycle = cycle == MENKF_CYCLE_DEVICE ? (uint64_t *)(w + p.off_info + 64) : nullptr;
-    hipLaunchKernelGGL(obs_pack, dim3((p.nyp + 255) / 256), dim3(256), 0, s, yraw, p.nyp, N, p.Ny, p.nyp, yobs, eps,
+    hipLaunchKernelGGL(obs_pack, dim3((p.nyp + 15) / 16), dim3(256), 0, s, yraw, p.nyp, N, p.Ny, p.nyp, yobs, eps,
                        seed, cycle, (const uint64_t *)dcycle, p.cfg.obs_sigma, sample, Yk, p.kdim, A, p.ld);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 4. S = Y Y^T + R (+ identity on the padding), FP64 MFMA

@@ -39,6 +39,47 @@ __global__ __launch_bounds__(256) void prolong_add(const T *__restrict__ dc, con
     xout[i] = xin[i] + prolong_at<T>(dc + (long long)f * nxc * nyc, nxc, nyc, r, y, x);
 }
 
+// 2D form: one fine row of one field per grid row (y = blockIdx.y, field =
+// blockIdx.z), so the coarse rows and y-weights are uniform per workgroup
+// and the x-weights come from an LDS table of the r sub-positions.  Same
+// weights and summation order as prolong_at.
+template <typename T>
+__global__ __launch_bounds__(256) void prolong_add_rows(const T *__restrict__ dc, const T *__restrict__ xin,
+                                                        T *__restrict__ xout, int nx, int ny, int r, int nxc,
+                                                        int nyc, const int32_t *__restrict__ info) {
+    __shared__ T wxs[64][4];
+    if (*info != 0) return;
+    const int y = blockIdx.y, f = blockIdx.z;
+    if ((int)threadIdx.x < r) lagrange4<T>(T(threadIdx.x) / T(r), wxs[threadIdx.x]);
+    __syncthreads();
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= nx) return;
+    const int jy = y / r, my = y - jy * r;
+    T wy[4];
+    lagrange4<T>(T(my) / T(r), wy);
+    const T *d = dc + (long long)f * nxc * nyc;
+    const int jx = x / r, mx = x - jx * r;
+    int cx[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        int v = jx - 1 + b;
+        v += v < 0 ? nxc : 0;
+        v -= v >= nxc ? nxc : 0;
+        cx[b] = v;
+    }
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const T *row = d + (long long)wrap(jy - 1 + a, nyc) * nxc;
+        T sa = T(0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sa += wxs[mx][b] * row[cx[b]];
+        acc += wy[a] * sa;
+    }
+    const long long g = ((long long)f * ny + y) * nx + x;
+    xout[g] = xin[g] + acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void copy_guarded(const T *__restrict__ src, T *__restrict__ dst, long long n,
                                                     const int32_t *__restrict__ info) {
@@ -61,6 +102,16 @@ hipError_t launch_restrict(const Plan &p, const void *xf, void *xc, hipStream_t 
 
 hipError_t launch_prolong_add(const Plan &p, const void *dc, const void *xin, void *xout, const int32_t *info,
                               hipStream_t s) {
+    if (p.dim == 2 && p.ny <= 65535 && p.cfg.ratio <= 64) {
+        const dim3 grid((p.nx + 255) / 256, p.ny, p.F);
+        if (p.cfg.precision == MENKF_F64)
+            hipLaunchKernelGGL(prolong_add_rows<double>, grid, dim3(256), 0, s, (const double *)dc,
+                               (const double *)xin, (double *)xout, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, info);
+        else
+            hipLaunchKernelGGL(prolong_add_rows<float>, grid, dim3(256), 0, s, (const float *)dc,
+                               (const float *)xin, (float *)xout, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, info);
+        return hipGetLastError();
+    }
     const long long n = p.nf * p.F;
     const int blocks = (int)((n + 255) / 256);
     if (p.cfg.precision == MENKF_F64)

@@ -119,21 +119,53 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
     __shared__ float dps[4][NP3];
     __shared__ float outb[4][NP3];
     __shared__ float red[3][256];
+    // coarse window of delta^C under the tile + halo 3 (unwrapped coarse
+    // origin cx0, cy0; at most CWMAX points per side for r >= 1) and the
+    // Lagrange weights of the r sub-positions
+    // the window lives in the act2 buffer, which the loader does not use
+    constexpr int CWMAX = 26;   // R0 / r + 5 <= 25 for r >= 1
+    static_assert(4 * CWMAX * CWMAX * sizeof(float) <= sizeof(__bf16) * NP2 * 32, "window fits in act2");
+    float (*cwin)[CWMAX][CWMAX] = reinterpret_cast<float (*)[CWMAX][CWMAX]>(act2);
+    __shared__ float wts[64][4];
+    __shared__ int s_fx[R0], s_fy[R0];   // periodic fine column / row offset
     if (*info != 0) return;
     const int lb = xcd_remap(blockIdx.x, total_tiles);
     const int y0 = (lb / tiles_x) * NT, x0 = (lb % tiles_x) * NT;
     const long long nf = (long long)nx * ny;
     const long long ncp = (long long)nxc * nyc;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    // floor division for the (possibly negative) unwrapped coordinates
+    auto fdiv = [](int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    const int cx0 = fdiv(x0 - 3, r) - 1, cy0 = fdiv(y0 - 3, r) - 1;
+    const int cwx = fdiv(x0 + NT + 2, r) + 3 - cx0, cwy = fdiv(y0 + NT + 2, r) + 3 - cy0;   // <= 25
+    if (tid < r) lagrange4<float>(float(tid) / float(r), wts[tid]);
+    if (tid < R0) s_fx[tid] = wrap(x0 - 3 + tid, nx);
+    else if (tid >= 64 && tid < 64 + R0) s_fy[tid - 64] = wrap(y0 - 3 + tid - 64, ny) * nx;
+    for (int e = tid; e < 4 * cwx * cwy; e += 256) {
+        const int f = e / (cwx * cwy), rem = e - f * cwx * cwy, wy = rem / cwx, wx = rem - wy * cwx;
+        cwin[f][wy][wx] = dc[f * ncp + (long long)wrap(cy0 + wy, nyc) * nxc + wrap(cx0 + wx, nxc)];
+    }
+    __syncthreads();
 
     for (int p = tid; p < NP0; p += 256) {
         const int py = p / R0, px = p - py * R0;
-        const int gy = wrap(y0 - 3 + py, ny), gx = wrap(x0 - 3 + px, nx);
-        const long long g = (long long)gy * nx + gx;
+        const long long g = (long long)s_fy[py] + s_fx[px];
+        // sub-positions and window columns of the 4-point stencils
+        const int X = x0 - 3 + px, Y = y0 - 3 + py;
+        const int jx = fdiv(X, r), jy = fdiv(Y, r);
+        const float *wx = wts[X - jx * r], *wy = wts[Y - jy * r];
+        const int bx = jx - 1 - cx0, by = jy - 1 - cy0;
         __bf16 v[8];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const float d = prolong_at<float>(dc + f * ncp, nxc, nyc, r, gy, gx);
+            float d = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                float sa = 0.0f;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) sa += wx[b] * cwin[f][by + a][bx + b];
+                d += wy[a] * sa;
+            }
             const float xv = xf[f * nf + g];
             v[f] = (__bf16)((d - nc.in_offset[f]) * nc.in_scale[f]);
             v[4 + f] = (__bf16)((xv - nc.in_offset[4 + f]) * nc.in_scale[4 + f]);
