@@ -419,6 +419,16 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def with_gain_mode(cfg, mode):
+    """The workload configuration with another menkf gain mode."""
+    import dataclasses
+
+    @dataclasses.dataclass(frozen=True)
+    class C(type(cfg)):
+        gain_mode: int = mode
+    return C(**dataclasses.asdict(cfg))
+
+
 def parse_schedule(text):
     """'fine=64x8:0,coarse=32x8:32' -> {"fine": ((64, 8), 0), "coarse": ((32, 8), 32)}"""
     out = {}
@@ -522,6 +532,20 @@ def main():
         variants["rmse"] = cmp
         if cmp["equal_rmse"] and lstatus == 0:
             value, ms, headline = lcps, lsec / args.steps * 1e3, "learned"
+        # the same cycle with the ensemble-space form of the gain (an exact
+        # identity for R = s^2 I; not the headline, which keeps the N_y x N_y
+        # FP64 Cholesky of the workload)
+        ens = Cycle(with_gain_mode(cfg, m.MENKF_GAIN_ENSEMBLE_SPACE), 0, mode=m.MENKF_PROLONG_LEARNED_FALLBACK,
+                    net=net)
+        if tuned:
+            ens.ctx.set_schedule(m.MENKF_FINE, tuned["fine"]["tile"], tuned["fine"]["member_chunk"])
+            ens.ctx.set_schedule(m.MENKF_COARSE, tuned["coarse"]["tile"], tuned["coarse"]["member_chunk"])
+        esec, _ = time_cycles(ens, Y, args.warmup, args.steps)
+        ecps = args.steps / esec
+        log(f"bench: learned + ensemble-space gain {ecps:.2f} cycles/s, status {ens.ctx.get_status()}")
+        variants["learned_ensemble_space_gain"] = {
+            "cycles_per_s": ecps, "ms_per_cycle": esec / args.steps * 1e3,
+            "gain": "(s^2 I + Y^T Y)^-1 Y^T [D | d*], N x N FP64 Cholesky (exact identity; not the headline)"}
     elif net is None:
         log(f"bench: no trained weights at {wpath}; learned variant not timed")
     rl = stage_kernel_roofline(cfg, plain)

@@ -64,7 +64,7 @@ typedef enum {
 
 enum { MENKF_BURGERS1D = 1, MENKF_NS2D = 2 };          /* model */
 enum { MENKF_F32 = 0, MENKF_F64 = 1 };                 /* precision */
-enum { MENKF_GAIN_EXACT_R = 0, MENKF_GAIN_SAMPLE_EE = 1 };
+enum { MENKF_GAIN_EXACT_R = 0, MENKF_GAIN_SAMPLE_EE = 1, MENKF_GAIN_ENSEMBLE_SPACE = 2 };
 enum { MENKF_FINE = 0, MENKF_COARSE = 1 };             /* grid level */
 enum { MENKF_PROLONG_PLAIN = 0, MENKF_PROLONG_LEARNED = 1, MENKF_PROLONG_LEARNED_FALLBACK = 2 };
 
@@ -83,6 +83,10 @@ enum { MENKF_PROLONG_PLAIN = 0, MENKF_PROLONG_LEARNED = 1, MENKF_PROLONG_LEARNED
  *   gain_mode  MENKF_GAIN_EXACT_R: S = Y Y^T + obs_sigma^2 I.
  *              MENKF_GAIN_SAMPLE_EE: S = Y Y^T + E E^T (Algo. 1 step 6 as
  *              printed; singular when n_probes > 2 n_members - 2).
+ *              MENKF_GAIN_ENSEMBLE_SPACE: the same gain as EXACT_R through
+ *              the identity Y^T (Y Y^T + s^2 I)^-1 = (s^2 I + Y^T Y)^-1 Y^T
+ *              (s = obs_sigma): Z = (s^2 I + Y^T Y)^-1 Y^T [D | d*], an
+ *              N_e x N_e FP64 Cholesky instead of the N_y x N_y one.
  *   nx, ny     fine grid points (ny = 1 for the 1D model); ratio = coarsening
  *              ratio r_C per direction, must divide nx (and ny in 2D).
  *   n_members  ensemble size 2 <= N_e <= 256 (anomalies scaled by 1/sqrt(N_e - 1)).

@@ -20,6 +20,7 @@ MENKF_F32 = 0
 MENKF_F64 = 1
 MENKF_GAIN_EXACT_R = 0
 MENKF_GAIN_SAMPLE_EE = 1
+MENKF_GAIN_ENSEMBLE_SPACE = 2
 MENKF_FINE = 0
 MENKF_COARSE = 1
 MENKF_PROLONG_PLAIN = 0

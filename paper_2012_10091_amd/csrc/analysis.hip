@@ -490,6 +490,50 @@ __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int l
     }
 }
 
+// ----------------------------------------------------------------- ensemble-space gain
+// Gram of the extra rows E = [D; d*; Y] (mextp x nyp, rows of A from nyp):
+// P = E E^T, lower 64 x 64 tiles, FP64 MFMA over the whole probe range.
+__global__ __launch_bounds__(256) void gram_extra(const double *__restrict__ A, int ld, int nyp, int mextp,
+                                                  double *__restrict__ P) {
+    extern __shared__ double smem_d[];
+    int bi, bj;
+    tri_index(blockIdx.x, bi, bj);
+    const double *E = A + (long long)nyp * ld;
+    f64x4 acc[2][2] = {};
+    mfma_nt_64_acc(E + (long long)(bi * 64) * ld, ld, E + (long long)(bj * 64) * ld, ld, nyp, acc, smem_d,
+                   smem_d + 64 * LDP);
+    for_each_acc(acc, [&](int r, int c, double v) { P[(long long)(bi * 64 + r) * mextp + bj * 64 + c] = v; });
+}
+
+// The small augmented system of the ensemble-space gain, lds x lds with
+// the first npm columns to be factored:
+//   [ s^2 I + Y^T Y    .  ]   rows 0 .. npm-1 (identity on the padding)
+//   [ (Y^T B)^T        0  ]   rows npm + j, j = 0..N (B_j = D_j, B_N = d*)
+//   [ I_N              0  ]   rows npm + N + 1 + i
+// Its factorisation leaves -(Y^T B)^T ... and, in the identity rows of the
+// Schur block, -(s^2 I + Y^T Y)^-1 Y^T B = -Z: the layout the gain
+// extraction reads for the N_y x N_y form.  Only the lower triangle and the
+// extra rows are written.
+__global__ __launch_bounds__(256) void ens_assemble(const double *__restrict__ P, int mextp, int N, int npm, int lds,
+                                                    double s2, double *__restrict__ As) {
+    const long long tot = (long long)lds * lds;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(t / lds), b = (int)(t - (long long)a * lds);
+        if (b > a) continue;
+        double v = 0.0;
+        if (a < npm) {
+            if (a < N && b < N) v = P[(long long)(N + 1 + a) * mextp + N + 1 + b] + (a == b ? s2 : 0.0);
+            else v = a == b ? 1.0 : 0.0;
+        } else if (b < npm) {
+            const int e = a - npm;
+            if (b < N && e <= N) v = P[(long long)(N + 1 + b) * mextp + e];
+            else if (e >= N + 1 && e <= 2 * N) v = (b == e - N - 1) ? 1.0 : 0.0;
+        }
+        As[t] = v;
+    }
+}
+
 // ----------------------------------------------------------------- Z from the Schur block
 // Z[i][j] = -M[N+1+i][j] with M the trailing block (rows/cols from nyp).
 // z64[j][i] = Z[i][j]; zstar[i] = Z[i][N]; zt holds Z^T for the member
@@ -649,6 +693,41 @@ hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, d
     return hipGetLastError();
 }
 
+// Blocked Cholesky of the first nbs * 64 columns of the ld x ld matrix M
+// (lower triangle, row-major), Schur complement on the remaining rows.
+static hipError_t chol_blocked(double *A, int ld, int nbs, double *Linv, int32_t *info, size_t lds, hipStream_t s) {
+    hipError_t e;
+    const int nblk = ld / CHOL_NB;
+    hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, ld, 0, Linv, info);
+    for (int k = 0; k < nbs; ++k) {
+        const int below = nblk - k - 1;
+        if (below > 0) {
+            hipLaunchKernelGGL(chol_panel, dim3(below), dim3(256), lds, s, A, ld, k, (const double *)Linv, info);
+            hipLaunchKernelGGL(chol_update, dim3(below * (below + 1) / 2), dim3(256), lds, s, A, ld, k, nbs, Linv,
+                               info);
+        } else if (k + 1 < nbs) {
+            hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, ld, k + 1, Linv, info);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Z (and its BF16 pair for the member update) from the Schur block of the
+// factored augmented matrix M (ld, first n0 columns factored).
+static hipError_t extract_gain(const Plan &p, const double *M, int ld, int n0, char *w, uint64_t *dcycle,
+                               hipStream_t s) {
+    const int N = p.N;
+    const int ge = (p.npad * p.npad + 255) / 256;
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(gain_extract<double>, dim3(ge), dim3(256), 0, s, M, ld, n0, N, p.npad,
+                           (double *)(w + p.off_z), (double *)(w + p.off_zt), (double *)(w + p.off_zstar), dcycle);
+    else
+        hipLaunchKernelGGL(gain_extract<__bf16>, dim3(ge), dim3(256), 0, s, M, ld, n0, N, p.npad,
+                           (double *)(w + p.off_z), (__bf16 *)(w + p.off_zt), (double *)(w + p.off_zstar), dcycle);
+    return hipGetLastError();
+}
+
 hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, const double *yobs, uint64_t seed,
                        uint64_t cycle, const double *eps, const int32_t *idx, const int32_t *comp, void *ws,
                        hipStream_t s) {
@@ -686,36 +765,31 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     hipLaunchKernelGGL(obs_pack, dim3((p.nyp + 15) / 16), dim3(256), 0, s, yraw, p.nyp, N, p.Ny, p.nyp, yobs, eps,
                        seed, cycle, (const uint64_t *)dcycle, p.cfg.obs_sigma, sample, Yk, p.kdim, A, p.ld);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (p.cfg.gain_mode == MENKF_GAIN_ENSEMBLE_SPACE) {
+        // 4'. P = E E^T of the extra rows, then the N_e x N_e system
+        double *P = (double *)(w + p.off_p), *As = (double *)(w + p.off_as);
+        const int mb = p.mextp / CHOL_NB;
+        if ((e = set_lds((const void *)gram_extra, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(gram_extra, dim3(mb * (mb + 1) / 2), dim3(256), lds, s, (const double *)A, p.ld, p.nyp,
+                           p.mextp, P);
+        hipLaunchKernelGGL(ens_assemble, dim3(256), dim3(256), 0, s, (const double *)P, p.mextp, N, p.npm, p.lds,
+                           p.cfg.obs_sigma * p.cfg.obs_sigma, As);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = chol_blocked(As, p.lds, p.npm / CHOL_NB, Linv, info, lds, s)) != hipSuccess) return e;
+        return extract_gain(p, As, p.lds, p.npm, w, dcycle, s);
+    }
     // 4. S = Y Y^T + R (+ identity on the padding), FP64 MFMA
     const int nbs = p.nyp / CHOL_NB;
     hipLaunchKernelGGL(syrk_f64_mfma, dim3(nbs * (nbs + 1) / 2), dim3(256), lds, s, (const double *)Yk, p.kdim, p.Ny,
                        sample ? 0.0 : rdiag, A, p.ld);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 5. blocked Cholesky of the first nyp columns, Schur complement on the rest
-    const int nblk = p.ld / CHOL_NB;
-    hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, p.ld, 0, Linv, info);
-    for (int k = 0; k < nbs; ++k) {
-        const int below = nblk - k - 1;
-        if (below > 0) {
-            hipLaunchKernelGGL(chol_panel, dim3(below), dim3(256), lds, s, A, p.ld, k, (const double *)Linv, info);
-            hipLaunchKernelGGL(chol_update, dim3(below * (below + 1) / 2), dim3(256), lds, s, A, p.ld, k, nbs, Linv,
-                               info);
-        } else if (k + 1 < nbs) {
-            hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, p.ld, k + 1, Linv, info);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    if ((e = chol_blocked(A, p.ld, nbs, Linv, info, lds, s)) != hipSuccess) return e;
     // 6. Z
-    const int ge = (p.npad * p.npad + 255) / 256;
-    if (f64)
-        hipLaunchKernelGGL(gain_extract<double>, dim3(ge), dim3(256), 0, s, (const double *)A, p.ld, p.nyp, N, p.npad,
-                           (double *)(w + p.off_z), (double *)(w + p.off_zt), (double *)(w + p.off_zstar), dcycle);
-    else
-        hipLaunchKernelGGL(gain_extract<__bf16>, dim3(ge), dim3(256), 0, s, (const double *)A, p.ld, p.nyp, N,
-                           p.npad, (double *)(w + p.off_z), (__bf16 *)(w + p.off_zt), (double *)(w + p.off_zstar),
-                           dcycle);
-    return hipGetLastError();
+    return extract_gain(p, A, p.ld, p.nyp, w, dcycle, s);
 }
+
+
 
 hipError_t launch_get_gain(const Plan &p, double *z, void *ws, hipStream_t s) {
     return hipMemcpyAsync(z, (char *)ws + p.off_z, sizeof(double) * (size_t)(p.N + 1) * p.N,

@@ -65,7 +65,8 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
         return fail(nullptr, MENKF_E_ARG, "model must be MENKF_BURGERS1D or MENKF_NS2D (got %d)", cfg->model);
     if (cfg->precision != MENKF_F32 && cfg->precision != MENKF_F64)
         return fail(nullptr, MENKF_E_ARG, "precision must be MENKF_F32 or MENKF_F64 (got %d)", cfg->precision);
-    if (cfg->gain_mode != MENKF_GAIN_EXACT_R && cfg->gain_mode != MENKF_GAIN_SAMPLE_EE)
+    if (cfg->gain_mode != MENKF_GAIN_EXACT_R && cfg->gain_mode != MENKF_GAIN_SAMPLE_EE &&
+        cfg->gain_mode != MENKF_GAIN_ENSEMBLE_SPACE)
         return fail(nullptr, MENKF_E_ARG, "unknown gain_mode %d", cfg->gain_mode);
     p->dim = cfg->model == MENKF_NS2D ? 2 : 1;
     p->F = p->dim == 2 ? 4 : 1;
@@ -93,8 +94,8 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     if (p->dim == 1 && !(cfg->nu >= 0)) return fail(nullptr, MENKF_E_ARG, "nu must be >= 0");
     if (p->dim == 2 && !(cfg->gamma > 1 && cfg->mach > 0 && cfg->reynolds > 0 && cfg->prandtl > 0))
         return fail(nullptr, MENKF_E_ARG, "need gamma > 1, mach > 0, reynolds > 0, prandtl > 0");
-    if (cfg->gain_mode == MENKF_GAIN_EXACT_R && !(cfg->obs_sigma > 0))
-        return fail(nullptr, MENKF_E_ARG, "obs_sigma must be > 0 with MENKF_GAIN_EXACT_R");
+    if (cfg->gain_mode != MENKF_GAIN_SAMPLE_EE && !(cfg->obs_sigma > 0))
+        return fail(nullptr, MENKF_E_ARG, "obs_sigma must be > 0 with MENKF_GAIN_EXACT_R / ENSEMBLE_SPACE");
     if (cfg->gain_mode == MENKF_GAIN_SAMPLE_EE && cfg->n_probes > 2 * cfg->n_members - 2)
         return fail(nullptr, MENKF_E_ARG,
                     "MENKF_GAIN_SAMPLE_EE: Y Y^T + E E^T has rank <= 2(N-1) = %d < n_probes = %d (singular)",
@@ -133,6 +134,10 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     p->off_z = take((size_t)(p->N + 1) * p->N * 8);
     p->off_zt = take((size_t)p->npad * p->npad * (f64 ? 8 : 4));
     p->off_zstar = take((size_t)p->npad * 8);
+    p->npm = roundup(p->N, CHOL_NB);
+    p->lds = p->npm + p->mextp;
+    p->off_p = take((size_t)p->mextp * p->mextp * 8);
+    p->off_as = take((size_t)p->lds * p->lds * 8);
     size_t scratch = (size_t)(p->N + 1) * p->nyp * 8;
     if (scratch < 4096 * 8) scratch = 4096 * 8;
     p->off_scratch = take(scratch);

@@ -114,6 +114,10 @@ struct Plan {
     // workspace offsets (bytes)
     size_t off_info, off_f1, off_f2, off_facc, off_c1, off_c2, off_cacc;
     size_t off_yb, off_a, off_linv, off_z, off_zt, off_zstar, off_scratch;
+    // ensemble-space gain: Gram of the extra rows (mextp^2) and the small
+    // augmented matrix [[s^2 I + Y^T Y, .], [ (Y^T B)^T ; I ], .] (lds^2)
+    int npm, lds;              // N rounded up to the block, npm + mextp
+    size_t off_p, off_as;
     size_t ws_bytes;
     menkf_schedule sched[2];   // forecast schedule per level (0 fine, 1 coarse)
     double tuned_ms[2];        // forecast time of the autotuned schedule (0: not tuned)

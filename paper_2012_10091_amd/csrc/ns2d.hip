@@ -148,8 +148,13 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     }
     __syncthreads();
 
-    // phase 2
-    for (int i = threadIdx.x; i < NC; i += 256) {
+    // phase 2 (compile-time trip count: no loop back-edge, so the pending
+    // prefetch loads are not waited for here)
+    constexpr int IT2 = (NC + 255) / 256;
+#pragma unroll
+    for (int k2 = 0; k2 < IT2; ++k2) {
+        const int i = threadIdx.x + 256 * k2;
+        if (i >= NC) break;
         const int cy = i / CX, cx = i - cy * CX;
         const int b = (cy + 2) * BX + (cx + 2);
         const T ux = (su[b - 2] - T(8) * su[b - 1] + T(8) * su[b + 1] - su[b + 2]) * c.i12hx;

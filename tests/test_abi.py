@@ -69,6 +69,8 @@ def _create(**kw):
     (dict(nx=12, ratio=4), -2),                # coarse grid of 3 nodes
     (dict(dt=0.0), -1),
     (dict(obs_sigma=0.0), -1),
+    (dict(obs_sigma=0.0, gain_mode=2), -1),    # ensemble space needs R = s^2 I, s > 0
+    (dict(gain_mode=3), -1),
     (dict(gain_mode=1, n_probes=20, n_members=8), -1),   # Y Y^T + E E^T singular
     (dict(model=1, ny=4), -2),                 # 1D needs ny = 1
 ])
@@ -91,6 +93,12 @@ def test_create_and_workspace_plan():
     assert n.value < 3 * fine + 3 * coarse + chol + 64 * 2 ** 20
     # calls that need a workspace refuse to run without one
     assert lib.menkf_forecast(h, 0, ctypes.c_void_p(1), 1, 1, None, None) == -7
+    lib.menkf_destroy(h)
+
+
+def test_ensemble_space_mode_plans_its_small_system():
+    st, h, lib = _create(gain_mode=2, n_members=64, n_probes=4096, nx=1024, ny=1024)
+    assert st == 0
     lib.menkf_destroy(h)
 
 
