@@ -171,19 +171,21 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every, tau=1.0):
     """Plain (Pi_F + sweeps) and learned (network, per-tile guard) MEnKF runs
     from the same seeds against one truth; the plain path also judges the
     learned one every judge_every cycles (relative L2 distance of the two
-    corrected states > tau switches the learned run to plain for good)."""
+    corrected states > tau switches the learned run to plain for good).  A
+    third run adds the fine-to-coarse feedback (members recentred on the
+    fine analysis after every cycle) to the plain path."""
     import numpy as np
     import torch
     import paper_2012_10091_amd as m
     from synthetic import fields
-    runs = {k: Cycle(cfg, n_sweeps if k == "plain" else 0,
-                     mode=m.MENKF_PROLONG_PLAIN if k == "plain" else m.MENKF_PROLONG_LEARNED_FALLBACK,
-                     net=None if k == "plain" else net)
-            for k in ("plain", "learned")}
+    runs = {k: Cycle(cfg, n_sweeps if k != "learned" else 0,
+                     mode=m.MENKF_PROLONG_LEARNED_FALLBACK if k == "learned" else m.MENKF_PROLONG_PLAIN,
+                     net=net if k == "learned" else None)
+            for k in ("plain", "learned", "plain_feedback")}
     ctx = runs["plain"].ctx
     truth = torch.as_tensor(fields.truth_ic(cfg), dtype=torch.float32, device="cuda").contiguous()
     out = torch.zeros(3, dtype=torch.float64, device="cuda")
-    rm = {"plain": [], "learned": []}
+    rm = {"plain": [], "learned": [], "plain_feedback": []}
     sticky = False
     judge = []
     scratch = torch.empty_like(runs["plain"].fine)
@@ -212,6 +214,8 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every, tau=1.0):
                 judge.append((c, d))
                 if d > tau:
                     sticky = True
+            if k == "plain_feedback":
+                cc.recentre(r.members, r.fine)
             cc.diagnostics(r.fine, truth, out=out)
             o = out.cpu().numpy()
             rm[k].append(float(np.sqrt(o[0] / o[1])))
@@ -223,6 +227,7 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every, tau=1.0):
     return {
         "plain_rmse": res["plain"], "learned_rmse": res["learned"],
         "ratio": res["learned"] / res["plain"], "equal_rmse": res["learned"] <= 1.05 * res["plain"],
+        "feedback_rmse": res["plain_feedback"], "feedback_ratio": res["plain_feedback"] / res["plain"],
         "cycles": n_cycles, "judge_fallback": sticky,
         "fallback_tiles": int(net.fallback_count.item()), "judge": judge,
         "rmse_first_last": {k: [v[0], v[-1]] for k, v in rm.items()},

@@ -299,6 +299,15 @@ menkf_status menkf_net_train_step(const menkf_net_train *t, menkf_stream stream)
  * MENKF_E_NOT_SPD if it is set.  Clears the word when clear != 0. */
 menkf_status menkf_get_status(menkf_ctx *ctx, int32_t *info, int32_t clear, menkf_stream stream);
 
+/* Fine-to-coarse feedback (driving the coarse ensemble by the fine-grid
+ * analysis, which the paper's closing section names as future work):
+ * x^(i) <- x^(i) - mean_i x^(i) + Pi_C(xf) for every member, so the
+ * ensemble mean becomes the injected fine state while every anomaly is
+ * kept; mean and shift in FP64.  members_dev: n_members coarse states
+ * (in/out); xf_dev: one fine state (the analysis x^F_a).  A no-op on the
+ * device if the status word is set. */
+menkf_status menkf_recentre(menkf_ctx *ctx, void *members_dev, const void *xf_dev, menkf_stream stream);
+
 /* Observation operator on nb states: level MENKF_FINE applies H^F (state =
  * fine), MENKF_COARSE applies H^C = H^F o Pi_F; y_dev gets nb x N_y doubles. */
 menkf_status menkf_observe(menkf_ctx *ctx, int32_t level, const void *state_dev, int32_t nb,
@@ -330,6 +339,7 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  *   menkf_gain(members, xstar, yobs, seed, cycle, NULL)
  *   menkf_update(members, deltac)
  *   menkf_prolong_smooth(deltac, fine, fine_prev, n_sweeps, alpha, prolong_mode, net)
+ *   [menkf_recentre(members, fine) if feedback]
  * with the contracts of those calls.  All pointers are device buffers owned
  * by the caller: fine and fine_prev one fine state each, members n_members
  * coarse states, xstar and deltac one coarse state each, yobs n_probes
@@ -349,6 +359,7 @@ typedef struct {
     int32_t prolong_mode;
     const menkf_net *net;
     menkf_stream aux_stream;
+    int32_t feedback;   /* 1: end the cycle with menkf_recentre(members, fine) */
 } menkf_cycle_args;
 
 menkf_status menkf_cycle(const menkf_cycle_args *args, menkf_stream stream);

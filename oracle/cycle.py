@@ -9,6 +9,7 @@ model parameters, so the parameter steps of the dual filter are inactive):
   4. EnKF analysis on the coarse members and delta^C = K (y^o - H^C(x*))
   5. x' = x^F_f + Pi_F(delta^C)
   6. n_s relaxed Jacobi sweeps (alpha = 0.5) -> x^F_a
+  7. optional fine-to-coarse feedback: members recentred on Pi_C(x^F_a)
 
 ``n_sweeps = 0`` is the multilevel EnKF without regularisation that the
 paper also discusses (Sec. 3) and uses as its "classical Dual EnKF on the
@@ -42,8 +43,17 @@ def observe_truth(cfg, truth, idx, comp):
     return obs.observe_fine(truth, idx, comp, cfg.dim)
 
 
+def recentre(members, fine, cfg):
+    """Fine-to-coarse feedback (the paper's closing section names driving the
+    coarse ensemble by the fine-grid analysis as future work): shift the
+    members so that their mean is Pi_C(x^F_a), keeping every anomaly:
+    x^(i) <- x^(i) - mean_i x^(i) + Pi_C(x^F_a)."""
+    target = grids.restrict(fine, cfg.ratio, cfg.dim)
+    return members - members.mean(axis=0, keepdims=True) + target[None]
+
+
 def cycle(cfg, st: State, y_obs, idx, comp, n_sweeps=1, alpha=0.5, eps=None,
-          seed=None, mode="exact_r", return_parts=False):
+          seed=None, mode="exact_r", return_parts=False, feedback=False):
     fine_model = Model(cfg, "fine")
     coarse_model = Model(cfg, "coarse")
     xf, xf_prev = fine_model.forecast(st.fine, cfg.n_obs)
@@ -56,7 +66,8 @@ def cycle(cfg, st: State, y_obs, idx, comp, n_sweeps=1, alpha=0.5, eps=None,
     res = enkf.analysis(mem_f, xstar, y_obs, eps, make_H(cfg, idx, comp), cfg.obs_sigma, mode=mode)
     x = xf + grids.prolong(res["delta"], cfg.ratio, cfg.dim)
     x = smooth.smooth(x, xf_prev, fine_model, n_sweeps, alpha)
-    new = State(fine=x, members=res["members"], cycle=c)
+    members = recentre(res["members"], x, cfg) if feedback else res["members"]
+    new = State(fine=x, members=members, cycle=c)
     if return_parts:
         return new, {"xf": xf, "xf_prev": xf_prev, "members_f": mem_f, "xstar": xstar,
                      "eps": eps, **res}

@@ -76,6 +76,7 @@ class MenkfCycleArgs(ctypes.Structure):
         ("prolong_mode", c_int32),
         ("net", ctypes.POINTER(MenkfNet)),
         ("aux_stream", c_void_p),
+        ("feedback", c_int32),
     ]
 
 
@@ -104,6 +105,7 @@ SIGNATURES = {
     "menkf_prolong_smooth": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_int32,
                                        ctypes.POINTER(MenkfNet), c_void_p]),
     "menkf_get_status": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_int32, c_void_p]),
+    "menkf_recentre": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_net_pack": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "menkf_net_train_workspace_size": (c_int32, [c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "menkf_net_train_step": (c_int32, [ctypes.POINTER(MenkfNetTrain), c_void_p]),

@@ -232,7 +232,7 @@ class Context:
 
     def cycle_args(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
                    n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None,
-                   aux_stream=None):
+                   aux_stream=None, feedback: bool = False):
         """The menkf_cycle_args of one cycle of this instance (buffers checked here)."""
         self._state(fine, self.fine_shape, "fine")
         self._state(fine_prev, self.fine_shape, "fine_prev")
@@ -255,14 +255,22 @@ class Context:
             a._keep = ns
         if aux_stream is not None:
             a.aux_stream = aux_stream.cuda_stream
+        a.feedback = 1 if feedback else 0
         return a
 
     def cycle(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
               n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None, stream=None,
-              aux_stream=None):
+              aux_stream=None, feedback: bool = False):
         a = self.cycle_args(fine, fine_prev, members, xstar, deltac, yobs, seed, cycle, nsteps, n_sweeps, alpha,
-                            mode, net, aux_stream)
+                            mode, net, aux_stream, feedback)
         self._check(self.lib.menkf_cycle(ctypes.byref(a), _stream(stream)))
+
+    def recentre(self, members: torch.Tensor, xf: torch.Tensor, stream=None):
+        self._state(members, self.coarse_shape, "members")
+        if members.shape[0] != self.N:
+            raise ValueError("members must hold n_members states")
+        self._state(xf, self.fine_shape, "xf")
+        self._check(self.lib.menkf_recentre(self.handle, _ptr(members), _ptr(xf), _stream(stream)))
 
     def get_status(self, clear: bool = True, stream=None) -> int:
         info = ctypes.c_int32()

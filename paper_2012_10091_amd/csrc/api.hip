@@ -426,6 +426,14 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
     return MENKF_OK;
 }
 
+menkf_status menkf_recentre(menkf_ctx *ctx, void *members, const void *xf, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!members || !xf) return fail(ctx, MENKF_E_ARG, "null state pointer");
+    const int32_t *info = (const int32_t *)((char *)ctx->ws + ctx->plan.off_info);
+    const hipError_t e = launch_recentre(ctx->plan, members, xf, info, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_recentre");
+}
+
 menkf_status menkf_net_pack(const float *params, void *wpacked, menkf_stream stream) {
     if (!params || !wpacked) return fail(nullptr, MENKF_E_ARG, "null pointer");
     const hipError_t e = launch_net_pack(params, wpacked, (hipStream_t)stream);
@@ -513,6 +521,7 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
     if (!a->fine || !a->fine_prev || !a->members || !a->xstar || !a->deltac || !a->yobs)
         return fail(ctx, MENKF_E_ARG, "menkf_cycle: null buffer");
     if (a->nsteps < 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: nsteps must be >= 1");
+    if (a->feedback != 0 && a->feedback != 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: feedback must be 0 or 1");
     menkf_status st;
     if (a->aux_stream && a->aux_stream != stream) {
         hipStream_t s0 = (hipStream_t)stream, s1 = (hipStream_t)a->aux_stream;
@@ -536,6 +545,7 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
     if (st == MENKF_OK)
         st = menkf_prolong_smooth(ctx, a->deltac, a->fine, a->fine_prev, a->n_sweeps, a->alpha, a->prolong_mode,
                                   a->net, stream);
+    if (st == MENKF_OK && a->feedback) st = menkf_recentre(ctx, a->members, a->fine, stream);
     return st;
 }
 

@@ -143,6 +143,7 @@ hipError_t launch_prolong_add(const Plan &p, const void *dc, const void *xin, vo
 hipError_t launch_sweep(const Plan &p, const void *xin, const void *xprev, void *xout,
                         double alpha, const int32_t *info, void *ws, hipStream_t s);
 hipError_t launch_copy(const Plan &p, const void *src, void *dst, const int32_t *info, hipStream_t s);
+hipError_t launch_recentre(const Plan &p, void *members, const void *xf, const int32_t *info, hipStream_t s);
 hipError_t launch_ns_resid(const Plan &p, const void *x, const void *xp, void *out, hipStream_t s);
 hipError_t launch_burgers_resid(const Plan &p, const void *x, const void *xp, void *out, hipStream_t s);
 // analysis

@@ -80,6 +80,26 @@ __global__ __launch_bounds__(256) void prolong_add_rows(const T *__restrict__ dc
     xout[g] = xin[g] + acc;
 }
 
+// Members recentred on the injected fine state: one thread per coarse
+// (field, point); the member mean is accumulated in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void recentre_members(T *__restrict__ X, const T *__restrict__ xf, int N,
+                                                        long long npts, long long nc, long long nf, int nx, int r,
+                                                        int nxc, const int32_t *__restrict__ info) {
+    if (*info != 0) return;
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const long long f = p / nc, q = p - f * nc;
+    const long long jy = q / nxc, jx = q - jy * nxc;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += (double)X[(long long)i * npts + p];
+    const double shift = (double)xf[f * nf + (jy * r) * nx + jx * r] - s / (double)N;
+    for (int i = 0; i < N; ++i) {
+        T *v = X + (long long)i * npts + p;
+        *v = (T)((double)*v + shift);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void copy_guarded(const T *__restrict__ src, T *__restrict__ dst, long long n,
                                                     const int32_t *__restrict__ info) {
@@ -120,6 +140,18 @@ hipError_t launch_prolong_add(const Plan &p, const void *dc, const void *xin, vo
     else
         hipLaunchKernelGGL(prolong_add<float>, dim3(blocks), dim3(256), 0, s, (const float *)dc,
                            (const float *)xin, (float *)xout, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, p.F, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_recentre(const Plan &p, void *members, const void *xf, const int32_t *info, hipStream_t s) {
+    const long long npts = p.nc * p.F;
+    const int blocks = (int)((npts + 255) / 256);
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(recentre_members<double>, dim3(blocks), dim3(256), 0, s, (double *)members,
+                           (const double *)xf, p.N, npts, p.nc, p.nf, p.nx, p.cfg.ratio, p.nxc, info);
+    else
+        hipLaunchKernelGGL(recentre_members<float>, dim3(blocks), dim3(256), 0, s, (float *)members,
+                           (const float *)xf, p.N, npts, p.nc, p.nf, p.nx, p.cfg.ratio, p.nxc, info);
     return hipGetLastError();
 }
 
