@@ -41,6 +41,15 @@ class Config:
     seed: int = 2012
     truth_sigma: float = 0.1  # 1D truth noise amplitude / 2D truth mode RMS
     smooth_width: float = 0.1  # 1D truth noise smoothing (Gaussian std, x units)
+    # inlet-forced 1D Burgers (dual parameter estimation); bc "periodic" elsewhere
+    bc: str = "periodic"
+    u0: float = 1.0
+    omega: float = 2.0 * math.pi
+    theta_true: tuple = (0.2, 0.0)
+    theta_prior: tuple = (0.0, 0.3)
+    theta_prior_sigma: tuple = (0.05, 0.05)
+    theta_walk: tuple = (0.005, 0.005)
+    t_spinup: float = 10.0
 
     @property
     def nfields(self) -> int:
@@ -95,6 +104,17 @@ C4 = Config(name="ns2d_512_128_n32", dim=2, nx=512, ny=512, ratio=4, n_members=3
             member_sigma=0.05, precision="f32")
 
 CONFIGS = {"C1": C1, "C2": C2, "C3": C3, "C4": C4}
+
+
+def inlet_burgers(ratio: int = 4, precision: str = "f64", **kw) -> Config:
+    """The Burgers case of Sec. 4: [0, 10], dx = 0.0125 (800 nodes), Re = 200,
+    dt = 2e-4, inlet u0 (1 + theta_1 sin(2 pi t + theta_2)), truth theta =
+    (0.2, 0), 80 sensors on [0, 1) observed every 30 steps with variance
+    0.0025, N_e = 100, prior theta ~ N((0, 0.3), 0.0025 I)."""
+    base = Config(name=f"burgers1d_inlet_800_r{ratio}_n100", dim=1, nx=800, ny=1, ratio=ratio,
+                  n_members=100, n_obs=30, n_probes=80, dt=2e-4, n_cycles=3166, obs_sigma=0.05,
+                  member_sigma=0.0, precision=precision, nu=1.0 / 200.0, length=10.0, bc="inlet")
+    return base.with_(**kw)
 
 
 def tiny_1d(precision: str = "f64", **kw) -> Config:

@@ -146,7 +146,11 @@ def probes_for(cfg: Config):
     2D: N_y distinct random fine nodes; probe p observes u if p is even and
     v if p is odd.
     """
-    if cfg.dim == 1:
+    if cfg.dim == 1 and getattr(cfg, "bc", "periodic") == "inlet":
+        # the first n_probes fine nodes (80 sensors on [0, 1) in the Sec. 4 case)
+        idx = np.arange(cfg.n_probes, dtype=np.int64)
+        comp = np.zeros(cfg.n_probes, dtype=np.int64)
+    elif cfg.dim == 1:
         step = cfg.nx // cfg.n_probes
         assert step * cfg.n_probes == cfg.nx
         idx = np.arange(cfg.n_probes, dtype=np.int64) * step
@@ -187,3 +191,18 @@ def random_members_like(cfg: Config, seed_offset: int = 11, amplitude: float = 1
         out[i, 2] = rho * v
         out[i, 3] = p_int + 0.5 * rho * (u * u + v * v)
     return out
+
+
+# ----------------------------------------------------------------------------- inlet case
+def inlet_theta_ics(cfg: Config) -> np.ndarray:
+    """Member parameters theta^(i) ~ N(theta_prior, diag(theta_prior_sigma^2)), (N, 2)."""
+    rng = np.random.default_rng(cfg.seed + 3)
+    return (np.asarray(cfg.theta_prior)[None, :]
+            + np.asarray(cfg.theta_prior_sigma)[None, :] * rng.standard_normal((cfg.n_members, 2)))
+
+
+def inlet_uniform(cfg: Config, level: str = "fine", nb: int = 0) -> np.ndarray:
+    """u(x, 0) = u0 everywhere: (1, n) for one state, (nb, 1, n) for nb states."""
+    n = cfg.nx if level == "fine" else cfg.nxc
+    u = np.full((1, n), cfg.u0)
+    return u if nb == 0 else np.repeat(u[None], nb, axis=0)

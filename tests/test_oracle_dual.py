@@ -1,0 +1,109 @@
+"""Pins of the dual-EnKF oracle on the inlet-forced Burgers case: the open
+prolongation (one-sided cubic stencils) reproduces cubics and inverts
+injection, uniform flow is an exact steady state, the scheme converges at
+second order under grid refinement, the parameter update equals the
+textbook ensemble Kalman update written with an explicit inverse, the
+random walk has the requested moments, and a short dual MEnKF run moves
+the amplitude estimate from its prior toward the truth."""
+
+import numpy as np
+
+from oracle import dual, enkf, rng
+from synthetic import configs, fields
+
+
+def test_open_prolongation_reproduces_cubics_and_inverts_injection():
+    for nc, r in ((12, 4), (9, 3), (8, 1), (16, 8)):
+        P = dual.prolong_matrix_open(nc, r)
+        np.testing.assert_allclose(P.sum(axis=1), 1.0, atol=1e-13)
+        X = np.arange(nc, dtype=np.float64)          # coarse coordinate in coarse-node units
+        xf = np.arange(nc * r) / r
+        for deg in range(4):
+            np.testing.assert_allclose(P @ X ** deg, xf ** deg, rtol=0, atol=1e-9 * max(1.0, nc ** deg))
+        # injection after prolongation is the identity on the coarse grid
+        np.testing.assert_allclose(P[::r], np.eye(nc), atol=1e-14)
+        xc = np.random.default_rng(nc).standard_normal((3, nc))
+        np.testing.assert_allclose(dual.restrict_open(dual.prolong_open(xc, r), r), xc, atol=1e-13)
+
+
+def test_uniform_flow_is_a_steady_state():
+    cfg = configs.inlet_burgers(nx=200)
+    u = fields.inlet_uniform(cfg)
+    out, prev = dual.inlet_forecast(u, 0.0, 500, cfg.dt, np.array([0.0, 0.7]), cfg.nu, cfg.length / cfg.nx,
+                                    cfg.u0, cfg.omega)
+    np.testing.assert_array_equal(out, u)
+    np.testing.assert_array_equal(prev, u)
+
+
+def test_second_order_under_refinement():
+    """Self-convergence of the inlet wave at t = 0.5 on n = 100 ... 800 cells
+    (common nodes x = 0.1 k): successive differences shrink by 4 per halving.
+    The viscosity is raised to 0.05 so that the front launched by the inlet
+    at t = 0 is resolved on the coarsest grid and the asymptotic rate shows."""
+    L, nu, u0, om = 10.0, 0.05, 1.0, np.pi
+    th = np.array([0.2, 0.0])
+    T, dt = 0.5, 5e-5
+
+    def run(n):
+        u = np.full((1, n), u0)
+        out, _ = dual.inlet_forecast(u, 0.0, int(round(T / dt)), dt, th, nu, L / n, u0, om)
+        return out[0, ::n // 100][:10]
+    s = [run(n) for n in (100, 200, 400, 800)]
+    d = [np.abs(s[i] - s[i + 1]).max() for i in range(3)]
+    orders = [np.log2(d[i] / d[i + 1]) for i in range(2)]
+    assert all(1.85 < o < 2.2 for o in orders), (d, orders)
+
+
+def test_parameter_update_is_the_ensemble_kalman_update():
+    """theta^a = theta^f + Theta Y^T (Y Y^T + R)^-1 (y^o + eps - y^f), with an
+    explicit inverse, for a nonlinear map of the parameters to probes."""
+    g = np.random.default_rng(3)
+    N, P, Ny, sig = 30, 2, 7, 0.05
+    theta_f = g.standard_normal((N, P)) * 0.1 + np.array([0.1, 0.3])
+    A = g.standard_normal((Ny, P))
+    yf = np.tanh(theta_f @ A.T)                       # (N, Ny), nonlinear in theta
+    yo = g.standard_normal(Ny) * 0.1
+    eps = sig * g.standard_normal((N, Ny))
+    # enkf.analysis works on states; use the observations themselves as the state
+    xs = yf[:, None, :]
+    res = enkf.analysis(xs, yf.mean(axis=0)[None, :], yo, eps, lambda x: x[..., 0, :], sig)
+    got = dual.param_update(theta_f, res["Z"])
+    Th = (theta_f - theta_f.mean(0)) / np.sqrt(N - 1)
+    Y = (yf - yf.mean(0)) / np.sqrt(N - 1)
+    K = Th.T @ Y @ np.linalg.inv(Y.T @ Y + sig ** 2 * np.eye(Ny))
+    want = theta_f + (K @ (yo[None, :] + eps - yf).T).T
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_random_walk_moments_and_independence_from_observation_draws():
+    tau = dual.param_perturbations(7, 3, 20000, [0.01, 0.002])
+    assert abs(tau[:, 0].mean()) < 3 * 0.01 / np.sqrt(20000)
+    assert abs(tau[:, 0].std() / 0.01 - 1) < 0.03
+    assert abs(tau[:, 1].std() / 0.002 - 1) < 0.03
+    eps = rng.perturbations(7, 3, 20000, 2, 1.0)
+    assert abs(np.corrcoef(tau[:, 0], eps[:, 0])[0, 1]) < 0.05
+
+
+def test_short_dual_run_moves_the_amplitude_toward_the_truth():
+    cfg = configs.inlet_burgers(nx=200, ratio=2, n_members=40, n_probes=20, n_obs=30)
+    idx, _ = fields.probes_for(cfg)
+    hf = cfg.length / cfg.nx
+    truth = fields.inlet_uniform(cfg)
+    truth, _ = dual.inlet_forecast(truth, 0.0, 5000, cfg.dt, np.array(cfg.theta_true), cfg.nu, hf, cfg.u0, cfg.omega)
+    st = dual.DualState(fine=fields.inlet_uniform(cfg), members=fields.inlet_uniform(cfg, "coarse", cfg.n_members),
+                        theta=fields.inlet_theta_ics(cfg), t=1.0)
+    # a short free spin-up of the model side from t = 0 to 1
+    st.fine, _ = dual.inlet_forecast(st.fine, 0.0, 5000, cfg.dt, st.theta.mean(0), cfg.nu, hf, cfg.u0, cfg.omega)
+    st.members, _ = dual.inlet_forecast(st.members, 0.0, 5000, cfg.dt, st.theta, cfg.nu, cfg.length / cfg.nxc,
+                                        cfg.u0, cfg.omega)
+    t = 1.0
+    for c in range(1, 61):
+        truth, _ = dual.inlet_forecast(truth, t, cfg.n_obs, cfg.dt, np.array(cfg.theta_true), cfg.nu, hf, cfg.u0,
+                                       cfg.omega)
+        t += cfg.n_obs * cfg.dt
+        y = truth[0, idx] + fields.obs_noise(cfg, c)
+        st, theta_bar = dual.dual_cycle(cfg, st, y, idx, n_sweeps=1)
+    # prior (0, 0.3), truth (0.2, 0): the amplitude is found within 60
+    # cycles, the phase has moved most of the way
+    assert abs(theta_bar[0] - 0.2) < 0.05, theta_bar
+    assert theta_bar[1] < 0.2, theta_bar
