@@ -89,6 +89,7 @@ class Cycle:
         self.seed = cfg.seed + 5
         self.graph = None
         self.aux = torch.cuda.Stream()
+        self.overlap = False
 
     def autotune(self):
         """Pick the forecast schedules of both levels with the library's autotuner."""
@@ -101,10 +102,12 @@ class Cycle:
         return self.tuned
 
     def issue(self, stream):
-        """One cycle (menkf_cycle); the fine forecast runs on a second stream beside the members'."""
+        """One cycle (menkf_cycle).  With overlap, the fine forecast runs on a
+        second stream beside the members' (at 1024^2/256^2 this no longer
+        pays: both forecasts fill the GPU)."""
         self.ctx.cycle(self.fine, self.prev, self.members, self.xs, self.dc, self.y, self.seed,
                        self.m.MENKF_CYCLE_DEVICE, self.cfg.n_obs, n_sweeps=self.n_sweeps, alpha=0.5, mode=self.mode,
-                       net=self.net, stream=stream, aux_stream=self.aux)
+                       net=self.net, stream=stream, aux_stream=self.aux if self.overlap else None)
 
     def set_state(self, fine, members):
         self.fine.copy_(fine)
