@@ -20,6 +20,9 @@ Readings (the paper leaves them open):
   coarse nodes b..b+3 with b = min(max(j - 1, 0), n_c - 4) for the fine
   node r j + m (one-sided near both ends, including the r - 1 fine nodes
   past the last coarse node); Pi_C is injection, so Pi_C o Pi_F = I.
+* the fine correction and the sweeps leave the inlet node alone (its value
+  is the boundary condition's, not an estimate); the sweeps extrapolate the
+  outlet node from the swept interior like the forecast does.
 * parameter random walk tau ~ N(0, diag(sigma_theta^2)) (Sigma^theta is not
   given), drawn with Philox4x32-10 and Box-Muller like the observation
   perturbations, counter (param, member, cycle, 0x5041).
@@ -112,18 +115,25 @@ def inlet_forecast(u, t0, nsteps, dt, theta, nu, h, u0, omega):
     return u[..., None, :], prev[..., None, :]
 
 
-def smooth_open(x, x_prev, cfg, n_sweeps, alpha, theta, t_end):
+def correct_open(xf, delta, ratio):
+    """x' = x^F_f + Pi_F(delta^C) (Algo. 4 step 5) at every node but the
+    inlet, whose value the boundary condition prescribes."""
+    x = np.asarray(xf, dtype=np.float64) + prolong_open(delta, ratio)
+    x[..., 0] = np.asarray(xf, dtype=np.float64)[..., 0]
+    return x
+
+
+def smooth_open(x, x_prev, cfg, n_sweeps, alpha):
     """Relaxed Jacobi sweeps of the implicit-Euler system of the last step
     (as for the periodic case, Algo. 4 step 6) at the interior nodes; the
-    boundary nodes keep the inlet value at t_end and the extrapolated
-    outlet."""
+    inlet node keeps its value and the outlet node is extrapolated from
+    the swept interior."""
     h = cfg.length / cfg.nx
     D = 1.0 + cfg.dt * cfg.nu * 2.0 / (h * h)
     u = np.asarray(x, dtype=np.float64)[..., 0, :]
     up = np.asarray(x_prev, dtype=np.float64)[..., 0, :]
-    g = inlet_value(t_end, theta, cfg.u0, cfg.omega)
     for _ in range(n_sweeps):
-        u = _with_bc(u + (alpha / D) * (up + cfg.dt * _rhs(u, cfg.nu, h) - u), g)
+        u = _with_bc(u + (alpha / D) * (up + cfg.dt * _rhs(u, cfg.nu, h) - u), u[..., 0])
     return u[..., None, :]
 
 
@@ -190,6 +200,6 @@ def dual_cycle(cfg, st: DualState, y_obs, idx, n_sweeps=1, alpha=0.5, seed=None)
     xf, xprev = inlet_forecast(st.fine, st.t, cfg.n_obs, cfg.dt, theta_bar, cfg.nu, hf, cfg.u0, cfg.omega)
     xstar = restrict_open(xf, r)
     res = enkf.analysis(mem_f2, xstar, y_obs, eps, H, cfg.obs_sigma)
-    x = xf + prolong_open(res["delta"], r)
-    x = smooth_open(x, xprev, cfg, n_sweeps, alpha, theta_bar, st.t + cfg.n_obs * cfg.dt)
+    x = correct_open(xf, res["delta"], r)
+    x = smooth_open(x, xprev, cfg, n_sweeps, alpha)
     return DualState(fine=x, members=res["members"], theta=theta_a, t=st.t + cfg.n_obs * cfg.dt, cycle=c), theta_bar

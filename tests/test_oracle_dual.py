@@ -107,3 +107,23 @@ def test_short_dual_run_moves_the_amplitude_toward_the_truth():
     # cycles, the phase has moved most of the way
     assert abs(theta_bar[0] - 0.2) < 0.05, theta_bar
     assert theta_bar[1] < 0.2, theta_bar
+
+
+def test_correction_keeps_the_inlet_and_sweeps_solve_the_implicit_system():
+    cfg = configs.inlet_burgers(nx=200, ratio=4, n_members=8, n_probes=20)
+    hf = cfg.length / cfg.nx
+    g = np.random.default_rng(5)
+    xf = 1.0 + 0.1 * np.sin(np.arange(cfg.nx) * hf)[None, :] + 0.01 * g.standard_normal((1, cfg.nx))
+    delta = 0.05 * g.standard_normal((1, cfg.nxc))
+    x = dual.correct_open(xf, delta, cfg.ratio)
+    assert x[0, 0] == xf[0, 0]
+    np.testing.assert_allclose(x[0, 1:], xf[0, 1:] + dual.prolong_open(delta, cfg.ratio)[0, 1:], atol=0)
+    xprev = xf - 0.001
+    y = dual.smooth_open(x, xprev, cfg, 0, 0.5)
+    np.testing.assert_array_equal(y, x)
+    # undamped Jacobi converges to the implicit-Euler solution at the interior
+    y = dual.smooth_open(x, xprev, cfg, 400, 1.0)      # (1, n): one state of one field
+    r = xprev + cfg.dt * dual._rhs(y, cfg.nu, hf) - y
+    assert np.abs(r[0, 1:-1]).max() < 1e-13
+    assert y[0, 0] == x[0, 0]
+    assert y[0, -1] == 2.0 * y[0, -2] - y[0, -3]
