@@ -62,7 +62,7 @@ typedef enum {
     MENKF_E_WORKSPACE = -7    /* workspace missing or too small */
 } menkf_status;
 
-enum { MENKF_BURGERS1D = 1, MENKF_NS2D = 2 };          /* model */
+enum { MENKF_BURGERS1D = 1, MENKF_NS2D = 2, MENKF_BURGERS1D_INLET = 3 };   /* model */
 enum { MENKF_F32 = 0, MENKF_F64 = 1 };                 /* precision */
 enum { MENKF_GAIN_EXACT_R = 0, MENKF_GAIN_SAMPLE_EE = 1, MENKF_GAIN_ENSEMBLE_SPACE = 2 };
 enum { MENKF_FINE = 0, MENKF_COARSE = 1 };             /* grid level */
@@ -76,6 +76,18 @@ enum { MENKF_PROLONG_PLAIN = 0, MENKF_PROLONG_LEARNED = 1, MENKF_PROLONG_LEARNED
  *              (Sec. 6, mass/momentum/energy equations), fourth-order centred
  *              differences, classical four-stage Runge-Kutta.
  *              Both periodic on [0, length)^dim.
+ *              MENKF_BURGERS1D_INLET: the Burgers equation on the open
+ *              interval of the inlet case of Sec. 4: nodes x_i = i length/nx,
+ *              Dirichlet inlet u(0, t) = u0 (1 + theta_1 sin(omega t + theta_2))
+ *              with per-state parameters theta (menkf_forecast_inlet),
+ *              imposed at every Runge-Kutta stage time, outlet node the
+ *              linear extrapolation 2 u_{n-2} - u_{n-3}.  Pi_F uses one-sided
+ *              cubic stencils at both ends (coarse nodes b..b+3,
+ *              b = clamp(j - 1, 0, n_c - 4) for the fine nodes of coarse
+ *              cell j); Pi_C is injection; the fine correction and the
+ *              relaxed sweeps leave the inlet node to the boundary
+ *              condition.  A state row lives in LDS during a forecast, so
+ *              nx <= 5290 (F64) or 8192 (F32).
  *   precision  MENKF_F32: float states and stencils, BF16 member-update
  *              products with FP32 accumulation, FP64 innovation covariance
  *              (S = Y Y^T + R), Cholesky and gain of x*.
@@ -107,6 +119,12 @@ typedef struct {
     double gamma, mach, reynolds, prandtl;
     double obs_sigma;
     int32_t anomaly_terms;
+    /* MENKF_BURGERS1D_INLET only: inlet mean velocity and angular
+     * frequency, and the standard deviations of the random walk
+     * theta^f = theta + tau, tau ~ N(0, diag(theta_sigma^2)), of the dual
+     * filter's parameter forecast (Algo. 2 step 1). */
+    double u0, omega;
+    double theta_sigma[2];
 } menkf_config;
 
 /* Create / destroy a context for the current HIP device.  The context owns
@@ -326,6 +344,70 @@ menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa_dev, const void *x
  * Gamma = -r / dt on that field (e.g. field 2, rho v, in 2D). */
 menkf_status menkf_residual(menkf_ctx *ctx, const void *x_dev, const void *xprev_dev, void *r_dev,
                             menkf_stream stream);
+
+/* ----------------------------------------------------------------------
+ * Dual estimation of the inlet parameters (Sec. 2.1.3, Algo. 2, applied to
+ * the coarse ensemble as in Algo. 3, the fine run of Algo. 4 driven by the
+ * mean analysed parameters), MENKF_BURGERS1D_INLET contexts only.
+ * Parameters are FP64 pairs theta = (amplitude theta_1, phase theta_2),
+ * one row of 2 doubles per state.
+ * ---------------------------------------------------------------------- */
+
+/* Forecast of the inlet-forced model (state-evolution equation with the
+ * inlet value of each state's own parameters): as menkf_forecast, plus
+ *   theta_dev  nb x 2 doubles, row i = parameters of state i
+ *   t0_dev     one double: the time at the start of the window (read when
+ *              the forecast runs, so a captured call sees updates)
+ * menkf_forecast on such a context returns MENKF_E_ARG. */
+menkf_status menkf_forecast_inlet(menkf_ctx *ctx, int32_t level, void *state_dev, int32_t nb, int32_t nsteps,
+                                  void *prev_dev, const double *theta_dev, const double *t0_dev,
+                                  menkf_stream stream);
+
+/* Parameter forecast (Algo. 2 step 1): theta_f = theta + tau for the
+ * n_members rows, tau_k ~ N(0, theta_sigma[k]^2) drawn with Philox4x32-10
+ * keyed by seed at counter (k/2, member, cycle, 0x5041), Box-Muller in FP64
+ * (cos for k = 0, sin for k = 1).  cycle = MENKF_CYCLE_DEVICE reads the
+ * context's device counter without advancing it.  theta_f may alias theta. */
+menkf_status menkf_param_perturb(menkf_ctx *ctx, const double *theta_dev, double *theta_f_dev, uint64_t seed,
+                                 uint64_t cycle, menkf_stream stream);
+
+/* Parameter analysis (Algo. 2 step 5): theta_a(j) = theta_f(j) +
+ * sum_i Theta_i Z[i, j], Theta_i = (theta_f(i) - mean) / sqrt(N_e - 1), with
+ * the gain factors Z of the preceding menkf_gain, which must have been
+ * computed on the members forecast with theta_f.  theta_mean_dev (2
+ * doubles) receives the mean of theta_a.  theta_a may alias theta_f.  A
+ * no-op on the device if the status word is set. */
+menkf_status menkf_param_update(menkf_ctx *ctx, const double *theta_f_dev, double *theta_a_dev,
+                                double *theta_mean_dev, menkf_stream stream);
+
+/* One dual cycle, issued on stream as
+ *   menkf_restrict(fine, xstar)                      any x*: only Z[:, :N] is used next
+ *   menkf_param_perturb(theta -> theta_f)            theta_f in the workspace
+ *   trial = members; menkf_forecast_inlet(COARSE, trial, theta_f, clock)
+ *   menkf_gain(trial, xstar, yobs, seed, cycle)      the cycle counter is not advanced here
+ *   menkf_param_update(theta_f -> theta, theta_mean)
+ *   menkf_forecast_inlet(COARSE, members, theta, clock)
+ *   menkf_forecast_inlet(FINE, fine, theta_mean, clock), x_{k-1} into fine_prev
+ *   menkf_restrict(fine, xstar)
+ *   menkf_gain(members, xstar, yobs, seed, cycle)    the same perturbed observations
+ *   menkf_update(members, deltac)
+ *   menkf_prolong_smooth(deltac, fine, fine_prev, n_sweeps, alpha, PLAIN)
+ *   clock += nsteps dt
+ * theta (n_members x 2 doubles) is in/out, theta_mean (2 doubles) out,
+ * clock (one double) in/out; the other buffers as for menkf_cycle.  A
+ * non-positive pivot of the parameter gain leaves theta as it was; the
+ * status word then reports the state gain's outcome only. */
+typedef struct {
+    menkf_ctx *ctx;
+    void *fine, *fine_prev, *members, *xstar, *deltac;
+    const double *yobs;
+    double *theta, *theta_mean, *clock;
+    uint64_t seed, cycle;
+    int32_t nsteps, n_sweeps;
+    double alpha;
+} menkf_dual_args;
+
+menkf_status menkf_dual_cycle(const menkf_dual_args *args, menkf_stream stream);
 
 /* Normalised RAM requirement R_RAM = 1 + N_e / r_C^dim of one fine
  * simulation plus N_e coarse members (Sec. 3).  Host only. */

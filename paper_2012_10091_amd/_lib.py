@@ -29,6 +29,8 @@ class MenkfConfig(ctypes.Structure):
         ("gamma", c_double), ("mach", c_double), ("reynolds", c_double), ("prandtl", c_double),
         ("obs_sigma", c_double),
         ("anomaly_terms", c_int32),
+        ("u0", c_double), ("omega", c_double),
+        ("theta_sigma", c_double * 2),
     ]
 
 
@@ -80,6 +82,19 @@ class MenkfCycleArgs(ctypes.Structure):
     ]
 
 
+class MenkfDualArgs(ctypes.Structure):
+    _fields_ = [
+        ("ctx", c_void_p),
+        ("fine", c_void_p), ("fine_prev", c_void_p), ("members", c_void_p),
+        ("xstar", c_void_p), ("deltac", c_void_p),
+        ("yobs", c_void_p),
+        ("theta", c_void_p), ("theta_mean", c_void_p), ("clock", c_void_p),
+        ("seed", c_uint64), ("cycle", c_uint64),
+        ("nsteps", c_int32), ("n_sweeps", c_int32),
+        ("alpha", c_double),
+    ]
+
+
 NET_NPARAM = 12740
 NET_NPACKED = 20736
 
@@ -118,6 +133,11 @@ SIGNATURES = {
     "menkf_batch_destroy": (None, [c_void_p]),
     "menkf_batch_cycle": (c_int32, [c_void_p, ctypes.POINTER(MenkfCycleArgs), c_int32, c_void_p]),
     "menkf_batch_lanes": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_int32]),
+    "menkf_forecast_inlet": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                       c_void_p]),
+    "menkf_param_perturb": (c_int32, [c_void_p, c_void_p, c_void_p, c_uint64, c_uint64, c_void_p]),
+    "menkf_param_update": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "menkf_dual_cycle": (c_int32, [ctypes.POINTER(MenkfDualArgs), c_void_p]),
     "menkf_graph_begin": (c_int32, [c_void_p]),
     "menkf_graph_end": (c_int32, [c_void_p, ctypes.POINTER(c_void_p)]),
     "menkf_graph_launch": (c_int32, [c_void_p, c_void_p]),

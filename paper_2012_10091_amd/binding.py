@@ -16,6 +16,7 @@ from . import _lib
 
 MENKF_BURGERS1D = 1
 MENKF_NS2D = 2
+MENKF_BURGERS1D_INLET = 3
 MENKF_F32 = 0
 MENKF_F64 = 1
 MENKF_GAIN_EXACT_R = 0
@@ -50,19 +51,27 @@ def _stream(stream=None):
 
 def make_config(model, nx, ny, ratio, n_members, n_probes, dt, precision=MENKF_F32,
                 gain_mode=MENKF_GAIN_EXACT_R, length=6.283185307179586, nu=0.0, gamma=1.4,
-                mach=0.3, reynolds=1000.0, prandtl=0.71, obs_sigma=0.01, anomaly_terms=0) -> _lib.MenkfConfig:
+                mach=0.3, reynolds=1000.0, prandtl=0.71, obs_sigma=0.01, anomaly_terms=0, u0=1.0, omega=0.0,
+                theta_sigma=(0.0, 0.0)) -> _lib.MenkfConfig:
     return _lib.MenkfConfig(model, precision, gain_mode, nx, ny, ratio, n_members, n_probes,
-                            length, dt, nu, gamma, mach, reynolds, prandtl, obs_sigma, anomaly_terms)
+                            length, dt, nu, gamma, mach, reynolds, prandtl, obs_sigma, anomaly_terms,
+                            u0, omega, (ctypes.c_double * 2)(*theta_sigma))
 
 
 def config_from(cfg) -> _lib.MenkfConfig:
     """menkf_config from any object with the workload attributes (dim, nx, ny, ...)."""
+    if cfg.dim == 2:
+        model = MENKF_NS2D
+    else:
+        model = MENKF_BURGERS1D_INLET if getattr(cfg, "bc", "periodic") == "inlet" else MENKF_BURGERS1D
     return make_config(
-        MENKF_NS2D if cfg.dim == 2 else MENKF_BURGERS1D, cfg.nx, cfg.ny, cfg.ratio, cfg.n_members,
+        model, cfg.nx, cfg.ny, cfg.ratio, cfg.n_members,
         cfg.n_probes, cfg.dt, precision=MENKF_F64 if cfg.precision == "f64" else MENKF_F32,
         gain_mode=getattr(cfg, "gain_mode", MENKF_GAIN_EXACT_R), length=cfg.length, nu=cfg.nu,
         gamma=cfg.gamma, mach=cfg.mach, reynolds=cfg.reynolds, prandtl=cfg.prandtl,
-        obs_sigma=cfg.obs_sigma, anomaly_terms=getattr(cfg, "anomaly_terms", 0))
+        obs_sigma=cfg.obs_sigma, anomaly_terms=getattr(cfg, "anomaly_terms", 0),
+        u0=getattr(cfg, "u0", 1.0), omega=getattr(cfg, "omega", 0.0),
+        theta_sigma=tuple(getattr(cfg, "theta_walk", (0.0, 0.0))))
 
 
 def ram_ratio(dim: int, ratio: int, n_members: int) -> float:
@@ -161,6 +170,73 @@ class Context:
                 raise ValueError("prev must match state")
         self._check(self.lib.menkf_forecast(self.handle, level, _ptr(state), nb, nsteps, _ptr(prev),
                                             _stream(stream)))
+
+    # ------------------------------------------------------------ dual filter (inlet-forced model)
+    def _theta(self, t, rows, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA float64 tensor")
+        if t.numel() != 2 * rows:
+            raise ValueError(f"{name} must hold {rows} x 2 doubles")
+        return t
+
+    def forecast_inlet(self, level: int, state: torch.Tensor, nsteps: int, theta: torch.Tensor, t0: torch.Tensor,
+                       prev: Optional[torch.Tensor] = None, stream=None):
+        shape = self.fine_shape if level == MENKF_FINE else self.coarse_shape
+        self._state(state, shape, "state")
+        nb = 1 if state.dim() == len(shape) else state.shape[0]
+        self._theta(theta, nb, "theta")
+        if t0.dtype != torch.float64 or t0.numel() != 1 or not t0.is_cuda:
+            raise ValueError("t0 must be one CUDA float64")
+        if prev is not None:
+            self._state(prev, shape, "prev")
+            if prev.numel() != state.numel():
+                raise ValueError("prev must match state")
+        self._check(self.lib.menkf_forecast_inlet(self.handle, level, _ptr(state), nb, nsteps, _ptr(prev),
+                                                  _ptr(theta), _ptr(t0), _stream(stream)))
+
+    def param_perturb(self, theta: torch.Tensor, theta_f: torch.Tensor, seed: int, cycle: int, stream=None):
+        self._theta(theta, self.N, "theta")
+        self._theta(theta_f, self.N, "theta_f")
+        self._check(self.lib.menkf_param_perturb(self.handle, _ptr(theta), _ptr(theta_f), seed, cycle,
+                                                 _stream(stream)))
+
+    def param_update(self, theta_f: torch.Tensor, theta_a: torch.Tensor, theta_mean: torch.Tensor, stream=None):
+        self._theta(theta_f, self.N, "theta_f")
+        self._theta(theta_a, self.N, "theta_a")
+        self._theta(theta_mean, 1, "theta_mean")
+        self._check(self.lib.menkf_param_update(self.handle, _ptr(theta_f), _ptr(theta_a), _ptr(theta_mean),
+                                                _stream(stream)))
+
+    def dual_args(self, fine, fine_prev, members, xstar, deltac, yobs, theta, theta_mean, clock, seed: int,
+                  cycle: int, nsteps: int, n_sweeps: int = 1, alpha: float = 0.5):
+        """The menkf_dual_args of one dual cycle of this instance (buffers checked here)."""
+        self._state(fine, self.fine_shape, "fine")
+        self._state(fine_prev, self.fine_shape, "fine_prev")
+        self._state(members, self.coarse_shape, "members")
+        if members.shape[0] != self.N:
+            raise ValueError("members must hold n_members states")
+        self._state(xstar, self.coarse_shape, "xstar")
+        self._state(deltac, self.coarse_shape, "deltac")
+        if yobs.dtype != torch.float64 or yobs.numel() != self.Ny or not yobs.is_cuda:
+            raise ValueError("yobs must be a CUDA float64 tensor of n_probes entries")
+        self._theta(theta, self.N, "theta")
+        self._theta(theta_mean, 1, "theta_mean")
+        if clock.dtype != torch.float64 or clock.numel() != 1 or not clock.is_cuda:
+            raise ValueError("clock must be one CUDA float64")
+        a = _lib.MenkfDualArgs()
+        a.ctx = self.handle
+        a.fine, a.fine_prev, a.members = _ptr(fine), _ptr(fine_prev), _ptr(members)
+        a.xstar, a.deltac, a.yobs = _ptr(xstar), _ptr(deltac), _ptr(yobs)
+        a.theta, a.theta_mean, a.clock = _ptr(theta), _ptr(theta_mean), _ptr(clock)
+        a.seed, a.cycle = seed, cycle
+        a.nsteps, a.n_sweeps, a.alpha = nsteps, n_sweeps, alpha
+        return a
+
+    def dual_cycle(self, fine, fine_prev, members, xstar, deltac, yobs, theta, theta_mean, clock, seed: int,
+                   cycle: int, nsteps: int, n_sweeps: int = 1, alpha: float = 0.5, stream=None):
+        a = self.dual_args(fine, fine_prev, members, xstar, deltac, yobs, theta, theta_mean, clock, seed, cycle,
+                           nsteps, n_sweeps, alpha)
+        self._check(self.lib.menkf_dual_cycle(ctypes.byref(a), _stream(stream)))
 
     def set_schedule(self, level: int, tile=(0, 0), member_chunk: int = 0):
         sc = _lib.MenkfSchedule(int(tile[0]), int(tile[1]), int(member_chunk), 0)

@@ -30,39 +30,9 @@
 
 namespace menkf {
 
-// ----------------------------------------------------------------- Philox4x32-10
-// Salmon et al., SC'11: per round the products M0*c0 and M1*c2 are split
-// into hi/lo words and the counter becomes (hi1^c1^k0, lo1, hi0^c3^k1, lo0);
-// the key advances by the Weyl constants between rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-        c[1] = (uint32_t)p1;
-        c[3] = (uint32_t)p0;
-        c[0] = n0;
-        c[2] = n2;
-    }
-}
-
-// Standard normal for (member i, probe p) at a cycle: counter
-// (p >> 1, i, cycle, 0x5045), 53-bit uniforms u = (k + 1/2) 2^-53 from
-// word pairs, Box-Muller cos branch for even p and sin branch for odd p.
+// Observation perturbations: Philox stream word 0x5045 (common.hpp).
 __device__ __forceinline__ double perturb_normal(uint64_t seed, uint64_t cycle, int i, int p) {
-    uint32_t c[4] = {(uint32_t)(p >> 1), (uint32_t)i, (uint32_t)cycle, 0x5045u};
-    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) * 0x1p-53;
-    const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) * 0x1p-53;
-    const double rad = sqrt(-2.0 * log(u1));
-    const double ang = 6.283185307179586 * u2;
-    return (p & 1) ? rad * sin(ang) : rad * cos(ang);
+    return philox_normal(seed, cycle, i, p, 0x5045u);
 }
 
 __global__ void philox_test_kernel(const uint32_t *in, uint32_t *out, int n) {
@@ -81,7 +51,7 @@ __global__ __launch_bounds__(256) void obs_eval(const T *__restrict__ states, lo
                                                 const T *__restrict__ extra, const int32_t *__restrict__ idx,
                                                 const int32_t *__restrict__ comp, int Ny, double *__restrict__ y,
                                                 int ldy, int coarse, int dim, int nx, int ny, int r, int nxc,
-                                                int nyc) {
+                                                int nyc, int open) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int sidx = blockIdx.y;
     if (p >= Ny) return;
@@ -103,7 +73,13 @@ __global__ __launch_bounds__(256) void obs_eval(const T *__restrict__ states, lo
         const int jx = fx / r, mx = fx - jx * r;
         double wx[4];
         lagrange4<double>((double)mx / (double)r, wx);
-        if (dim == 1) {
+        if (dim == 1 && open) {
+            const int b0 = open_cubic<double>(fx, r, nxc, wx);
+            double a = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) a += wx[b] * (double)st[b0 + b];
+            val = a;
+        } else if (dim == 1) {
             double a = 0.0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) a += wx[b] * (double)st[wrap(jx - 1 + b, nxc)];
@@ -685,11 +661,11 @@ hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, d
     if (p.cfg.precision == MENKF_F64)
         hipLaunchKernelGGL(obs_eval<double>, grid, dim3(256), 0, s, (const double *)state, stride, nb,
                            (const double *)nullptr, idx, comp, p.Ny, y, p.Ny, coarse ? 1 : 0, p.dim, p.nx, p.ny,
-                           p.cfg.ratio, p.nxc, p.nyc);
+                           p.cfg.ratio, p.nxc, p.nyc, p.open);
     else
         hipLaunchKernelGGL(obs_eval<float>, grid, dim3(256), 0, s, (const float *)state, stride, nb,
                            (const float *)nullptr, idx, comp, p.Ny, y, p.Ny, coarse ? 1 : 0, p.dim, p.nx, p.ny,
-                           p.cfg.ratio, p.nxc, p.nyc);
+                           p.cfg.ratio, p.nxc, p.nyc, p.open);
     return hipGetLastError();
 }
 
@@ -730,7 +706,7 @@ static hipError_t extract_gain(const Plan &p, const double *M, int ld, int n0, c
 
 hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, const double *yobs, uint64_t seed,
                        uint64_t cycle, const double *eps, const int32_t *idx, const int32_t *comp, void *ws,
-                       hipStream_t s) {
+                       hipStream_t s, bool advance_cycle) {
     char *w = (char *)ws;
     int32_t *info = (int32_t *)(w + p.off_info);
     double *yraw = (double *)(w + p.off_scratch);
@@ -752,11 +728,11 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     if (f64)
         hipLaunchKernelGGL(obs_eval<double>, g1, dim3(256), 0, s, (const double *)members, stride, N,
                            (const double *)xstar, idx, comp, p.Ny, yraw, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
-                           p.nxc, p.nyc);
+                           p.nxc, p.nyc, p.open);
     else
         hipLaunchKernelGGL(obs_eval<float>, g1, dim3(256), 0, s, (const float *)members, stride, N,
                            (const float *)xstar, idx, comp, p.Ny, yraw, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
-                           p.nxc, p.nyc);
+                           p.nxc, p.nyc, p.open);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 2. clear the Schur block, reset status
     hipLaunchKernelGGL(zero_extra, dim3(256), dim3(256), 0, s, A, p.ld, p.nyp, p.mext, info);
@@ -776,7 +752,7 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
                            p.cfg.obs_sigma * p.cfg.obs_sigma, As);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = chol_blocked(As, p.lds, p.npm / CHOL_NB, Linv, info, lds, s)) != hipSuccess) return e;
-        return extract_gain(p, As, p.lds, p.npm, w, dcycle, s);
+        return extract_gain(p, As, p.lds, p.npm, w, advance_cycle ? dcycle : nullptr, s);
     }
     // 4. S = Y Y^T + R (+ identity on the padding), FP64 MFMA
     const int nbs = p.nyp / CHOL_NB;
@@ -786,7 +762,7 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     // 5. blocked Cholesky of the first nyp columns, Schur complement on the rest
     if ((e = chol_blocked(A, p.ld, nbs, Linv, info, lds, s)) != hipSuccess) return e;
     // 6. Z
-    return extract_gain(p, A, p.ld, p.nyp, w, dcycle, s);
+    return extract_gain(p, A, p.ld, p.nyp, w, advance_cycle ? dcycle : nullptr, s);
 }
 
 

@@ -61,8 +61,9 @@ static int roundup(int v, int m) { return (v + m - 1) / m * m; }
 static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     std::memset(p, 0, sizeof(*p));
     p->cfg = *cfg;
-    if (cfg->model != MENKF_BURGERS1D && cfg->model != MENKF_NS2D)
-        return fail(nullptr, MENKF_E_ARG, "model must be MENKF_BURGERS1D or MENKF_NS2D (got %d)", cfg->model);
+    if (cfg->model != MENKF_BURGERS1D && cfg->model != MENKF_NS2D && cfg->model != MENKF_BURGERS1D_INLET)
+        return fail(nullptr, MENKF_E_ARG, "model must be MENKF_BURGERS1D, MENKF_NS2D or MENKF_BURGERS1D_INLET (got %d)",
+                    cfg->model);
     if (cfg->precision != MENKF_F32 && cfg->precision != MENKF_F64)
         return fail(nullptr, MENKF_E_ARG, "precision must be MENKF_F32 or MENKF_F64 (got %d)", cfg->precision);
     if (cfg->gain_mode != MENKF_GAIN_EXACT_R && cfg->gain_mode != MENKF_GAIN_SAMPLE_EE &&
@@ -92,6 +93,19 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     if (cfg->n_probes < 1) return fail(nullptr, MENKF_E_ARG, "n_probes must be >= 1 (got %d)", cfg->n_probes);
     if (!(cfg->dt > 0) || !(cfg->length > 0)) return fail(nullptr, MENKF_E_ARG, "dt and length must be positive");
     if (p->dim == 1 && !(cfg->nu >= 0)) return fail(nullptr, MENKF_E_ARG, "nu must be >= 0");
+    p->open = cfg->model == MENKF_BURGERS1D_INLET ? 1 : 0;
+    if (p->open) {
+        if (!std::isfinite(cfg->u0) || !std::isfinite(cfg->omega))
+            return fail(nullptr, MENKF_E_ARG, "MENKF_BURGERS1D_INLET needs finite u0 and omega");
+        if (!(cfg->theta_sigma[0] >= 0) || !(cfg->theta_sigma[1] >= 0) || !std::isfinite(cfg->theta_sigma[0]) ||
+            !std::isfinite(cfg->theta_sigma[1]))
+            return fail(nullptr, MENKF_E_ARG, "theta_sigma must be finite and >= 0");
+        const size_t ts = cfg->precision == MENKF_F64 ? 8 : 4;
+        if (cfg->nx > 8192 || inlet_window_lds(cfg->nx, ts) > 128 * 1024)
+            return fail(nullptr, MENKF_E_UNSUPPORTED,
+                        "MENKF_BURGERS1D_INLET keeps a state row in LDS: nx = %d exceeds %d", cfg->nx,
+                        cfg->precision == MENKF_F64 ? 5290 : 8192);
+    }
     if (p->dim == 2 && !(cfg->gamma > 1 && cfg->mach > 0 && cfg->reynolds > 0 && cfg->prandtl > 0))
         return fail(nullptr, MENKF_E_ARG, "need gamma > 1, mach > 0, reynolds > 0, prandtl > 0");
     if (cfg->gain_mode != MENKF_GAIN_SAMPLE_EE && !(cfg->obs_sigma > 0))
@@ -141,6 +155,10 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     size_t scratch = (size_t)(p->N + 1) * p->nyp * 8;
     if (scratch < 4096 * 8) scratch = 4096 * 8;
     p->off_scratch = take(scratch);
+    if (p->open) {
+        p->off_trial = take(coarse);
+        p->off_thf = take((size_t)p->N * 2 * 8);
+    }
     p->ws_bytes = o;
     for (int l = 0; l < 2; ++l) {
         ns_tile_shape(cfg->precision, 0, &p->sched[l].tile_x, &p->sched[l].tile_y);
@@ -231,6 +249,7 @@ menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state, int32_t 
     if (level == MENKF_FINE && nb != 1) return fail(ctx, MENKF_E_ARG, "the fine level takes nb = 1 (got %d)", nb);
     if (level == MENKF_COARSE && (nb < 1 || nb > p.N))
         return fail(ctx, MENKF_E_ARG, "coarse nb must be in [1, %d] (got %d)", p.N, nb);
+    if (p.open) return fail(ctx, MENKF_E_ARG, "MENKF_BURGERS1D_INLET forecasts need parameters: menkf_forecast_inlet");
     const hipError_t e = p.dim == 1 ? launch_burgers_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream)
                                     : launch_ns_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream);
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_forecast");
@@ -268,6 +287,7 @@ menkf_status menkf_autotune(menkf_ctx *ctx, int32_t level, void *scratch, int32_
     NEED_WS(ctx);
     if (!scratch) return fail(ctx, MENKF_E_ARG, "scratch state is NULL");
     if (reps < 1 || reps > 1000) return fail(ctx, MENKF_E_ARG, "reps must be in [1, 1000]");
+    if (ctx->plan.open) return fail(ctx, MENKF_E_UNSUPPORTED, "the inlet-forced model has a single schedule");
     Plan &p = ctx->plan;
     const int li = level == MENKF_FINE ? 0 : 1;
     // candidate list
@@ -503,6 +523,7 @@ menkf_status menkf_residual(menkf_ctx *ctx, const void *x, const void *xprev, vo
     if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
     if (!x || !xprev || !r) return fail(ctx, MENKF_E_ARG, "null pointer");
     if (r == x || r == xprev) return fail(ctx, MENKF_E_ARG, "r must not alias x or xprev");
+    if (ctx->plan.open) return fail(ctx, MENKF_E_UNSUPPORTED, "menkf_residual is defined for the periodic models");
     const hipError_t e = ctx->plan.dim == 2 ? launch_ns_resid(ctx->plan, x, xprev, r, (hipStream_t)stream)
                                             : launch_burgers_resid(ctx->plan, x, xprev, r, (hipStream_t)stream);
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_residual");
@@ -511,6 +532,79 @@ menkf_status menkf_residual(menkf_ctx *ctx, const void *x, const void *xprev, vo
 double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members) {
     if (dim < 1 || ratio < 1 || n_members < 0) return -1.0;
     return 1.0 + (double)n_members / std::pow((double)ratio, (double)dim);
+}
+
+menkf_status menkf_forecast_inlet(menkf_ctx *ctx, int32_t level, void *state, int32_t nb, int32_t nsteps, void *prev,
+                                  const double *theta, const double *t0, menkf_stream stream) {
+    NEED_WS(ctx);
+    const Plan &p = ctx->plan;
+    if (!p.open) return fail(ctx, MENKF_E_ARG, "menkf_forecast_inlet needs a MENKF_BURGERS1D_INLET context");
+    if (level != MENKF_FINE && level != MENKF_COARSE) return fail(ctx, MENKF_E_ARG, "bad level %d", level);
+    if (!state || !theta || !t0) return fail(ctx, MENKF_E_ARG, "null pointer");
+    if (nsteps < 1) return fail(ctx, MENKF_E_ARG, "nsteps must be >= 1 (got %d)", nsteps);
+    if (level == MENKF_FINE && nb != 1) return fail(ctx, MENKF_E_ARG, "the fine level takes nb = 1 (got %d)", nb);
+    if (level == MENKF_COARSE && (nb < 1 || nb > p.N))
+        return fail(ctx, MENKF_E_ARG, "coarse nb must be in [1, %d] (got %d)", p.N, nb);
+    const hipError_t e = launch_inlet_forecast(p, level, state, nb, nsteps, prev, theta, t0, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_forecast_inlet");
+}
+
+menkf_status menkf_param_perturb(menkf_ctx *ctx, const double *theta, double *theta_f, uint64_t seed, uint64_t cycle,
+                                 menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!ctx->plan.open) return fail(ctx, MENKF_E_ARG, "menkf_param_perturb needs a MENKF_BURGERS1D_INLET context");
+    if (!theta || !theta_f) return fail(ctx, MENKF_E_ARG, "null pointer");
+    const hipError_t e = launch_param_perturb(ctx->plan, theta, theta_f, seed, cycle, ctx->ws, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_param_perturb");
+}
+
+menkf_status menkf_param_update(menkf_ctx *ctx, const double *theta_f, double *theta_a, double *theta_mean,
+                                menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!ctx->plan.open) return fail(ctx, MENKF_E_ARG, "menkf_param_update needs a MENKF_BURGERS1D_INLET context");
+    if (!theta_f || !theta_a || !theta_mean) return fail(ctx, MENKF_E_ARG, "null pointer");
+    const hipError_t e = launch_param_update(ctx->plan, theta_f, theta_a, theta_mean, ctx->ws, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_param_update");
+}
+
+menkf_status menkf_dual_cycle(const menkf_dual_args *a, menkf_stream stream) {
+    if (!a) return fail(nullptr, MENKF_E_ARG, "args is NULL");
+    menkf_ctx *ctx = a->ctx;
+    NEED_WS(ctx);
+    const Plan &p = ctx->plan;
+    if (!p.open) return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle needs a MENKF_BURGERS1D_INLET context");
+    if (!a->fine || !a->fine_prev || !a->members || !a->xstar || !a->deltac || !a->yobs || !a->theta ||
+        !a->theta_mean || !a->clock)
+        return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle: null buffer");
+    if (a->nsteps < 1) return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle: nsteps must be >= 1");
+    if (!ctx->idx) return fail(ctx, MENKF_E_ARG, "probes not set (menkf_set_probes)");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ctx->ws;
+    void *trial = w + p.off_trial;
+    double *thf = (double *)(w + p.off_thf);
+    hipError_t e = launch_restrict(p, a->fine, a->xstar, s);
+    if (e == hipSuccess) e = launch_param_perturb(p, a->theta, thf, a->seed, a->cycle, ctx->ws, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(trial, a->members, (size_t)p.N * p.nc * p.F * p.tsize, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_inlet_forecast(p, MENKF_COARSE, trial, p.N, a->nsteps, nullptr, thf, a->clock, s);
+    if (e == hipSuccess)
+        e = launch_gain(p, trial, a->xstar, a->yobs, a->seed, a->cycle, nullptr, ctx->idx, ctx->comp, ctx->ws, s,
+                        false);
+    if (e == hipSuccess) e = launch_param_update(p, thf, a->theta, a->theta_mean, ctx->ws, s);
+    if (e == hipSuccess)
+        e = launch_inlet_forecast(p, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, a->theta, a->clock, s);
+    if (e == hipSuccess)
+        e = launch_inlet_forecast(p, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->theta_mean, a->clock, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_dual_cycle");
+    menkf_status st = menkf_restrict(ctx, a->fine, a->xstar, stream);
+    if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);
+    if (st == MENKF_OK) st = menkf_update(ctx, a->members, a->deltac, stream);
+    if (st == MENKF_OK)
+        st = menkf_prolong_smooth(ctx, a->deltac, a->fine, a->fine_prev, a->n_sweeps, a->alpha, MENKF_PROLONG_PLAIN,
+                                  nullptr, stream);
+    if (st != MENKF_OK) return st;
+    e = launch_clock_advance(a->clock, (double)a->nsteps * p.cfg.dt, s);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_dual_cycle (clock)");
 }
 
 menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {

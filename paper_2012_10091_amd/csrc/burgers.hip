@@ -135,6 +135,135 @@ __global__ __launch_bounds__(256) void burgers_resid(const T *__restrict__ x, co
     out[i] = xp[i] + c.dt * burgers_L(x[im], xx, x[ip], c) - xx;
 }
 
+// ----------------------------------------------------------------- inlet-forced case
+// Open grid, nodes x_i = i h (Sec. 4 inlet case): Dirichlet inlet
+// u(0, t) = u0 (1 + th0 sin(omega t + th1)) with the parameters th of the
+// state's own row, imposed at every stage time (t + dt, t + dt/2, t + dt);
+// the outlet node is the linear extrapolation 2 u_{n-2} - u_{n-3} of each
+// stage's interior values.  One workgroup per state; the step-start state U
+// and the two stage arrays stay in LDS for the whole window.  The thread
+// that owns the outlet node recomputes the two interior values it
+// extrapolates from (they are read from the stage's inputs only, so no
+// extra barrier is needed).  Inlet values of up to GCH steps at a time are
+// tabulated in LDS by all threads together before they are needed.
+constexpr int INLET_GCH = 256;
+
+template <typename T>
+struct InletCoef {
+    double u0, omega, dt;   // the boundary value is evaluated in FP64
+};
+
+template <int S, typename T>
+__device__ __forceinline__ T inlet_stage_val(const T *__restrict__ U, const T *__restrict__ X, int i,
+                                             const BurgersCoef<T> &c) {
+    const T xi = X[i];
+    const T v = xi + c.dt * burgers_L(X[i - 1], xi, X[i + 1], c);
+    if (S == 1) return v;
+    if (S == 2) return T(0.75) * U[i] + T(0.25) * v;
+    return U[i] / T(3) + (T(2) / T(3)) * v;
+}
+
+template <int S, int PPT, typename T>
+__device__ __forceinline__ void inlet_stage(const T *__restrict__ U, const T *__restrict__ X, T *__restrict__ Y,
+                                            int n, T g, const BurgersCoef<T> &c) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int i = threadIdx.x + k * blockDim.x;
+        if (i >= n) continue;
+        T v;
+        if (i == 0)
+            v = g;
+        else if (i < n - 1)
+            v = inlet_stage_val<S>(U, X, i, c);
+        else
+            v = T(2) * inlet_stage_val<S>(U, X, n - 2, c) - inlet_stage_val<S>(U, X, n - 3, c);
+        Y[i] = v;
+    }
+}
+
+template <typename T, int PPT>
+__global__ __launch_bounds__(1024) void burgers_inlet_window(T *__restrict__ state, T *__restrict__ prev, int n,
+                                                             int nsteps, BurgersCoef<T> c, InletCoef<T> ic,
+                                                             const double *__restrict__ theta,
+                                                             const double *__restrict__ t0p) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *G = reinterpret_cast<T *>(smem_raw);   // [INLET_GCH][2]: g(t + dt), g(t + dt/2)
+    T *U = G + 2 * INLET_GCH;
+    T *A = U + n;
+    T *B = A + n;
+    const int bs = blockDim.x;
+    T *row = state + (size_t)blockIdx.x * n;
+    T *prow = prev ? prev + (size_t)blockIdx.x * n : nullptr;
+    const double th0 = theta[2 * blockIdx.x], th1 = theta[2 * blockIdx.x + 1];
+    const double t0 = *t0p;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int i = threadIdx.x + k * bs;
+        if (i < n) U[i] = row[i];
+    }
+    for (int base = 0; base < nsteps; base += INLET_GCH) {
+        const int cnt = nsteps - base < INLET_GCH ? nsteps - base : INLET_GCH;
+        __syncthreads();   // the previous chunk's table is no longer read
+        for (int q = threadIdx.x; q < 2 * cnt; q += bs) {
+            const double tt = t0 + (double)(base + (q >> 1)) * ic.dt;
+            const double ts = (q & 1) ? tt + 0.5 * ic.dt : tt + ic.dt;
+            G[q] = (T)(ic.u0 * (1.0 + th0 * sin(ic.omega * ts + th1)));
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const int step = base + j;
+            if (prow && step == nsteps - 1) {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int i = threadIdx.x + k * bs;
+                    if (i < n) prow[i] = U[i];
+                }
+            }
+            const T g1 = G[2 * j], g2 = G[2 * j + 1];
+            inlet_stage<1, PPT>(U, U, A, n, g1, c);
+            __syncthreads();
+            inlet_stage<2, PPT>(U, A, B, n, g2, c);
+            __syncthreads();
+            inlet_stage<3, PPT>(U, B, A, n, g1, c);   // the new state, into A
+            __syncthreads();
+            T *t = U;
+            U = A;
+            A = t;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int i = threadIdx.x + k * bs;
+        if (i < n) row[i] = U[i];
+    }
+}
+
+// Relaxed Jacobi sweep on the open grid: interior as in the periodic case,
+// the inlet node kept, the outlet extrapolated from the swept interior.
+template <typename T>
+__device__ __forceinline__ T sweep_val(const T *__restrict__ x, const T *__restrict__ xp, int i, T w,
+                                       const BurgersCoef<T> &c) {
+    const T xx = x[i];
+    return xx + w * (xp[i] + c.dt * burgers_L(x[i - 1], xx, x[i + 1], c) - xx);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void burgers_sweep_inlet(const T *__restrict__ x, const T *__restrict__ xp,
+                                                           T *__restrict__ out, int n, T w, BurgersCoef<T> c,
+                                                           const int32_t *__restrict__ info) {
+    if (*info != 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T v;
+    if (i == 0)
+        v = x[0];
+    else if (i < n - 1)
+        v = sweep_val(x, xp, i, w, c);
+    else
+        v = T(2) * sweep_val(x, xp, n - 2, w, c) - sweep_val(x, xp, n - 3, w, c);
+    out[i] = v;
+}
+
 template <typename T>
 static BurgersCoef<T> make_coef(const Plan &p, int level) {
     const int n = level == MENKF_FINE ? p.nx : p.nxc;
@@ -192,6 +321,42 @@ static hipError_t burgers_forecast_t(const Plan &p, int level, T *state, int nb,
     return hipGetLastError();
 }
 
+size_t inlet_window_lds(int n, size_t tsize) { return (2 * (size_t)INLET_GCH + 3 * (size_t)n) * tsize; }
+
+template <typename T, int PPT>
+static hipError_t launch_inlet(T *state, T *prev, int n, int nb, int nsteps, BurgersCoef<T> c, InletCoef<T> ic,
+                               const double *theta, const double *t0, int bs, hipStream_t s) {
+    const size_t lds = inlet_window_lds(n, sizeof(T));
+    auto kern = burgers_inlet_window<T, PPT>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, s, state, prev, n, nsteps, c, ic, theta, t0);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t inlet_forecast_t(const Plan &p, int level, T *state, int nb, int nsteps, T *prev,
+                                   const double *theta, const double *t0, hipStream_t s) {
+    const int n = level == MENKF_FINE ? p.nx : p.nxc;
+    const BurgersCoef<T> c = make_coef<T>(p, level);
+    const InletCoef<T> ic{p.cfg.u0, p.cfg.omega, p.cfg.dt};
+    int bs = 64;
+    while (bs < 1024 && bs < n) bs *= 2;
+    const int ppt = (n + bs - 1) / bs;
+    if (ppt <= 1) return launch_inlet<T, 1>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
+    if (ppt <= 2) return launch_inlet<T, 2>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
+    if (ppt <= 4) return launch_inlet<T, 4>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
+    if (ppt <= 8) return launch_inlet<T, 8>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
+    return hipErrorInvalidValue;   // rows this long are rejected when the context is created
+}
+
+hipError_t launch_inlet_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev,
+                                 const double *theta, const double *t0, hipStream_t s) {
+    if (p.cfg.precision == MENKF_F64)
+        return inlet_forecast_t<double>(p, level, (double *)state, nb, nsteps, (double *)prev, theta, t0, s);
+    return inlet_forecast_t<float>(p, level, (float *)state, nb, nsteps, (float *)prev, theta, t0, s);
+}
+
 hipError_t launch_burgers_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev,
                                    void *ws, hipStream_t s) {
     if (p.cfg.precision == MENKF_F64)
@@ -205,8 +370,12 @@ static hipError_t burgers_sweep_t(const Plan &p, const T *x, const T *xp, T *out
     const BurgersCoef<T> c = make_coef<T>(p, MENKF_FINE);
     const double h = p.cfg.length / p.nx;
     const double D = 1.0 + p.cfg.dt * p.cfg.nu * 2.0 / (h * h);
-    hipLaunchKernelGGL(burgers_sweep<T>, dim3((p.nx + 255) / 256), dim3(256), 0, s, x, xp, out, p.nx,
-                       (T)(alpha / D), c, info);
+    if (p.open)
+        hipLaunchKernelGGL(burgers_sweep_inlet<T>, dim3((p.nx + 255) / 256), dim3(256), 0, s, x, xp, out, p.nx,
+                           (T)(alpha / D), c, info);
+    else
+        hipLaunchKernelGGL(burgers_sweep<T>, dim3((p.nx + 255) / 256), dim3(256), 0, s, x, xp, out, p.nx,
+                           (T)(alpha / D), c, info);
     return hipGetLastError();
 }
 

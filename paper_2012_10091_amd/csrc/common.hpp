@@ -59,6 +59,41 @@ __device__ __forceinline__ void buf_store(double v, buf_t r, int voff, int soff)
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
+// Philox4x32-10 (Salmon et al., SC'11): per round the products M0*c0 and
+// M1*c2 are split into hi/lo words and the counter becomes
+// (hi1^c1^k0, lo1, hi0^c3^k1, lo0); the key advances by the Weyl constants
+// between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+    }
+}
+
+// Standard normal number k of member i at a cycle on a stream: counter
+// (k >> 1, i, cycle, stream), key = seed, 53-bit uniforms u = (m + 1/2) 2^-53
+// from word pairs, Box-Muller cos branch for even k and sin branch for odd k.
+__device__ __forceinline__ double philox_normal(uint64_t seed, uint64_t cycle, int i, int k, uint32_t stream) {
+    uint32_t c[4] = {(uint32_t)(k >> 1), (uint32_t)i, (uint32_t)cycle, stream};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) * 0x1p-53;
+    const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) * 0x1p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 6.283185307179586 * u2;
+    return (k & 1) ? rad * sin(ang) : rad * cos(ang);
+}
+
 // Four-point Lagrange basis on nodes -1, 0, 1, 2 evaluated at s in [0, 1).
 template <typename R>
 __host__ __device__ __forceinline__ void lagrange4(R s, R w[4]) {
@@ -67,6 +102,19 @@ __host__ __device__ __forceinline__ void lagrange4(R s, R w[4]) {
     w[1] = sp1 * sm1 * sm2 / R(2);
     w[2] = -sp1 * s * sm2 / R(2);
     w[3] = sp1 * s * sm1 / R(6);
+}
+
+// Pi_F on an open 1D grid (the inlet-forced case): fine node x uses the
+// cubic through coarse nodes b..b+3, b = clamp(x / r - 1, 0, nc - 4), so the
+// stencil turns one-sided at both ends.  Writes the weights and returns b.
+// In the interior b = x / r - 1 and the weights are those of the periodic
+// stencil (lagrange4 is a polynomial in s, valid outside [0, 1) too).
+template <typename R>
+__host__ __device__ __forceinline__ int open_cubic(int x, int r, int nc, R w[4]) {
+    int b = x / r - 1;
+    b = b < 0 ? 0 : (b > nc - 4 ? nc - 4 : b);
+    lagrange4<R>(R(x - (b + 1) * r) / R(r), w);
+    return b;
 }
 
 // (Pi_F d)(y, x): cubic Lagrange interpolation of a periodic coarse field
@@ -122,6 +170,10 @@ struct Plan {
     menkf_schedule sched[2];   // forecast schedule per level (0 fine, 1 coarse)
     double tuned_ms[2];        // forecast time of the autotuned schedule (0: not tuned)
     int tuned_nsteps[2];       // ... and the window it was timed on
+    // inlet-forced model: open grid (one-sided prolongation and observation),
+    // the trial member forecast of the parameter filter and its parameters
+    int open;
+    size_t off_trial, off_thf;
 };
 
 constexpr int CHOL_NB = 64;
@@ -130,6 +182,15 @@ constexpr int CHOL_NB = 64;
 // forecast
 hipError_t launch_burgers_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
                                    void *prev, void *ws, hipStream_t s);
+size_t inlet_window_lds(int n, size_t tsize);
+hipError_t launch_inlet_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev,
+                                 const double *theta, const double *t0, hipStream_t s);
+// dual EnKF parameter filter
+hipError_t launch_param_perturb(const Plan &p, const double *theta, double *thf, uint64_t seed, uint64_t cycle,
+                                void *ws, hipStream_t s);
+hipError_t launch_param_update(const Plan &p, const double *thf, double *tha, double *tmean, void *ws,
+                               hipStream_t s);
+hipError_t launch_clock_advance(double *clock, double dt_window, hipStream_t s);
 // stencil tile table of the 2D model
 int ns_tile_count(int precision);
 void ns_tile_shape(int precision, int i, int *tx, int *ty);
@@ -149,7 +210,7 @@ hipError_t launch_burgers_resid(const Plan &p, const void *x, const void *xp, vo
 // analysis
 hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, const double *yobs,
                        uint64_t seed, uint64_t cycle, const double *eps, const int32_t *idx,
-                       const int32_t *comp, void *ws, hipStream_t s);
+                       const int32_t *comp, void *ws, hipStream_t s, bool advance_cycle = true);
 hipError_t launch_get_gain(const Plan &p, double *z, void *ws, hipStream_t s);
 hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipStream_t s);
 hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, double *y,

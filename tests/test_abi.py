@@ -135,3 +135,58 @@ def test_schedule_defaults_and_validation():
         # the autotuner needs a workspace
         assert lib.menkf_autotune(h, 1, ctypes.c_void_p(1), 8, 1, 1, None, None, None) == -7
         lib.menkf_destroy(h)
+
+
+def _inlet(**kw):
+    base = dict(model=3, nx=800, ny=1, ratio=4, n_members=100, n_probes=80, dt=2e-4, length=10.0,
+                nu=0.005, obs_sigma=0.05, u0=1.0, omega=6.283185307179586, theta_sigma=(0.005, 0.005),
+                precision=1)
+    base.update(kw)
+    return _create(**base)
+
+
+def test_inlet_model_plans_the_parameter_filter():
+    st, h, lib = _inlet()
+    assert st == 0, lib.menkf_last_error(None)
+    n3 = ctypes.c_size_t()
+    assert lib.menkf_workspace_size(h, ctypes.byref(n3)) == 0
+    lib.menkf_destroy(h)
+    st, h, lib = _create(model=1, nx=800, ny=1, ratio=4, n_members=100, n_probes=80, dt=2e-4, length=10.0,
+                         nu=0.005, obs_sigma=0.05, precision=1)
+    assert st == 0
+    n1 = ctypes.c_size_t()
+    assert lib.menkf_workspace_size(h, ctypes.byref(n1)) == 0
+    lib.menkf_destroy(h)
+    # the trial member copy (100 x 200 doubles) and theta^f (100 x 2 doubles)
+    assert n3.value - n1.value >= 100 * 200 * 8 + 100 * 2 * 8
+    assert n3.value - n1.value < 100 * 200 * 8 + 100 * 2 * 8 + 1024
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=5296, ratio=4), -6),                # F64 row beyond the LDS window
+    (dict(nx=8196, ratio=4, precision=0), -6),   # F32 row beyond 8 points x 1024 threads
+    (dict(theta_sigma=(-1.0, 0.0)), -1),
+    (dict(u0=float("nan")), -1),
+    (dict(omega=float("inf")), -1),
+])
+def test_inlet_model_rejects(kw, code):
+    st, h, lib = _inlet(**kw)
+    assert st == code
+    assert not h.value
+
+
+def test_inlet_model_limits_are_accepted():
+    for kw in (dict(nx=5288, ratio=4), dict(nx=8192, ratio=4, precision=0)):
+        st, h, lib = _inlet(**kw)
+        assert st == 0, (kw, lib.menkf_last_error(None))
+        lib.menkf_destroy(h)
+
+
+def test_dual_calls_need_a_workspace():
+    st, h, lib = _inlet()
+    assert st == 0
+    one = ctypes.c_void_p(8)
+    assert lib.menkf_forecast_inlet(h, 1, one, 1, 1, None, one, one, None) == -7
+    assert lib.menkf_param_perturb(h, one, one, 1, 1, None) == -7
+    assert lib.menkf_param_update(h, one, one, one, None) == -7
+    lib.menkf_destroy(h)
