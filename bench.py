@@ -48,8 +48,10 @@ def parse():
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the forecast schedules first")
     ap.add_argument("--workload", default="ns2d_1024_256_n64",
-                    choices=["ns2d_1024_256_n64", "uneven48"],
-                    help="uneven48: the batch of 48 uneven instances in one graph (not the headline)")
+                    choices=["ns2d_1024_256_n64", "uneven48", "inlet_dual"],
+                    help="uneven48: the batch of 48 uneven instances in one graph; inlet_dual: the dual "
+                         "(parameter + state) filter of the inlet-forced Burgers case (neither is the headline)")
+    ap.add_argument("--dual-precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--lanes", type=int, default=4, help="streams of the uneven batch")
     ap.add_argument("--schedule", default=None,
                     help="fixed forecast schedules instead of autotuning, e.g. fine=64x8:0,coarse=32x8:32")
@@ -427,6 +429,141 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP64/FP32 operations per grid point and time step of the inlet forecast
+# kernel: per Runge-Kutta stage 8 for the right-hand side (centred
+# difference, product, second difference, scaling, sum) and 2 for
+# x + dt L; 3 each for the stage combinations of stages 2 and 3.
+INLET_FLOPS_PER_POINT_STEP = 3 * 10 + 2 * 3
+
+
+def dual_cpu_baseline(cfg, n_cycles=20):
+    """The FP64 oracle's dual cycle on a bounded sample of cycles (Sec. 4 size)."""
+    import numpy as np
+    from oracle import dual
+    from synthetic import fields
+    cores = len(os.sched_getaffinity(0))
+    idx, _ = fields.probes_for(cfg)
+    st = dual.DualState(fine=fields.inlet_uniform(cfg), members=fields.inlet_uniform(cfg, "coarse", cfg.n_members),
+                        theta=fields.inlet_theta_ics(cfg), t=0.0)
+    y = np.full(cfg.n_probes, cfg.u0)
+    t = time.perf_counter()
+    for _ in range(n_cycles):
+        st, _ = dual.dual_cycle(cfg, st, y, idx, n_sweeps=1)
+    sec = time.perf_counter() - t
+    return {"value": n_cycles / sec, "unit": "dual cycles/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_cycles} dual cycles of the oracle at the full size ({sec:.1f}s)"}
+
+
+def bench_dual(args):
+    """Dual (parameter + state) MEnKF of the inlet-forced Burgers case at the
+    Sec. 4 size: fine 800 nodes, coarse 200, 100 members, 80 sensors every 30
+    steps.  One step = one dual cycle (two member forecasts, fine forecast,
+    two gains, parameter and member updates, correction + sweep), captured as
+    one graph with the device cycle counter and clock.  Truth, spin-up and
+    observations are produced by the library on the GPU beforehand."""
+    import numpy as np
+    import torch
+
+    import paper_2012_10091_amd as m
+    from synthetic import configs, fields
+    cfg = configs.inlet_burgers(n_members=100, precision=args.dual_precision)
+    F64 = torch.float64
+    dt = F64 if cfg.precision == "f64" else torch.float32
+    ctx = m.Context(cfg)
+    idx, comp = fields.probes_for(cfg)
+    ctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+    dev = lambda a, ty=dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", ty).contiguous()
+    truth = dev(fields.inlet_uniform(cfg))
+    fine = dev(fields.inlet_uniform(cfg))
+    prev = torch.empty_like(fine)
+    mem = dev(fields.inlet_uniform(cfg, "coarse", cfg.n_members))
+    theta = dev(fields.inlet_theta_ics(cfg), F64)
+    th_true = dev(np.array([cfg.theta_true]), F64)
+    tmean = dev(fields.inlet_theta_ics(cfg).mean(axis=0), F64)
+    spin = int(round(cfg.t_spinup / cfg.dt))
+    t0 = torch.zeros(1, dtype=F64, device="cuda")
+    ctx.forecast_inlet(m.MENKF_FINE, truth, spin, th_true, t0)
+    ctx.forecast_inlet(m.MENKF_FINE, fine, spin, tmean, t0)
+    ctx.forecast_inlet(m.MENKF_COARSE, mem, spin, theta, t0)
+    n_cyc = args.warmup + args.steps
+    t_obs = torch.empty(1, dtype=F64, device="cuda")
+    Y = torch.empty((n_cyc, cfg.n_probes), dtype=F64, device="cuda")
+    for c in range(n_cyc):
+        t_obs.fill_(spin * cfg.dt + c * cfg.n_obs * cfg.dt)
+        ctx.forecast_inlet(m.MENKF_FINE, truth, cfg.n_obs, th_true, t_obs)
+        Y[c] = ctx.observe(m.MENKF_FINE, truth)[0] + dev(fields.obs_noise(cfg, c + 1), F64)
+    clock = torch.full((1,), spin * cfg.dt, dtype=F64, device="cuda")
+    xs = torch.empty((1, cfg.nxc), dtype=dt, device="cuda")
+    dc = torch.empty_like(xs)
+    y = torch.empty(cfg.n_probes, dtype=F64, device="cuda")
+    torch.cuda.synchronize()
+    log(f"bench: dual workload {cfg.name} {cfg.precision} ready (spin-up {spin} steps)")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx.set_cycle(1, stream=stream)
+        m.Graph.begin(stream)
+        ctx.dual_cycle(fine, prev, mem, xs, dc, y, theta, tmean, clock, cfg.seed + 5, m.MENKF_CYCLE_DEVICE,
+                       cfg.n_obs, n_sweeps=1, alpha=0.5, stream=stream)
+        g = m.Graph.end(stream)
+    for c in range(args.warmup):
+        with torch.cuda.stream(stream):
+            y.copy_(Y[c])
+        g.launch(stream)
+    stream.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for c in range(args.warmup, n_cyc):
+        with torch.cuda.stream(stream):
+            y.copy_(Y[c])
+        g.launch(stream)
+    e1.record(stream)
+    stream.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    cps = args.steps / sec
+    status = ctx.get_status()
+    th = tmean.cpu().numpy().tolist()
+    log(f"bench: dual {cps:.1f} cycles/s, theta mean after {n_cyc} cycles {th}, status {status}")
+    # dominant kernel: the member forecast (burgers_inlet_window), timed on its own stream
+    scratch = mem.clone()
+    reps = 20
+    with torch.cuda.stream(stream):
+        ctx.forecast_inlet(m.MENKF_COARSE, scratch, cfg.n_obs, theta, clock, stream=stream)
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.forecast_inlet(m.MENKF_COARSE, scratch, cfg.n_obs, theta, clock, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    avg_s = e0.elapsed_time(e1) / 1e3 / reps
+    flops = INLET_FLOPS_PER_POINT_STEP * cfg.n_members * cfg.nxc * cfg.n_obs
+    peak = FP64_VECTOR_PEAK_TFLOPS if cfg.precision == "f64" else FP32_VECTOR_PEAK_TFLOPS
+    achieved = flops / avg_s / 1e12
+    log(f"bench: member forecast {avg_s * 1e6:.1f} us per launch, {achieved:.3f} TFLOP/s")
+    out = {
+        "metric": "dual assimilation cycles/s, inlet-forced Burgers 800/200 N=100 (parameters + state)",
+        "value": cps, "unit": "dual cycles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 / cps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": cfg.precision, "data": "synthetic",
+        "config": {"workload": cfg.name, "fine": cfg.nx, "coarse": cfg.nxc, "members": cfg.n_members,
+                   "probes": cfg.n_probes, "steps_per_cycle": cfg.n_obs, "spinup_steps": spin,
+                   "theta_true": list(cfg.theta_true), "theta_prior": list(cfg.theta_prior),
+                   "theta_mean_after": th, "cycles_run": n_cyc, "status_word": status},
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None,
+            "kernel": f"burgers_inlet_window<{'double' if cfg.precision == 'f64' else 'float'}> "
+                      f"({cfg.n_members} members x {cfg.nxc} nodes x {cfg.n_obs} steps, LDS-resident)",
+            "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops,
+        },
+    }
+    if args.cpu_baseline:
+        log("bench: timing the oracle's dual cycle on the host (bounded sample)")
+        out["cpu_baseline"] = dual_cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
 def with_gain_mode(cfg, mode):
     """The workload configuration with another menkf gain mode."""
     import dataclasses
@@ -492,6 +629,8 @@ def main():
         sys.exit(2)
     if args.workload == "uneven48":
         return bench_batch(args)
+    if args.workload == "inlet_dual":
+        return bench_dual(args)
     if args.traffic_probe:
         return traffic_probe(args)
     import torch

@@ -620,32 +620,44 @@ __global__ __launch_bounds__(256) void update_bf16(float *__restrict__ X, float 
     }
 }
 
-// FP64 update for MENKF_F64 contexts: 64 points per workgroup, one thread per point.
-__global__ __launch_bounds__(64) void update_f64(double *__restrict__ X, double *__restrict__ dc,
-                                                 const double *__restrict__ zt, const double *__restrict__ zstar,
-                                                 int N, int npad, long long npts, double scale,
-                                                 const int32_t *__restrict__ info) {
-    extern __shared__ double xsd[];
+// FP64 update for MENKF_F64 contexts, in two passes so that both are
+// parallel over points and output members alike (the in-place update of
+// member j must not overwrite x^(j) while other workgroups still read it
+// for the mean):
+//   pass 1, one thread per point: A[i][p] = (x^(i)_p - mean_p) / sqrt(N - 1)
+//           into the workspace and delta^C_p = sum_i A[i][p] Z*[i];
+//   pass 2, one thread per (point, member j): x^(j)_p += sum_i A[i][p] Z[i, j]
+//           (j uniform per workgroup, so Z[., j] is read as scalars).
+__global__ __launch_bounds__(256) void update_anom_f64(const double *__restrict__ X, double *__restrict__ A,
+                                                       double *__restrict__ dc, const double *__restrict__ zstar,
+                                                       int N, long long npts, double scale,
+                                                       const int32_t *__restrict__ info) {
+    if (*info != 0) return;
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    double m = 0.0;
+    for (int i = 0; i < N; ++i) m += X[(long long)i * npts + p];
+    m /= (double)N;
+    double d = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double a = (X[(long long)i * npts + p] - m) * scale;
+        A[(long long)i * npts + p] = a;
+        d += a * zstar[i];
+    }
+    dc[p] = d;
+}
+
+__global__ __launch_bounds__(64) void update_apply_f64(double *__restrict__ X, const double *__restrict__ A,
+                                                       const double *__restrict__ zt, int N, int npad,
+                                                       long long npts, const int32_t *__restrict__ info) {
     if (*info != 0) return;
     const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
-    const bool ok = p < npts;
-    double m = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double v = ok ? X[(long long)i * npts + p] : 0.0;
-        xsd[i * 64 + threadIdx.x] = v;
-        m += v;
-    }
-    m /= (double)N;
-    for (int i = 0; i < N; ++i) xsd[i * 64 + threadIdx.x] = (xsd[i * 64 + threadIdx.x] - m) * scale;
-    if (!ok) return;
-    double d = 0.0;
-    for (int i = 0; i < N; ++i) d += xsd[i * 64 + threadIdx.x] * zstar[i];
-    dc[p] = d;
-    for (int j = 0; j < N; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < N; ++i) s += xsd[i * 64 + threadIdx.x] * zt[(long long)j * npad + i];
-        X[(long long)j * npts + p] += s;
-    }
+    const int j = blockIdx.y;
+    if (p >= npts) return;
+    const double *zj = zt + (long long)j * npad;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += A[(long long)i * npts + p] * zj[i];
+    X[(long long)j * npts + p] += s;
 }
 
 // ----------------------------------------------------------------- launchers
@@ -787,12 +799,14 @@ hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipSt
     const long long npts = p.nc * p.F;
     const int N = p.N;
     if (p.cfg.precision == MENKF_F64) {
-        const size_t lds = (size_t)N * 64 * sizeof(double);
-        hipError_t e = set_lds((const void *)update_f64, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(update_f64, dim3((unsigned)((npts + 63) / 64)), dim3(64), lds, s, (double *)members,
-                           (double *)dc, (const double *)(w + p.off_zt), (const double *)(w + p.off_zstar), N, p.npad,
-                           npts, 1.0 / sqrt((double)(N - 1)), info);
+        // the anomalies go to the coarse Runge-Kutta scratch (N x npts, idle between forecasts)
+        double *A = (double *)(w + p.off_c1);
+        hipLaunchKernelGGL(update_anom_f64, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s,
+                           (const double *)members, A, (double *)dc, (const double *)(w + p.off_zstar), N, npts,
+                           1.0 / sqrt((double)(N - 1)), info);
+        hipLaunchKernelGGL(update_apply_f64, dim3((unsigned)((npts + 63) / 64), (unsigned)N), dim3(64), 0, s,
+                           (double *)members, (const double *)A, (const double *)(w + p.off_zt), N, p.npad, npts,
+                           info);
         return hipGetLastError();
     }
     const int pw = p.npad <= 128 ? 128 : 64;
