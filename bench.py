@@ -52,6 +52,11 @@ def parse():
                     help="uneven48: the batch of 48 uneven instances in one graph; inlet_dual: the dual "
                          "(parameter + state) filter of the inlet-forced Burgers case (neither is the headline)")
     ap.add_argument("--dual-precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--theta-walk", type=float, default=None,
+                    help="standard deviation of the parameter random walk per analysis (default: the workload's)")
+    ap.add_argument("--dual-study", action="store_true",
+                    help="with --workload inlet_dual: the parameter estimate over the whole assimilation window "
+                         "for coarsening ratios 1, 2, 4, 8, 16 instead of the timing")
     ap.add_argument("--lanes", type=int, default=4, help="streams of the uneven batch")
     ap.add_argument("--schedule", default=None,
                     help="fixed forecast schedules instead of autotuning, e.g. fine=64x8:0,coarse=32x8:32")
@@ -501,11 +506,12 @@ def bench_dual(args):
     torch.cuda.synchronize()
     log(f"bench: dual workload {cfg.name} {cfg.precision} ready (spin-up {spin} steps)")
     stream = torch.cuda.Stream()
+    aux = torch.cuda.Stream()     # the fine forecast runs beside the member forecast
     with torch.cuda.stream(stream):
         ctx.set_cycle(1, stream=stream)
         m.Graph.begin(stream)
         ctx.dual_cycle(fine, prev, mem, xs, dc, y, theta, tmean, clock, cfg.seed + 5, m.MENKF_CYCLE_DEVICE,
-                       cfg.n_obs, n_sweeps=1, alpha=0.5, stream=stream)
+                       cfg.n_obs, n_sweeps=1, alpha=0.5, stream=stream, aux_stream=aux)
         g = m.Graph.end(stream)
     for c in range(args.warmup):
         with torch.cuda.stream(stream):
@@ -561,6 +567,106 @@ def bench_dual(args):
     if args.cpu_baseline:
         log("bench: timing the oracle's dual cycle on the host (bounded sample)")
         out["cpu_baseline"] = dual_cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+def dual_study(args):
+    """Parameter estimation of the inlet-forced case for r_C = 1, 2, 4, 8, 16
+    as in Sec. 4: everything starts from u0 at t = 0, runs freely to t = 10,
+    then one analysis every 30 steps up to t = 29 (3166 dual cycles).  The
+    truth (theta = (0.2, 0)) is a fine run of the library's own model; all
+    ratios see the same observations.  Prints one JSON line with theta-mean
+    traces and summary figures per ratio."""
+    import numpy as np
+    import torch
+
+    import paper_2012_10091_amd as m
+    from synthetic import configs, fields
+    F64 = torch.float64
+    ratios = (1, 2, 4, 8, 16)
+    base = configs.inlet_burgers(n_members=100, precision=args.dual_precision)
+    if args.theta_walk is not None:
+        base = base.with_(theta_walk=(args.theta_walk, args.theta_walk))
+    dt = F64 if base.precision == "f64" else torch.float32
+    dev = lambda a, ty=dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", ty).contiguous()
+    spin = int(round(base.t_spinup / base.dt))
+    n_cyc = base.n_cycles
+    # truth and observations (same for every ratio)
+    tctx = m.Context(base)
+    idx, comp = fields.probes_for(base)
+    tctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+    truth = dev(fields.inlet_uniform(base))
+    th_true = dev(np.array([base.theta_true]), F64)
+    t_obs = torch.zeros(1, dtype=F64, device="cuda")
+    tctx.forecast_inlet(m.MENKF_FINE, truth, spin, th_true, t_obs)
+    Y = torch.empty((n_cyc, base.n_probes), dtype=F64, device="cuda")
+    for c in range(n_cyc):
+        t_obs.fill_(spin * base.dt + c * base.n_obs * base.dt)
+        tctx.forecast_inlet(m.MENKF_FINE, truth, base.n_obs, th_true, t_obs)
+        Y[c] = tctx.observe(m.MENKF_FINE, truth)[0] + dev(fields.obs_noise(base, c + 1), F64)
+    truth_end = truth.clone()
+    torch.cuda.synchronize()
+    log(f"bench: dual study, {n_cyc} observation times ready")
+    out = {"study": "inlet_dual_theta", "precision": base.precision, "members": base.n_members,
+           "probes": base.n_probes, "window": [spin * base.dt, (spin + n_cyc * base.n_obs) * base.dt],
+           "theta_true": list(base.theta_true), "theta_prior": list(base.theta_prior),
+           "theta_walk": list(base.theta_walk), "ratios": {}}
+    every = 50
+    for r in ratios:
+        cfg = base.with_(ratio=r, name=f"burgers1d_inlet_800_r{r}_n100")
+        ctx = m.Context(cfg)
+        ctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+        theta = dev(fields.inlet_theta_ics(cfg), F64)
+        tmean = dev(fields.inlet_theta_ics(cfg).mean(axis=0), F64)
+        fine = dev(fields.inlet_uniform(cfg))
+        prev = torch.empty_like(fine)
+        mem = dev(fields.inlet_uniform(cfg, "coarse", cfg.n_members))
+        t0 = torch.zeros(1, dtype=F64, device="cuda")
+        ctx.forecast_inlet(m.MENKF_FINE, fine, spin, tmean, t0)
+        ctx.forecast_inlet(m.MENKF_COARSE, mem, spin, theta, t0)
+        clock = torch.full((1,), spin * cfg.dt, dtype=F64, device="cuda")
+        xs = torch.empty((1, cfg.nxc), dtype=dt, device="cuda")
+        dc = torch.empty_like(xs)
+        y = torch.empty(cfg.n_probes, dtype=F64, device="cuda")
+        hist = torch.empty((n_cyc, 2), dtype=F64, device="cuda")
+        stream = torch.cuda.Stream()
+        aux = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            ctx.set_cycle(1, stream=stream)
+            m.Graph.begin(stream)
+            ctx.dual_cycle(fine, prev, mem, xs, dc, y, theta, tmean, clock, cfg.seed + 5, m.MENKF_CYCLE_DEVICE,
+                           cfg.n_obs, n_sweeps=1, alpha=0.5, stream=stream, aux_stream=aux)
+            g = m.Graph.end(stream)
+        t = time.perf_counter()
+        for c in range(n_cyc):
+            with torch.cuda.stream(stream):
+                y.copy_(Y[c])
+            g.launch(stream)
+            with torch.cuda.stream(stream):
+                hist[c].copy_(tmean)
+        stream.synchronize()
+        wall = time.perf_counter() - t
+        h = hist.cpu().numpy()
+        status = ctx.get_status()
+        tc = cfg.n_obs * cfg.dt                      # time units per cycle (t_c = 1)
+        # converged: the running mean over one t_c stays within 0.01 (5 %) of the truth
+        w = int(round(1.0 / tc))
+        run = np.convolve(h[:, 0], np.ones(w) / w, mode="valid")     # run[k] = mean of cycles k..k+w-1
+        bad = np.nonzero(np.abs(run - cfg.theta_true[0]) >= 0.01)[0]
+        conv = (int(bad[-1]) + 1 if len(bad) else 0) + w              # end of the first good window
+        last = h[-int(round(5.0 / tc)):]             # the last 5 t_c
+        fe = float(torch.linalg.vector_norm(fine - truth_end) / torch.linalg.vector_norm(truth_end))
+        rec = {"coarse": cfg.nxc, "status": status, "wall_s": wall,
+               "t_converged_1tc_mean_within_0p01": None if conv > n_cyc else conv * tc,
+               "theta_mean_last5tc": last.mean(axis=0).tolist(), "theta_std_last5tc": last.std(axis=0).tolist(),
+               "theta_end": h[-1].tolist(), "fine_rel_err_end": fe,
+               "theta_after_cycles_1_10_50": [h[0].tolist(), h[9].tolist(), h[49].tolist()],
+               "trace_every_50_cycles": h[::every].round(5).tolist()}
+        out["ratios"][str(r)] = rec
+        log(f"bench: r={r}: theta end {h[-1]}, last-5tc mean {rec['theta_mean_last5tc']} "
+            f"std {rec['theta_std_last5tc']}, converged after {rec['t_converged_1tc_mean_within_0p01']} t_c, "
+            f"fine rel err {fe:.4f}, {wall:.1f}s")
     print(json.dumps(out), flush=True)
 
 
@@ -630,7 +736,7 @@ def main():
     if args.workload == "uneven48":
         return bench_batch(args)
     if args.workload == "inlet_dual":
-        return bench_dual(args)
+        return dual_study(args) if args.dual_study else bench_dual(args)
     if args.traffic_probe:
         return traffic_probe(args)
     import torch

@@ -381,22 +381,26 @@ menkf_status menkf_param_update(menkf_ctx *ctx, const double *theta_f_dev, doubl
                                 double *theta_mean_dev, menkf_stream stream);
 
 /* One dual cycle, issued on stream as
- *   menkf_restrict(fine, xstar)                      any x*: only Z[:, :N] is used next
- *   menkf_param_perturb(theta -> theta_f)            theta_f in the workspace
- *   trial = members; menkf_forecast_inlet(COARSE, trial, theta_f, clock)
- *   menkf_gain(trial, xstar, yobs, seed, cycle)      the cycle counter is not advanced here
+ *   theta_f = theta + tau (as menkf_param_perturb), trial = members      (workspace)
+ *   menkf_forecast_inlet(COARSE, trial, theta_f, clock)
+ *   menkf_gain(trial, members[0], yobs, seed, cycle)  any x* (only Z[:, :N] is used
+ *                                                    next); the cycle counter is not
+ *                                                    advanced here
  *   menkf_param_update(theta_f -> theta, theta_mean)
- *   menkf_forecast_inlet(COARSE, members, theta, clock)
  *   menkf_forecast_inlet(FINE, fine, theta_mean, clock), x_{k-1} into fine_prev
+ *   menkf_forecast_inlet(COARSE, members, theta, clock)
  *   menkf_restrict(fine, xstar)
  *   menkf_gain(members, xstar, yobs, seed, cycle)    the same perturbed observations
  *   menkf_update(members, deltac)
  *   menkf_prolong_smooth(deltac, fine, fine_prev, n_sweeps, alpha, PLAIN)
  *   clock += nsteps dt
  * theta (n_members x 2 doubles) is in/out, theta_mean (2 doubles) out,
- * clock (one double) in/out; the other buffers as for menkf_cycle.  A
- * non-positive pivot of the parameter gain leaves theta as it was; the
- * status word then reports the state gain's outcome only. */
+ * clock (one double) in/out; the other buffers as for menkf_cycle.
+ * aux_stream (optional, NULL = none, not stream itself): the fine forecast
+ * is issued there, forked from and joined back into stream with the
+ * context's two events, so it runs beside the member forecast; results are
+ * the same.  A non-positive pivot of the parameter gain leaves theta as it
+ * was; the status word then reports the state gain's outcome only. */
 typedef struct {
     menkf_ctx *ctx;
     void *fine, *fine_prev, *members, *xstar, *deltac;
@@ -405,6 +409,7 @@ typedef struct {
     uint64_t seed, cycle;
     int32_t nsteps, n_sweeps;
     double alpha;
+    menkf_stream aux_stream;
 } menkf_dual_args;
 
 menkf_status menkf_dual_cycle(const menkf_dual_args *args, menkf_stream stream);

@@ -92,6 +92,7 @@ class MenkfDualArgs(ctypes.Structure):
         ("seed", c_uint64), ("cycle", c_uint64),
         ("nsteps", c_int32), ("n_sweeps", c_int32),
         ("alpha", c_double),
+        ("aux_stream", c_void_p),
     ]
 
 

@@ -208,7 +208,7 @@ class Context:
                                                 _stream(stream)))
 
     def dual_args(self, fine, fine_prev, members, xstar, deltac, yobs, theta, theta_mean, clock, seed: int,
-                  cycle: int, nsteps: int, n_sweeps: int = 1, alpha: float = 0.5):
+                  cycle: int, nsteps: int, n_sweeps: int = 1, alpha: float = 0.5, aux_stream=None):
         """The menkf_dual_args of one dual cycle of this instance (buffers checked here)."""
         self._state(fine, self.fine_shape, "fine")
         self._state(fine_prev, self.fine_shape, "fine_prev")
@@ -230,12 +230,14 @@ class Context:
         a.theta, a.theta_mean, a.clock = _ptr(theta), _ptr(theta_mean), _ptr(clock)
         a.seed, a.cycle = seed, cycle
         a.nsteps, a.n_sweeps, a.alpha = nsteps, n_sweeps, alpha
+        if aux_stream is not None:
+            a.aux_stream = aux_stream.cuda_stream
         return a
 
     def dual_cycle(self, fine, fine_prev, members, xstar, deltac, yobs, theta, theta_mean, clock, seed: int,
-                   cycle: int, nsteps: int, n_sweeps: int = 1, alpha: float = 0.5, stream=None):
+                   cycle: int, nsteps: int, n_sweeps: int = 1, alpha: float = 0.5, stream=None, aux_stream=None):
         a = self.dual_args(fine, fine_prev, members, xstar, deltac, yobs, theta, theta_mean, clock, seed, cycle,
-                           nsteps, n_sweeps, alpha)
+                           nsteps, n_sweeps, alpha, aux_stream)
         self._check(self.lib.menkf_dual_cycle(ctypes.byref(a), _stream(stream)))
 
     def set_schedule(self, level: int, tile=(0, 0), member_chunk: int = 0):

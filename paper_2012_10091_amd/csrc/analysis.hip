@@ -621,43 +621,77 @@ __global__ __launch_bounds__(256) void update_bf16(float *__restrict__ X, float 
 }
 
 // FP64 update for MENKF_F64 contexts, in two passes so that both are
-// parallel over points and output members alike (the in-place update of
-// member j must not overwrite x^(j) while other workgroups still read it
-// for the mean):
-//   pass 1, one thread per point: A[i][p] = (x^(i)_p - mean_p) / sqrt(N - 1)
-//           into the workspace and delta^C_p = sum_i A[i][p] Z*[i];
-//   pass 2, one thread per (point, member j): x^(j)_p += sum_i A[i][p] Z[i, j]
-//           (j uniform per workgroup, so Z[., j] is read as scalars).
+// parallel over points and members alike (the in-place update of member j
+// must not overwrite x^(j) while other workgroups still read it for the
+// mean):
+//   pass 1: A[i][p] = (x^(i)_p - mean_p) / sqrt(N - 1) into the workspace and
+//           delta^C_p = sum_i A[i][p] Z*[i];  16 points x 16 member groups per
+//           workgroup, partial sums combined in LDS in a fixed order;
+//   pass 2: x^(j)_p += sum_i A[i][p] Z[i, j];  64 points x 4 member groups per
+//           workgroup and one j per grid row (Z[., j] read as scalars).
+constexpr int UPD_GRP = 16;
+
 __global__ __launch_bounds__(256) void update_anom_f64(const double *__restrict__ X, double *__restrict__ A,
                                                        double *__restrict__ dc, const double *__restrict__ zstar,
                                                        int N, long long npts, double scale,
                                                        const int32_t *__restrict__ info) {
+    __shared__ double part[UPD_GRP][UPD_GRP + 1];
+    __shared__ double mean[UPD_GRP];
     if (*info != 0) return;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npts) return;
-    double m = 0.0;
-    for (int i = 0; i < N; ++i) m += X[(long long)i * npts + p];
-    m /= (double)N;
-    double d = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double a = (X[(long long)i * npts + p] - m) * scale;
-        A[(long long)i * npts + p] = a;
-        d += a * zstar[i];
+    const int pl = threadIdx.x & (UPD_GRP - 1), g = threadIdx.x / UPD_GRP;
+    const long long p = (long long)blockIdx.x * UPD_GRP + pl;
+    const bool ok = p < npts;
+    double s = 0.0;
+    if (ok)
+        for (int i = g; i < N; i += UPD_GRP) s += X[(long long)i * npts + p];
+    part[g][pl] = s;
+    __syncthreads();
+    if (g == 0) {
+        double t = 0.0;
+        for (int k = 0; k < UPD_GRP; ++k) t += part[k][pl];
+        mean[pl] = t / (double)N;
     }
-    dc[p] = d;
+    __syncthreads();
+    const double m = mean[pl];
+    double d = 0.0;
+    if (ok)
+        for (int i = g; i < N; i += UPD_GRP) {
+            const double a = (X[(long long)i * npts + p] - m) * scale;
+            A[(long long)i * npts + p] = a;
+            d += a * zstar[i];
+        }
+    __syncthreads();   // every read of part[][] (the mean) is done
+    part[g][pl] = d;
+    __syncthreads();
+    if (g == 0 && ok) {
+        double t = 0.0;
+        for (int k = 0; k < UPD_GRP; ++k) t += part[k][pl];
+        dc[p] = t;
+    }
 }
 
-__global__ __launch_bounds__(64) void update_apply_f64(double *__restrict__ X, const double *__restrict__ A,
-                                                       const double *__restrict__ zt, int N, int npad,
-                                                       long long npts, const int32_t *__restrict__ info) {
+__global__ __launch_bounds__(256) void update_apply_f64(double *__restrict__ X, const double *__restrict__ A,
+                                                        const double *__restrict__ zt, int N, int npad,
+                                                        long long npts, const int32_t *__restrict__ info) {
+    __shared__ double part[4][64];
     if (*info != 0) return;
-    const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
+    const int pl = threadIdx.x & 63, g = threadIdx.x >> 6;   // g is uniform per wave
+    const long long p = (long long)blockIdx.x * 64 + pl;
     const int j = blockIdx.y;
-    if (p >= npts) return;
     const double *zj = zt + (long long)j * npad;
-    double s = 0.0;
-    for (int i = 0; i < N; ++i) s += A[(long long)i * npts + p] * zj[i];
-    X[(long long)j * npts + p] += s;
+    double s0 = 0.0, s1 = 0.0;
+    if (p < npts) {
+        int i = g;
+        for (; i + 4 < N; i += 8) {
+            s0 += A[(long long)i * npts + p] * zj[i];
+            s1 += A[(long long)(i + 4) * npts + p] * zj[i + 4];
+        }
+        if (i < N) s0 += A[(long long)i * npts + p] * zj[i];
+    }
+    part[g][pl] = s0 + s1;
+    __syncthreads();
+    if (g == 0 && p < npts)
+        X[(long long)j * npts + p] += (part[0][pl] + part[1][pl]) + (part[2][pl] + part[3][pl]);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -801,10 +835,10 @@ hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipSt
     if (p.cfg.precision == MENKF_F64) {
         // the anomalies go to the coarse Runge-Kutta scratch (N x npts, idle between forecasts)
         double *A = (double *)(w + p.off_c1);
-        hipLaunchKernelGGL(update_anom_f64, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(update_anom_f64, dim3((unsigned)((npts + UPD_GRP - 1) / UPD_GRP)), dim3(256), 0, s,
                            (const double *)members, A, (double *)dc, (const double *)(w + p.off_zstar), N, npts,
                            1.0 / sqrt((double)(N - 1)), info);
-        hipLaunchKernelGGL(update_apply_f64, dim3((unsigned)((npts + 63) / 64), (unsigned)N), dim3(64), 0, s,
+        hipLaunchKernelGGL(update_apply_f64, dim3((unsigned)((npts + 63) / 64), (unsigned)N), dim3(256), 0, s,
                            (double *)members, (const double *)A, (const double *)(w + p.off_zt), N, p.npad, npts,
                            info);
         return hipGetLastError();

@@ -577,24 +577,36 @@ menkf_status menkf_dual_cycle(const menkf_dual_args *a, menkf_stream stream) {
         !a->theta_mean || !a->clock)
         return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle: null buffer");
     if (a->nsteps < 1) return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle: nsteps must be >= 1");
+    if (a->aux_stream && a->aux_stream == stream)
+        return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle: aux_stream must differ from stream");
     if (!ctx->idx) return fail(ctx, MENKF_E_ARG, "probes not set (menkf_set_probes)");
     hipStream_t s = (hipStream_t)stream;
+    hipStream_t aux = (hipStream_t)a->aux_stream;
     char *w = (char *)ctx->ws;
     void *trial = w + p.off_trial;
     double *thf = (double *)(w + p.off_thf);
-    hipError_t e = launch_restrict(p, a->fine, a->xstar, s);
-    if (e == hipSuccess) e = launch_param_perturb(p, a->theta, thf, a->seed, a->cycle, ctx->ws, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(trial, a->members, (size_t)p.N * p.nc * p.F * p.tsize, hipMemcpyDeviceToDevice, s);
+    // parameter filter: theta_f and the trial members, their forecast and
+    // gain (any x* will do: only Z[:, :N] is used, so the first member
+    // serves), then theta_a and its mean
+    hipError_t e = launch_dual_prep(p, a->members, trial, a->theta, thf, a->seed, a->cycle, ctx->ws, s);
     if (e == hipSuccess) e = launch_inlet_forecast(p, MENKF_COARSE, trial, p.N, a->nsteps, nullptr, thf, a->clock, s);
     if (e == hipSuccess)
-        e = launch_gain(p, trial, a->xstar, a->yobs, a->seed, a->cycle, nullptr, ctx->idx, ctx->comp, ctx->ws, s,
+        e = launch_gain(p, trial, a->members, a->yobs, a->seed, a->cycle, nullptr, ctx->idx, ctx->comp, ctx->ws, s,
                         false);
     if (e == hipSuccess) e = launch_param_update(p, thf, a->theta, a->theta_mean, ctx->ws, s);
+    // state filter: members with theta_a, the fine run with its mean (on
+    // the second stream if given: one workgroup beside the members')
+    if (e == hipSuccess && aux) {
+        e = hipEventRecord(ctx->ev_fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(aux, ctx->ev_fork, 0);
+    }
+    if (e == hipSuccess)
+        e = launch_inlet_forecast(p, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->theta_mean, a->clock,
+                                  aux ? aux : s);
+    if (e == hipSuccess && aux) e = hipEventRecord(ctx->ev_join, aux);
     if (e == hipSuccess)
         e = launch_inlet_forecast(p, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, a->theta, a->clock, s);
-    if (e == hipSuccess)
-        e = launch_inlet_forecast(p, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->theta_mean, a->clock, s);
+    if (e == hipSuccess && aux) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_dual_cycle");
     menkf_status st = menkf_restrict(ctx, a->fine, a->xstar, stream);
     if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);

@@ -191,6 +191,8 @@ hipError_t launch_param_perturb(const Plan &p, const double *theta, double *thf,
 hipError_t launch_param_update(const Plan &p, const double *thf, double *tha, double *tmean, void *ws,
                                hipStream_t s);
 hipError_t launch_clock_advance(double *clock, double dt_window, hipStream_t s);
+hipError_t launch_dual_prep(const Plan &p, const void *members, void *trial, const double *theta, double *thf,
+                            uint64_t seed, uint64_t cycle, void *ws, hipStream_t s);
 // stencil tile table of the 2D model
 int ns_tile_count(int precision);
 void ns_tile_shape(int precision, int i, int *tx, int *ty);

@@ -64,6 +64,38 @@ __global__ void clock_advance(double *clock, double dt_window) {
     if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = clock[0] + dt_window;
 }
 
+// Start of a dual cycle in one launch: the trial copy of the members (the
+// parameter filter forecasts them with theta_f) and theta_f itself.
+template <typename T>
+__global__ __launch_bounds__(256) void dual_prep(const T *__restrict__ members, T *__restrict__ trial, long long n,
+                                                 const double *__restrict__ theta, double *__restrict__ thf, int N,
+                                                 double s0, double s1, uint64_t seed, uint64_t cycle,
+                                                 const uint64_t *__restrict__ dcycle) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) trial[q] = members[q];
+    if (q < (long long)N * DUAL_P) {
+        if (dcycle) cycle = *dcycle;
+        const int i = (int)q / DUAL_P, k = (int)q - i * DUAL_P;
+        thf[q] = theta[q] + (k == 0 ? s0 : s1) * philox_normal(seed, cycle, i, k, 0x5041u);
+    }
+}
+
+hipError_t launch_dual_prep(const Plan &p, const void *members, void *trial, const double *theta, double *thf,
+                            uint64_t seed, uint64_t cycle, void *ws, hipStream_t s) {
+    const uint64_t *dcycle =
+        cycle == MENKF_CYCLE_DEVICE ? (const uint64_t *)((char *)ws + p.off_info + 64) : nullptr;
+    const long long n = (long long)p.N * p.nc * p.F;
+    const long long work = n > (long long)p.N * DUAL_P ? n : (long long)p.N * DUAL_P;
+    const dim3 grid((unsigned)((work + 255) / 256));
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(dual_prep<double>, grid, dim3(256), 0, s, (const double *)members, (double *)trial, n, theta,
+                           thf, p.N, p.cfg.theta_sigma[0], p.cfg.theta_sigma[1], seed, cycle, dcycle);
+    else
+        hipLaunchKernelGGL(dual_prep<float>, grid, dim3(256), 0, s, (const float *)members, (float *)trial, n, theta,
+                           thf, p.N, p.cfg.theta_sigma[0], p.cfg.theta_sigma[1], seed, cycle, dcycle);
+    return hipGetLastError();
+}
+
 hipError_t launch_param_perturb(const Plan &p, const double *theta, double *thf, uint64_t seed, uint64_t cycle,
                                 void *ws, hipStream_t s) {
     const uint64_t *dcycle =

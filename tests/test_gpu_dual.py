@@ -199,9 +199,10 @@ class _Dev:
         self.y = torch.empty(cfg.n_probes, dtype=F64, device="cuda")
         self.ctx, self.cfg = ctx, cfg
 
-    def cycle(self, seed, c, n_sweeps, stream=None):
+    def cycle(self, seed, c, n_sweeps, stream=None, aux_stream=None):
         self.ctx.dual_cycle(self.fine, self.prev, self.mem, self.xs, self.dc, self.y, self.theta, self.tm,
-                            self.clock, seed, c, self.cfg.n_obs, n_sweeps=n_sweeps, alpha=0.5, stream=stream)
+                            self.clock, seed, c, self.cfg.n_obs, n_sweeps=n_sweeps, alpha=0.5, stream=stream,
+                            aux_stream=aux_stream)
 
 
 @pytest.mark.parametrize("cfg,tol,ncyc", [
@@ -235,7 +236,8 @@ def test_dual_cycles_match_oracle(cfg, tol, ncyc):
         assert to_np(dev.clock)[0] == st.t
 
 
-def test_dual_cycle_graph_replays_match_eager_calls():
+@pytest.mark.parametrize("aux", [False, True], ids=["one-stream", "fine-on-second-stream"])
+def test_dual_cycle_graph_replays_match_eager_calls(aux):
     from paper_2012_10091_amd import MENKF_CYCLE_DEVICE, Graph
     cfg = configs.inlet_burgers(nx=200, ratio=2, n_members=40, n_probes=20)
     ctx_a, idx, _ = make_ctx(cfg)
@@ -245,14 +247,15 @@ def test_dual_cycle_graph_replays_match_eager_calls():
     seed = 42
     ys = [truth[0, idx] + fields.obs_noise(cfg, c) for c in range(1, 6)]
     s = torch.cuda.Stream()
+    s_aux = torch.cuda.Stream() if aux else None
     with torch.cuda.stream(s):
         ctx_b.set_cycle(1, stream=s)
         Graph.begin(s)
-        b.cycle(seed, MENKF_CYCLE_DEVICE, 1, stream=s)
+        b.cycle(seed, MENKF_CYCLE_DEVICE, 1, stream=s, aux_stream=s_aux)
         g = Graph.end(s)
     torch.cuda.synchronize()
     for c, y in enumerate(ys, start=1):
-        say(f"dual graph replay {c}")
+        say(f"dual graph replay {c} (aux {aux})")
         a.y.copy_(torch.as_tensor(y, dtype=F64))
         a.cycle(seed, c, 1)
         with torch.cuda.stream(s):
