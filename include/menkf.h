@@ -62,7 +62,7 @@ typedef enum {
     MENKF_E_WORKSPACE = -7    /* workspace missing or too small */
 } menkf_status;
 
-enum { MENKF_BURGERS1D = 1, MENKF_NS2D = 2, MENKF_BURGERS1D_INLET = 3 };   /* model */
+enum { MENKF_BURGERS1D = 1, MENKF_NS2D = 2, MENKF_BURGERS1D_INLET = 3, MENKF_EULER1D_INLET = 4 };   /* model */
 enum { MENKF_F32 = 0, MENKF_F64 = 1 };                 /* precision */
 enum { MENKF_GAIN_EXACT_R = 0, MENKF_GAIN_SAMPLE_EE = 1, MENKF_GAIN_ENSEMBLE_SPACE = 2 };
 enum { MENKF_FINE = 0, MENKF_COARSE = 1 };             /* grid level */
@@ -88,6 +88,22 @@ enum { MENKF_PROLONG_PLAIN = 0, MENKF_PROLONG_LEARNED = 1, MENKF_PROLONG_LEARNED
  *              relaxed sweeps leave the inlet node to the boundary
  *              condition.  A state row lives in LDS during a forecast, so
  *              nx <= 5290 (F64) or 8192 (F32).
+ *              MENKF_EULER1D_INLET: the inviscid 1D Euler equations of the
+ *              acoustic case of Sec. 5 in conservative variables (rho,
+ *              rho u, rho E; F = 3) on the same open grid, in
+ *              characteristic units (u0 + a = 1, rho0 = 1, so a = 1/(1+mach),
+ *              u0 = mach a, p0 = a^2/gamma; the u0 field is not used):
+ *              centred second-order flux differences, forward Euler in time
+ *              (a single matrix-splitting iteration from x_{k-1} is that
+ *              step, the centred inviscid operator having no diagonal),
+ *              then the centred explicit filter x + (-1)^(p+1) filter_sigma
+ *              delta^(2p) x / 4^p of order 2p = 6 on nodes 3..n-4, 4 on
+ *              nodes 2 and n-3, 2 on nodes 1 and n-2.  Inlet node (rho0,
+ *              rho0 u0 (1 + theta_1 sin(omega t + theta_2)), rho0 E0) at the
+ *              end of every step, outlet node extrapolated linearly after
+ *              the filter.  Observations read rho u (component 0 = rho u);
+ *              the relaxed sweeps use the diagonal 1.  nx <= 1792 (F64) or
+ *              3612 (F32), coarse grid >= 8 nodes.
  *   precision  MENKF_F32: float states and stencils, BF16 member-update
  *              products with FP32 accumulation, FP64 innovation covariance
  *              (S = Y Y^T + R), Cholesky and gain of x*.
@@ -125,6 +141,8 @@ typedef struct {
      * filter's parameter forecast (Algo. 2 step 1). */
     double u0, omega;
     double theta_sigma[2];
+    /* MENKF_EULER1D_INLET only: strength of the explicit filter, in [0, 1]. */
+    double filter_sigma;
 } menkf_config;
 
 /* Create / destroy a context for the current HIP device.  The context owns

@@ -1,4 +1,5 @@
-"""Dual EnKF parameter estimation on the inlet-forced 1D Burgers case.
+"""Dual EnKF parameter estimation on the inlet-forced 1D cases (Burgers of
+Sec. 4; the Euler acoustic case of Sec. 5 through oracle.euler1d).
 
 Test oracle: plain FP64 NumPy, used by the tests only.
 
@@ -68,10 +69,32 @@ def prolong_open(xc, ratio):
     return xc @ prolong_matrix_open(xc.shape[-1], ratio).T
 
 
-def observe_coarse_open(xc, idx, ratio):
-    """H^C = H^F o Pi_F at the probe nodes for coarse states (..., 1, n_c)."""
+def observe_coarse_open(xc, idx, ratio, field=0):
+    """H^C = H^F o Pi_F at the probe nodes for coarse states (..., F, n_c):
+    the observed field (u for Burgers, rho u for Euler) prolonged and sampled."""
     P = prolong_matrix_open(np.asarray(xc).shape[-1], ratio)
-    return np.asarray(xc, dtype=np.float64)[..., 0, :] @ P[np.asarray(idx, dtype=np.int64)].T
+    return np.asarray(xc, dtype=np.float64)[..., field, :] @ P[np.asarray(idx, dtype=np.int64)].T
+
+
+def observed_field(cfg):
+    return 1 if getattr(cfg, "eq", "burgers") == "euler" else 0
+
+
+def model_forecast(cfg, x, t0, nsteps, theta, level):
+    """The inlet-forced forecast of the configuration's equations on a level."""
+    n = cfg.nx if level == "fine" else cfg.nxc
+    h = cfg.length / n
+    if getattr(cfg, "eq", "burgers") == "euler":
+        from . import euler1d
+        return euler1d.forecast(x, t0, nsteps, cfg.dt, theta, h, cfg.gamma, cfg.mach, cfg.omega, cfg.filter_sigma)
+    return inlet_forecast(x, t0, nsteps, cfg.dt, theta, cfg.nu, h, cfg.u0, cfg.omega)
+
+
+def model_smooth(cfg, x, x_prev, n_sweeps, alpha):
+    if getattr(cfg, "eq", "burgers") == "euler":
+        from . import euler1d
+        return euler1d.sweep(x, x_prev, cfg.dt, cfg.length / cfg.nx, cfg.gamma, alpha, n_sweeps)
+    return smooth_open(x, x_prev, cfg, n_sweeps, alpha)
 
 
 # ------------------------------------------------------------------ model
@@ -182,24 +205,25 @@ def dual_cycle(cfg, st: DualState, y_obs, idx, n_sweeps=1, alpha=0.5, seed=None)
     c = st.cycle + 1
     seed = cfg.seed + 5 if seed is None else seed
     N, r = cfg.n_members, cfg.ratio
-    hf, hc = cfg.length / cfg.nx, cfg.length / cfg.nxc
     eps = rng.perturbations(seed, c, N, cfg.n_probes, cfg.obs_sigma)
 
+    fld = observed_field(cfg)
+
     def H(xc):
-        return observe_coarse_open(xc, idx, r)
+        return observe_coarse_open(xc, idx, r, fld)
 
     # parameter forecast, member forecast with theta^f, parameter update
     theta_f = st.theta + param_perturbations(seed, c, N, cfg.theta_walk)
-    mem_f, _ = inlet_forecast(st.members, st.t, cfg.n_obs, cfg.dt, theta_f, cfg.nu, hc, cfg.u0, cfg.omega)
+    mem_f, _ = model_forecast(cfg, st.members, st.t, cfg.n_obs, theta_f, "coarse")
     xstar0 = restrict_open(st.fine, r)     # any x*: the parameter update uses only the D columns
     res_p = enkf.analysis(mem_f, xstar0, y_obs, eps, H, cfg.obs_sigma)
     theta_a = param_update(theta_f, res_p["Z"])
     theta_bar = theta_a.mean(axis=0)
     # member forecast again with theta^a, fine forecast with the mean
-    mem_f2, _ = inlet_forecast(st.members, st.t, cfg.n_obs, cfg.dt, theta_a, cfg.nu, hc, cfg.u0, cfg.omega)
-    xf, xprev = inlet_forecast(st.fine, st.t, cfg.n_obs, cfg.dt, theta_bar, cfg.nu, hf, cfg.u0, cfg.omega)
+    mem_f2, _ = model_forecast(cfg, st.members, st.t, cfg.n_obs, theta_a, "coarse")
+    xf, xprev = model_forecast(cfg, st.fine, st.t, cfg.n_obs, theta_bar, "fine")
     xstar = restrict_open(xf, r)
     res = enkf.analysis(mem_f2, xstar, y_obs, eps, H, cfg.obs_sigma)
     x = correct_open(xf, res["delta"], r)
-    x = smooth_open(x, xprev, cfg, n_sweeps, alpha)
+    x = model_smooth(cfg, x, xprev, n_sweeps, alpha)
     return DualState(fine=x, members=res["members"], theta=theta_a, t=st.t + cfg.n_obs * cfg.dt, cycle=c), theta_bar

@@ -6,7 +6,7 @@ include/menkf.h); this package only loads it and marshals torch tensors.
 
 from .binding import (  # noqa: F401
     Batch, Context, Graph, MenkfError, Net, Trainer, pack_params, unpack_params, config_from, make_config, ram_ratio, last_error,
-    MENKF_BURGERS1D, MENKF_NS2D, MENKF_BURGERS1D_INLET, MENKF_F32, MENKF_F64, MENKF_GAIN_EXACT_R, MENKF_GAIN_SAMPLE_EE, MENKF_GAIN_ENSEMBLE_SPACE,
+    MENKF_BURGERS1D, MENKF_NS2D, MENKF_BURGERS1D_INLET, MENKF_EULER1D_INLET, MENKF_F32, MENKF_F64, MENKF_GAIN_EXACT_R, MENKF_GAIN_SAMPLE_EE, MENKF_GAIN_ENSEMBLE_SPACE,
     MENKF_FINE, MENKF_COARSE, MENKF_PROLONG_PLAIN, MENKF_PROLONG_LEARNED, MENKF_PROLONG_LEARNED_FALLBACK,
     MENKF_CYCLE_DEVICE,
 )

@@ -31,6 +31,7 @@ class MenkfConfig(ctypes.Structure):
         ("anomaly_terms", c_int32),
         ("u0", c_double), ("omega", c_double),
         ("theta_sigma", c_double * 2),
+        ("filter_sigma", c_double),
     ]
 
 

@@ -17,6 +17,7 @@ from . import _lib
 MENKF_BURGERS1D = 1
 MENKF_NS2D = 2
 MENKF_BURGERS1D_INLET = 3
+MENKF_EULER1D_INLET = 4
 MENKF_F32 = 0
 MENKF_F64 = 1
 MENKF_GAIN_EXACT_R = 0
@@ -52,10 +53,10 @@ def _stream(stream=None):
 def make_config(model, nx, ny, ratio, n_members, n_probes, dt, precision=MENKF_F32,
                 gain_mode=MENKF_GAIN_EXACT_R, length=6.283185307179586, nu=0.0, gamma=1.4,
                 mach=0.3, reynolds=1000.0, prandtl=0.71, obs_sigma=0.01, anomaly_terms=0, u0=1.0, omega=0.0,
-                theta_sigma=(0.0, 0.0)) -> _lib.MenkfConfig:
+                theta_sigma=(0.0, 0.0), filter_sigma=0.0) -> _lib.MenkfConfig:
     return _lib.MenkfConfig(model, precision, gain_mode, nx, ny, ratio, n_members, n_probes,
                             length, dt, nu, gamma, mach, reynolds, prandtl, obs_sigma, anomaly_terms,
-                            u0, omega, (ctypes.c_double * 2)(*theta_sigma))
+                            u0, omega, (ctypes.c_double * 2)(*theta_sigma), filter_sigma)
 
 
 def config_from(cfg) -> _lib.MenkfConfig:
@@ -63,7 +64,10 @@ def config_from(cfg) -> _lib.MenkfConfig:
     if cfg.dim == 2:
         model = MENKF_NS2D
     else:
-        model = MENKF_BURGERS1D_INLET if getattr(cfg, "bc", "periodic") == "inlet" else MENKF_BURGERS1D
+        if getattr(cfg, "bc", "periodic") != "inlet":
+            model = MENKF_BURGERS1D
+        else:
+            model = MENKF_EULER1D_INLET if getattr(cfg, "eq", "burgers") == "euler" else MENKF_BURGERS1D_INLET
     return make_config(
         model, cfg.nx, cfg.ny, cfg.ratio, cfg.n_members,
         cfg.n_probes, cfg.dt, precision=MENKF_F64 if cfg.precision == "f64" else MENKF_F32,
@@ -71,7 +75,7 @@ def config_from(cfg) -> _lib.MenkfConfig:
         gamma=cfg.gamma, mach=cfg.mach, reynolds=cfg.reynolds, prandtl=cfg.prandtl,
         obs_sigma=cfg.obs_sigma, anomaly_terms=getattr(cfg, "anomaly_terms", 0),
         u0=getattr(cfg, "u0", 1.0), omega=getattr(cfg, "omega", 0.0),
-        theta_sigma=tuple(getattr(cfg, "theta_walk", (0.0, 0.0))))
+        theta_sigma=tuple(getattr(cfg, "theta_walk", (0.0, 0.0))), filter_sigma=getattr(cfg, "filter_sigma", 0.0))
 
 
 def ram_ratio(dim: int, ratio: int, n_members: int) -> float:
@@ -96,7 +100,7 @@ class Context:
         self.handle = h
         c = self.c_cfg
         self.dim = 2 if c.model == MENKF_NS2D else 1
-        self.F = 4 if self.dim == 2 else 1
+        self.F = 4 if self.dim == 2 else (3 if c.model == MENKF_EULER1D_INLET else 1)
         self.dtype = torch.float64 if c.precision == MENKF_F64 else torch.float32
         self.nx, self.ny, self.ratio = c.nx, c.ny, c.ratio
         self.nxc = c.nx // c.ratio

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void obs_eval(const T *__restrict__ states, lo
                                                 const T *__restrict__ extra, const int32_t *__restrict__ idx,
                                                 const int32_t *__restrict__ comp, int Ny, double *__restrict__ y,
                                                 int ldy, int coarse, int dim, int nx, int ny, int r, int nxc,
-                                                int nyc, int open) {
+                                                int nyc, int open, int obs_field) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int sidx = blockIdx.y;
     if (p >= Ny) return;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void obs_eval(const T *__restrict__ states, lo
     double val;
     if (!coarse) {
         if (dim == 1) {
-            val = (double)st[node];
+            val = (double)st[(long long)obs_field * nx + node];
         } else {
             const long long nf = (long long)nx * ny;
             const double rho = (double)st[node];
@@ -75,9 +75,10 @@ __global__ __launch_bounds__(256) void obs_eval(const T *__restrict__ states, lo
         lagrange4<double>((double)mx / (double)r, wx);
         if (dim == 1 && open) {
             const int b0 = open_cubic<double>(fx, r, nxc, wx);
+            const T *sf = st + (long long)obs_field * nxc;
             double a = 0.0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) a += wx[b] * (double)st[b0 + b];
+            for (int b = 0; b < 4; ++b) a += wx[b] * (double)sf[b0 + b];
             val = a;
         } else if (dim == 1) {
             double a = 0.0;
@@ -707,11 +708,11 @@ hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, d
     if (p.cfg.precision == MENKF_F64)
         hipLaunchKernelGGL(obs_eval<double>, grid, dim3(256), 0, s, (const double *)state, stride, nb,
                            (const double *)nullptr, idx, comp, p.Ny, y, p.Ny, coarse ? 1 : 0, p.dim, p.nx, p.ny,
-                           p.cfg.ratio, p.nxc, p.nyc, p.open);
+                           p.cfg.ratio, p.nxc, p.nyc, p.open, p.obs_field);
     else
         hipLaunchKernelGGL(obs_eval<float>, grid, dim3(256), 0, s, (const float *)state, stride, nb,
                            (const float *)nullptr, idx, comp, p.Ny, y, p.Ny, coarse ? 1 : 0, p.dim, p.nx, p.ny,
-                           p.cfg.ratio, p.nxc, p.nyc, p.open);
+                           p.cfg.ratio, p.nxc, p.nyc, p.open, p.obs_field);
     return hipGetLastError();
 }
 
@@ -774,11 +775,11 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     if (f64)
         hipLaunchKernelGGL(obs_eval<double>, g1, dim3(256), 0, s, (const double *)members, stride, N,
                            (const double *)xstar, idx, comp, p.Ny, yraw, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
-                           p.nxc, p.nyc, p.open);
+                           p.nxc, p.nyc, p.open, p.obs_field);
     else
         hipLaunchKernelGGL(obs_eval<float>, g1, dim3(256), 0, s, (const float *)members, stride, N,
                            (const float *)xstar, idx, comp, p.Ny, yraw, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
-                           p.nxc, p.nyc, p.open);
+                           p.nxc, p.nyc, p.open, p.obs_field);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 2. clear the Schur block, reset status
     hipLaunchKernelGGL(zero_extra, dim3(256), dim3(256), 0, s, A, p.ld, p.nyp, p.mext, info);

@@ -61,16 +61,20 @@ static int roundup(int v, int m) { return (v + m - 1) / m * m; }
 static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     std::memset(p, 0, sizeof(*p));
     p->cfg = *cfg;
-    if (cfg->model != MENKF_BURGERS1D && cfg->model != MENKF_NS2D && cfg->model != MENKF_BURGERS1D_INLET)
-        return fail(nullptr, MENKF_E_ARG, "model must be MENKF_BURGERS1D, MENKF_NS2D or MENKF_BURGERS1D_INLET (got %d)",
+    if (cfg->model != MENKF_BURGERS1D && cfg->model != MENKF_NS2D && cfg->model != MENKF_BURGERS1D_INLET &&
+        cfg->model != MENKF_EULER1D_INLET)
+        return fail(nullptr, MENKF_E_ARG,
+                    "model must be MENKF_BURGERS1D, MENKF_NS2D, MENKF_BURGERS1D_INLET or MENKF_EULER1D_INLET (got %d)",
                     cfg->model);
     if (cfg->precision != MENKF_F32 && cfg->precision != MENKF_F64)
         return fail(nullptr, MENKF_E_ARG, "precision must be MENKF_F32 or MENKF_F64 (got %d)", cfg->precision);
     if (cfg->gain_mode != MENKF_GAIN_EXACT_R && cfg->gain_mode != MENKF_GAIN_SAMPLE_EE &&
         cfg->gain_mode != MENKF_GAIN_ENSEMBLE_SPACE)
         return fail(nullptr, MENKF_E_ARG, "unknown gain_mode %d", cfg->gain_mode);
+    const bool euler = cfg->model == MENKF_EULER1D_INLET;
     p->dim = cfg->model == MENKF_NS2D ? 2 : 1;
-    p->F = p->dim == 2 ? 4 : 1;
+    p->F = p->dim == 2 ? 4 : (euler ? 3 : 1);
+    p->obs_field = euler ? 1 : 0;
     const int r = cfg->ratio;
     if (r < 1 || r > 64) return fail(nullptr, MENKF_E_ARG, "ratio must be in [1, 64] (got %d)", r);
     if (cfg->nx < 1 || cfg->nx % r) return fail(nullptr, MENKF_E_SHAPE, "nx=%d must be a positive multiple of ratio=%d", cfg->nx, r);
@@ -93,15 +97,28 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
     if (cfg->n_probes < 1) return fail(nullptr, MENKF_E_ARG, "n_probes must be >= 1 (got %d)", cfg->n_probes);
     if (!(cfg->dt > 0) || !(cfg->length > 0)) return fail(nullptr, MENKF_E_ARG, "dt and length must be positive");
     if (p->dim == 1 && !(cfg->nu >= 0)) return fail(nullptr, MENKF_E_ARG, "nu must be >= 0");
-    p->open = cfg->model == MENKF_BURGERS1D_INLET ? 1 : 0;
+    p->open = (cfg->model == MENKF_BURGERS1D_INLET || euler) ? 1 : 0;
+    if (euler) {
+        if (!(cfg->gamma > 1) || !(cfg->mach > 0 && cfg->mach < 1))
+            return fail(nullptr, MENKF_E_ARG, "MENKF_EULER1D_INLET needs gamma > 1 and a subsonic inlet, 0 < mach < 1");
+        if (!(cfg->filter_sigma >= 0 && cfg->filter_sigma <= 1))
+            return fail(nullptr, MENKF_E_ARG, "filter_sigma must be in [0, 1]");
+        if (cfg->nx / cfg->ratio < 8)
+            return fail(nullptr, MENKF_E_SHAPE, "MENKF_EULER1D_INLET needs >= 8 coarse nodes (filter stencils)");
+        const size_t ts = cfg->precision == MENKF_F64 ? 8 : 4;
+        if (cfg->nx > 4096 || euler_window_lds(cfg->nx, ts) > 128 * 1024)
+            return fail(nullptr, MENKF_E_UNSUPPORTED,
+                        "MENKF_EULER1D_INLET keeps a state in LDS: nx = %d exceeds %d", cfg->nx,
+                        cfg->precision == MENKF_F64 ? 1792 : 3612);
+    }
     if (p->open) {
-        if (!std::isfinite(cfg->u0) || !std::isfinite(cfg->omega))
-            return fail(nullptr, MENKF_E_ARG, "MENKF_BURGERS1D_INLET needs finite u0 and omega");
+        if ((!euler && !std::isfinite(cfg->u0)) || !std::isfinite(cfg->omega))
+            return fail(nullptr, MENKF_E_ARG, "the inlet-forced models need finite u0 (Burgers) and omega");
         if (!(cfg->theta_sigma[0] >= 0) || !(cfg->theta_sigma[1] >= 0) || !std::isfinite(cfg->theta_sigma[0]) ||
             !std::isfinite(cfg->theta_sigma[1]))
             return fail(nullptr, MENKF_E_ARG, "theta_sigma must be finite and >= 0");
         const size_t ts = cfg->precision == MENKF_F64 ? 8 : 4;
-        if (cfg->nx > 8192 || inlet_window_lds(cfg->nx, ts) > 128 * 1024)
+        if (!euler && (cfg->nx > 8192 || inlet_window_lds(cfg->nx, ts) > 128 * 1024))
             return fail(nullptr, MENKF_E_UNSUPPORTED,
                         "MENKF_BURGERS1D_INLET keeps a state row in LDS: nx = %d exceeds %d", cfg->nx,
                         cfg->precision == MENKF_F64 ? 5290 : 8192);
@@ -249,7 +266,7 @@ menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state, int32_t 
     if (level == MENKF_FINE && nb != 1) return fail(ctx, MENKF_E_ARG, "the fine level takes nb = 1 (got %d)", nb);
     if (level == MENKF_COARSE && (nb < 1 || nb > p.N))
         return fail(ctx, MENKF_E_ARG, "coarse nb must be in [1, %d] (got %d)", p.N, nb);
-    if (p.open) return fail(ctx, MENKF_E_ARG, "MENKF_BURGERS1D_INLET forecasts need parameters: menkf_forecast_inlet");
+    if (p.open) return fail(ctx, MENKF_E_ARG, "the inlet-forced models' forecasts need parameters: menkf_forecast_inlet");
     const hipError_t e = p.dim == 1 ? launch_burgers_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream)
                                     : launch_ns_forecast(p, level, state, nb, nsteps, prev, ctx->ws, (hipStream_t)stream);
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_forecast");
@@ -538,7 +555,7 @@ menkf_status menkf_forecast_inlet(menkf_ctx *ctx, int32_t level, void *state, in
                                   const double *theta, const double *t0, menkf_stream stream) {
     NEED_WS(ctx);
     const Plan &p = ctx->plan;
-    if (!p.open) return fail(ctx, MENKF_E_ARG, "menkf_forecast_inlet needs a MENKF_BURGERS1D_INLET context");
+    if (!p.open) return fail(ctx, MENKF_E_ARG, "menkf_forecast_inlet needs an inlet-forced context");
     if (level != MENKF_FINE && level != MENKF_COARSE) return fail(ctx, MENKF_E_ARG, "bad level %d", level);
     if (!state || !theta || !t0) return fail(ctx, MENKF_E_ARG, "null pointer");
     if (nsteps < 1) return fail(ctx, MENKF_E_ARG, "nsteps must be >= 1 (got %d)", nsteps);
@@ -552,7 +569,7 @@ menkf_status menkf_forecast_inlet(menkf_ctx *ctx, int32_t level, void *state, in
 menkf_status menkf_param_perturb(menkf_ctx *ctx, const double *theta, double *theta_f, uint64_t seed, uint64_t cycle,
                                  menkf_stream stream) {
     NEED_WS(ctx);
-    if (!ctx->plan.open) return fail(ctx, MENKF_E_ARG, "menkf_param_perturb needs a MENKF_BURGERS1D_INLET context");
+    if (!ctx->plan.open) return fail(ctx, MENKF_E_ARG, "menkf_param_perturb needs an inlet-forced context");
     if (!theta || !theta_f) return fail(ctx, MENKF_E_ARG, "null pointer");
     const hipError_t e = launch_param_perturb(ctx->plan, theta, theta_f, seed, cycle, ctx->ws, (hipStream_t)stream);
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_param_perturb");
@@ -561,7 +578,7 @@ menkf_status menkf_param_perturb(menkf_ctx *ctx, const double *theta, double *th
 menkf_status menkf_param_update(menkf_ctx *ctx, const double *theta_f, double *theta_a, double *theta_mean,
                                 menkf_stream stream) {
     NEED_WS(ctx);
-    if (!ctx->plan.open) return fail(ctx, MENKF_E_ARG, "menkf_param_update needs a MENKF_BURGERS1D_INLET context");
+    if (!ctx->plan.open) return fail(ctx, MENKF_E_ARG, "menkf_param_update needs an inlet-forced context");
     if (!theta_f || !theta_a || !theta_mean) return fail(ctx, MENKF_E_ARG, "null pointer");
     const hipError_t e = launch_param_update(ctx->plan, theta_f, theta_a, theta_mean, ctx->ws, (hipStream_t)stream);
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_param_update");
@@ -572,7 +589,7 @@ menkf_status menkf_dual_cycle(const menkf_dual_args *a, menkf_stream stream) {
     menkf_ctx *ctx = a->ctx;
     NEED_WS(ctx);
     const Plan &p = ctx->plan;
-    if (!p.open) return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle needs a MENKF_BURGERS1D_INLET context");
+    if (!p.open) return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle needs an inlet-forced context");
     if (!a->fine || !a->fine_prev || !a->members || !a->xstar || !a->deltac || !a->yobs || !a->theta ||
         !a->theta_mean || !a->clock)
         return fail(ctx, MENKF_E_ARG, "menkf_dual_cycle: null buffer");

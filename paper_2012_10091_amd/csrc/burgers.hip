@@ -352,6 +352,7 @@ static hipError_t inlet_forecast_t(const Plan &p, int level, T *state, int nb, i
 
 hipError_t launch_inlet_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev,
                                  const double *theta, const double *t0, hipStream_t s) {
+    if (p.cfg.model == MENKF_EULER1D_INLET) return launch_euler_forecast(p, level, state, nb, nsteps, prev, theta, t0, s);
     if (p.cfg.precision == MENKF_F64)
         return inlet_forecast_t<double>(p, level, (double *)state, nb, nsteps, (double *)prev, theta, t0, s);
     return inlet_forecast_t<float>(p, level, (float *)state, nb, nsteps, (float *)prev, theta, t0, s);

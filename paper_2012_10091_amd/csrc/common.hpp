@@ -173,6 +173,7 @@ struct Plan {
     // inlet-forced model: open grid (one-sided prolongation and observation),
     // the trial member forecast of the parameter filter and its parameters
     int open;
+    int obs_field;             // field the 1D observation reads (rho u for the Euler model)
     size_t off_trial, off_thf;
 };
 
@@ -183,6 +184,11 @@ constexpr int CHOL_NB = 64;
 hipError_t launch_burgers_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
                                    void *prev, void *ws, hipStream_t s);
 size_t inlet_window_lds(int n, size_t tsize);
+size_t euler_window_lds(int n, size_t tsize);
+hipError_t launch_euler_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev,
+                                 const double *theta, const double *t0, hipStream_t s);
+hipError_t launch_euler_sweep(const Plan &p, const void *x, const void *xp, void *out, double alpha,
+                              const int32_t *info, hipStream_t s);
 hipError_t launch_inlet_forecast(const Plan &p, int level, void *state, int nb, int nsteps, void *prev,
                                  const double *theta, const double *t0, hipStream_t s);
 // dual EnKF parameter filter

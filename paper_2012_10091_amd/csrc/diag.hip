@@ -1,5 +1,6 @@
 // Diagnostics (Sec. 4, relative RMSE): sum (xa - xt)^2 and sum xt^2 over
-// the observed quantity (u in 1D, (u, v) = momentum/density in 2D) and the
+// the observed quantity (u in 1D Burgers, rho u in 1D Euler, (u, v) =
+// momentum/density in 2D) and the
 // count of non-finite entries of xa.  Deterministic two-pass reduction in
 // FP64: fixed per-block partials, then one block sums them in order.
 #include "common.hpp"
@@ -59,6 +60,10 @@ __global__ __launch_bounds__(64) void diag_final(const double *__restrict__ part
 hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, double *out, void *ws, hipStream_t s) {
     double *part = (double *)((char *)ws + p.off_scratch);
     const long long nf = p.nf;
+    // 1D: the observed field (u for Burgers, rho u for the Euler model)
+    const size_t off = (size_t)p.obs_field * nf * p.tsize;
+    xa = (const char *)xa + off;
+    xt = (const char *)xt + off;
     int nb = (int)((nf + 255) / 256);
     if (nb > DIAG_BLOCKS) nb = DIAG_BLOCKS;
     if (p.cfg.precision == MENKF_F64)

@@ -39,26 +39,28 @@ __global__ __launch_bounds__(256) void prolong_add(const T *__restrict__ dc, con
     xout[i] = xin[i] + prolong_at<T>(dc + (long long)f * nxc * nyc, nxc, nyc, r, y, x);
 }
 
-// Open 1D grid (inlet-forced case): xout = xin + Pi_F(dc) with the
-// one-sided cubic stencils of open_cubic, except at the inlet node, whose
-// value the boundary condition prescribes (xout[0] = xin[0]).
+// Open 1D grid (inlet-forced cases): xout = xin + Pi_F(dc) for every field
+// with the one-sided cubic stencils of open_cubic, except at the inlet
+// node, whose value the boundary condition prescribes (xout = xin there).
 template <typename T>
 __global__ __launch_bounds__(256) void prolong_add_open(const T *__restrict__ dc, const T *__restrict__ xin,
-                                                        T *__restrict__ xout, int nx, int r, int nxc,
+                                                        T *__restrict__ xout, int nx, int r, int nxc, int F,
                                                         const int32_t *__restrict__ info) {
     if (*info != 0) return;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nx) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nx * F) return;
+    const int f = g / nx, x = g - f * nx;
     if (x == 0) {
-        xout[0] = xin[0];
+        xout[g] = xin[g];
         return;
     }
     T w[4];
     const int b0 = open_cubic<T>(x, r, nxc, w);
+    const T *d = dc + (long long)f * nxc;
     T acc = T(0);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc += w[b] * dc[b0 + b];
-    xout[x] = xin[x] + acc;
+    for (int b = 0; b < 4; ++b) acc += w[b] * d[b0 + b];
+    xout[g] = xin[g] + acc;
 }
 
 // 2D form: one fine row of one field per grid row (y = blockIdx.y, field =
@@ -145,13 +147,13 @@ hipError_t launch_restrict(const Plan &p, const void *xf, void *xc, hipStream_t 
 hipError_t launch_prolong_add(const Plan &p, const void *dc, const void *xin, void *xout, const int32_t *info,
                               hipStream_t s) {
     if (p.open) {
-        const int blocks = (p.nx + 255) / 256;
+        const int blocks = (p.nx * p.F + 255) / 256;
         if (p.cfg.precision == MENKF_F64)
             hipLaunchKernelGGL(prolong_add_open<double>, dim3(blocks), dim3(256), 0, s, (const double *)dc,
-                               (const double *)xin, (double *)xout, p.nx, p.cfg.ratio, p.nxc, info);
+                               (const double *)xin, (double *)xout, p.nx, p.cfg.ratio, p.nxc, p.F, info);
         else
             hipLaunchKernelGGL(prolong_add_open<float>, dim3(blocks), dim3(256), 0, s, (const float *)dc,
-                               (const float *)xin, (float *)xout, p.nx, p.cfg.ratio, p.nxc, info);
+                               (const float *)xin, (float *)xout, p.nx, p.cfg.ratio, p.nxc, p.F, info);
         return hipGetLastError();
     }
     if (p.dim == 2 && p.ny <= 65535 && p.cfg.ratio <= 64) {
@@ -202,6 +204,7 @@ hipError_t launch_copy(const Plan &p, const void *src, void *dst, const int32_t 
 hipError_t launch_sweep(const Plan &p, const void *xin, const void *xprev, void *xout, double alpha,
                         const int32_t *info, void *ws, hipStream_t s) {
     (void)ws;
+    if (p.cfg.model == MENKF_EULER1D_INLET) return launch_euler_sweep(p, xin, xprev, xout, alpha, info, s);
     if (p.dim == 1) return launch_burgers_sweep(p, xin, xprev, xout, alpha, info, s);
     return launch_ns_sweep(p, xin, xprev, xout, alpha, info, s);
 }

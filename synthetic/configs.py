@@ -50,10 +50,16 @@ class Config:
     theta_prior_sigma: tuple = (0.05, 0.05)
     theta_walk: tuple = (0.005, 0.005)
     t_spinup: float = 10.0
+    # 1D equations: "burgers" or "euler" (inviscid 1D Euler, acoustic case)
+    eq: str = "burgers"
+    filter_sigma: float = 1.0      # strength of the explicit filter (Euler case)
+    theta_b: float = 10.0          # truth amplitude theta0 (1 + sin(omega t / b)) (Euler case)
 
     @property
     def nfields(self) -> int:
-        return 1 if self.dim == 1 else 4
+        if self.dim == 2:
+            return 4
+        return 3 if self.eq == "euler" else 1
 
     @property
     def nxc(self) -> int:
@@ -114,6 +120,29 @@ def inlet_burgers(ratio: int = 4, precision: str = "f64", **kw) -> Config:
     base = Config(name=f"burgers1d_inlet_800_r{ratio}_n100", dim=1, nx=800, ny=1, ratio=ratio,
                   n_members=100, n_obs=30, n_probes=80, dt=2e-4, n_cycles=3166, obs_sigma=0.05,
                   member_sigma=0.0, precision=precision, nu=1.0 / 200.0, length=10.0, bc="inlet")
+    return base.with_(**kw)
+
+
+def euler_inlet(ratio: int = 4, n_obs: int = 30, precision: str = "f64", **kw) -> Config:
+    """The acoustic case of Sec. 5: inviscid 1D Euler on [0, 10], 800 cells,
+    dt = 6e-4, inlet Mach 0.4, inlet velocity u0 (1 + theta(t) sin(2 pi t))
+    with the truth theta(t) = 0.015 (1 + sin(2 pi t / 10)), 80 sensors on
+    [0, 1) observing rho u, N_e = 100, r_C = 4, prior theta ~ N(0, 6.4e-5),
+    random walk variance 1e-10 per analysis, assimilation over t in [0, 110]
+    after a 10-unit spin-up of the truth.  n_obs = 30, 167, 833 give the
+    analysis frequencies f_a = 55, 10, 2 per characteristic time.  The
+    observation noise is the paper's variance 0.09 read in SI units of
+    momentum (rho0 = 1.17 kg/m^3, T0 = 300 K, air) and converted to
+    rho0 (u0 + a) units."""
+    a_si = math.sqrt(1.4 * 287.05 * 300.0)
+    sigma = 0.3 / (1.17 * (1.0 + 0.4) * a_si)
+    mach = 0.4
+    base = Config(name=f"euler1d_inlet_800_r{ratio}_n100_nobs{n_obs}", dim=1, nx=800, ny=1, ratio=ratio,
+                  n_members=100, n_obs=n_obs, n_probes=80, dt=6e-4, n_cycles=int(110.0 / (n_obs * 6e-4)),
+                  obs_sigma=sigma, member_sigma=0.0, precision=precision, length=10.0, bc="inlet", eq="euler",
+                  gamma=1.4, mach=mach, u0=mach / (1.0 + mach), omega=2.0 * math.pi,
+                  theta_true=(0.015, 0.0), theta_prior=(0.0, 0.0), theta_prior_sigma=(0.008, 0.0),
+                  theta_walk=(1e-5, 0.0), t_spinup=10.0, filter_sigma=1.0, theta_b=10.0)
     return base.with_(**kw)
 
 

@@ -202,7 +202,17 @@ def inlet_theta_ics(cfg: Config) -> np.ndarray:
 
 
 def inlet_uniform(cfg: Config, level: str = "fine", nb: int = 0) -> np.ndarray:
-    """u(x, 0) = u0 everywhere: (1, n) for one state, (nb, 1, n) for nb states."""
+    """The uniform inlet state everywhere: u = u0 (Burgers, (1, n)) or
+    (rho0, rho0 u0, rho0 E0) of the characteristic units (Euler, (3, n));
+    (nb, F, n) for nb states."""
     n = cfg.nx if level == "fine" else cfg.nxc
-    u = np.full((1, n), cfg.u0)
+    if cfg.eq == "euler":
+        a = 1.0 / (1.0 + cfg.mach)
+        u0 = cfg.mach * a
+        p0 = a * a / cfg.gamma
+        e0 = p0 / (cfg.gamma - 1.0) + 0.5 * u0 * u0
+        u = np.empty((3, n))
+        u[0], u[1], u[2] = 1.0, u0, e0
+    else:
+        u = np.full((1, n), cfg.u0)
     return u if nb == 0 else np.repeat(u[None], nb, axis=0)

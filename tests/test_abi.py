@@ -190,3 +190,48 @@ def test_dual_calls_need_a_workspace():
     assert lib.menkf_param_perturb(h, one, one, 1, 1, None) == -7
     assert lib.menkf_param_update(h, one, one, one, None) == -7
     lib.menkf_destroy(h)
+
+
+def _euler(**kw):
+    base = dict(model=4, nx=800, ny=1, ratio=4, n_members=100, n_probes=80, dt=6e-4, length=10.0,
+                obs_sigma=5e-4, gamma=1.4, mach=0.4, omega=6.283185307179586, theta_sigma=(1e-5, 0.0),
+                filter_sigma=1.0, precision=1)
+    base.update(kw)
+    return _create(**base)
+
+
+def test_euler_model_plans_three_fields():
+    st, h, lib = _euler()
+    assert st == 0, lib.menkf_last_error(None)
+    n4 = ctypes.c_size_t()
+    assert lib.menkf_workspace_size(h, ctypes.byref(n4)) == 0
+    lib.menkf_destroy(h)
+    st, h, lib = _inlet()
+    n3 = ctypes.c_size_t()
+    assert lib.menkf_workspace_size(h, ctypes.byref(n3)) == 0
+    lib.menkf_destroy(h)
+    # three fields instead of one: the fine and coarse buffers triple
+    assert n4.value > n3.value + 2 * (3 * 800 * 8 + 3 * 100 * 200 * 8)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=1800, ratio=4), -6),                # F64 state beyond the LDS window
+    (dict(nx=3616, ratio=4, precision=0), -6),
+    (dict(mach=1.2), -1),                        # supersonic inlet
+    (dict(mach=0.0), -1),
+    (dict(gamma=1.0), -1),
+    (dict(filter_sigma=1.5), -1),
+    (dict(filter_sigma=-0.1), -1),
+    (dict(nx=28, ratio=4, n_probes=8), -2),      # 7 coarse nodes: no room for the filter stencils
+])
+def test_euler_model_rejects(kw, code):
+    st, h, lib = _euler(**kw)
+    assert st == code, lib.menkf_last_error(None)
+    assert not h.value
+
+
+def test_euler_model_limits_are_accepted():
+    for kw in (dict(nx=1792, ratio=4), dict(nx=3612, ratio=4, precision=0), dict(nx=32, ratio=4, n_probes=8)):
+        st, h, lib = _euler(**kw)
+        assert st == 0, (kw, lib.menkf_last_error(None))
+        lib.menkf_destroy(h)
