@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the forecast schedules first")
     ap.add_argument("--workload", default="ns2d_1024_256_n64",
-                    choices=["ns2d_1024_256_n64", "uneven48", "inlet_dual"],
+                    choices=["ns2d_1024_256_n64", "uneven48", "inlet_dual", "euler_dual"],
                     help="uneven48: the batch of 48 uneven instances in one graph; inlet_dual: the dual "
                          "(parameter + state) filter of the inlet-forced Burgers case (neither is the headline)")
     ap.add_argument("--dual-precision", default="f64", choices=["f64", "f32"])
@@ -670,6 +670,229 @@ def dual_study(args):
     print(json.dumps(out), flush=True)
 
 
+# FP64/FP32 operations per node and step of the Euler forecast kernel:
+# flux 9 (u = m / rho, p from 4 operations, two products with their sums),
+# update 4 per field, filter 10 per field.
+EULER_FLOPS_PER_POINT_STEP = 9 + 3 * 4 + 3 * 10
+
+
+class EulerTruth:
+    """Reference run of the acoustic case on the GPU: the library's fine
+    forecast advanced one step per call, its inlet amplitude the truth
+    theta(t) = theta0 (1 + sin(omega t / b)) at the end of each step (the
+    per-step parameters and start times are tabulated on the device)."""
+
+    def __init__(self, ctx, cfg):
+        import torch
+
+        from synthetic import fields
+        self.ctx, self.cfg = ctx, cfg
+        self.x = torch.as_tensor(fields.inlet_uniform(cfg)) \
+            .to("cuda", torch.float64 if cfg.precision == "f64" else torch.float32).contiguous()
+
+    def advance(self, nsteps, t_start):
+        """nsteps single steps from time t_start."""
+        import numpy as np
+        import torch
+        cfg = self.cfg
+        ts = t_start + np.arange(nsteps) * cfg.dt
+        th = np.zeros((nsteps, 2))
+        th[:, 0] = cfg.theta_true[0] * (1.0 + np.sin(cfg.omega / cfg.theta_b * (ts + cfg.dt)))
+        th_d = torch.as_tensor(th, dtype=torch.float64, device="cuda")
+        ts_d = torch.as_tensor(ts, dtype=torch.float64, device="cuda")
+        for k in range(nsteps):
+            self.ctx.forecast_inlet(0, self.x, 1, th_d[k], ts_d[k:k + 1])
+
+
+def euler_observations(m, cfg, ctx, n_obs_list, t_end=110.0):
+    """Spin-up of the truth (restarted at t = 0, as the paper does), then the
+    noise-free momentum at the sensors every n_obs steps for each n_obs of
+    the list, plus the momentum field at those times, over [0, t_end]."""
+    import torch
+    spin = int(round(cfg.t_spinup / cfg.dt))
+    tr = EulerTruth(ctx, cfg)
+    tr.advance(spin, 0.0)
+    total = int(round(t_end / cfg.dt))
+    obs = {n: [] for n in n_obs_list}
+    fields_at = {n: [] for n in n_obs_list}
+    step = 0
+    marks = sorted({k * n for n in n_obs_list for k in range(1, total // n + 1)})
+    mi = 0
+    while step < total:
+        nxt = marks[mi] if mi < len(marks) else total
+        tr.advance(nxt - step, step * cfg.dt)
+        step = nxt
+        if mi < len(marks) and step == marks[mi]:
+            y = ctx.observe(m.MENKF_FINE, tr.x)[0].clone()
+            for n in n_obs_list:
+                if step % n == 0:
+                    obs[n].append(y)
+                    fields_at[n].append(tr.x[1].to(torch.float64).clone())
+            mi += 1
+    return {n: (torch.stack(obs[n]), torch.stack(fields_at[n])) for n in n_obs_list}
+
+
+def euler_run(m, cfg, obs, truth_fields, record=True, aux=True, warmup=0):
+    """Dual filter over the observations of one analysis frequency; returns
+    (seconds of the replays after the first `warmup`, theta-mean trace,
+    momentum errors, context, (members, theta, clock))."""
+    import numpy as np
+    import torch
+
+    from synthetic import fields
+    F64 = torch.float64
+    dt = F64 if cfg.precision == "f64" else torch.float32
+    ctx = m.Context(cfg)
+    idx, comp = fields.probes_for(cfg)
+    ctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+    dev = lambda a, ty=dt: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", ty).contiguous()
+    fine = dev(fields.inlet_uniform(cfg))
+    prev = torch.empty_like(fine)
+    mem = dev(fields.inlet_uniform(cfg, "coarse", cfg.n_members))
+    theta = dev(fields.inlet_theta_ics(cfg), F64)
+    tmean = torch.zeros(2, dtype=F64, device="cuda")
+    clock = torch.zeros(1, dtype=F64, device="cuda")
+    xs = torch.empty((3, cfg.nxc), dtype=dt, device="cuda")
+    dc = torch.empty_like(xs)
+    y = torch.empty(cfg.n_probes, dtype=F64, device="cuda")
+    n_cyc = obs.shape[0]
+    noise = dev(np.stack([fields.obs_noise(cfg, c + 1) for c in range(n_cyc)]), F64)
+    Y = (obs + noise).contiguous()
+    base = torch.as_tensor(fields.inlet_uniform(cfg)[1], dtype=F64, device="cuda")
+    hist = torch.empty((n_cyc, 2), dtype=F64, device="cuda")
+    err = torch.empty(n_cyc, dtype=F64, device="cuda")
+    stream = torch.cuda.Stream()
+    aux_s = torch.cuda.Stream() if aux else None
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        ctx.set_cycle(1, stream=stream)
+        m.Graph.begin(stream)
+        ctx.dual_cycle(fine, prev, mem, xs, dc, y, theta, tmean, clock, cfg.seed + 5, m.MENKF_CYCLE_DEVICE,
+                       cfg.n_obs, n_sweeps=1, alpha=0.5, stream=stream, aux_stream=aux_s)
+        g = m.Graph.end(stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for c in range(n_cyc):
+        if c == warmup:
+            e0.record(stream)
+        with torch.cuda.stream(stream):
+            y.copy_(Y[c])
+        g.launch(stream)
+        if record:
+            with torch.cuda.stream(stream):
+                hist[c].copy_(tmean)
+                d = fine[1].to(F64) - truth_fields[c]
+                err[c] = torch.linalg.vector_norm(d) / torch.linalg.vector_norm(truth_fields[c] - base)
+    e1.record(stream)
+    stream.synchronize()
+    return e0.elapsed_time(e1) / 1e3, hist.cpu().numpy(), err.cpu().numpy(), ctx, (mem, theta, clock)
+
+
+def euler_study(args):
+    """Tracking of the time-varying inlet amplitude for f_a = 55, 10, 2
+    analyses per characteristic time over [0, 110] (Sec. 5): theta-mean
+    traces, mean tracking error, best lag, peak ratio, momentum error."""
+    import numpy as np
+    import torch
+
+    import paper_2012_10091_amd as m
+    from synthetic import configs, fields
+    n_list = (30, 167, 833)
+    walk = {} if args.theta_walk is None else {"theta_walk": (args.theta_walk, 0.0)}
+    base = configs.euler_inlet(precision=args.dual_precision, **walk)
+    tctx = m.Context(base)
+    idx, comp = fields.probes_for(base)
+    tctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+    t0 = time.perf_counter()
+    O = euler_observations(m, base, tctx, n_list)
+    log(f"bench: euler truth over [0, 110] ready in {time.perf_counter() - t0:.1f}s")
+    out = {"study": "euler_dual_theta_tracking", "precision": base.precision, "members": base.n_members,
+           "ratio": base.ratio, "probes": base.n_probes, "theta_walk": list(base.theta_walk),
+           "obs_sigma": base.obs_sigma, "runs": {}}
+    for n in n_list:
+        cfg = configs.euler_inlet(n_obs=n, precision=args.dual_precision, **walk)
+        obs, tf = O[n]
+        sec, h, err, _, _ = euler_run(m, cfg, obs, tf)
+        ta = cfg.n_obs * cfg.dt
+        t = ta * np.arange(1, len(h) + 1)
+        truth = cfg.theta_true[0] * (1.0 + np.sin(cfg.omega / cfg.theta_b * t))
+        late = t >= 10.0
+        mae = float(np.abs(h[late, 0] - truth[late]).mean())
+        lags = np.arange(0.0, 3.01, 0.05)
+        lag_err = [float(np.abs(h[late, 0] - cfg.theta_true[0] * (1.0 + np.sin(cfg.omega / cfg.theta_b * (t[late] - L)))).mean())
+                   for L in lags]
+        best = float(lags[int(np.argmin(lag_err))])
+        # ratio of the estimate's maxima to the truth's (0.03), one per period of 10 after t = 10
+        peaks = [float(h[(t >= p0) & (t < p0 + 10.0), 0].max()) / (2 * cfg.theta_true[0]) for p0 in np.arange(10.0, 110.0, 10.0)
+                 if np.any((t >= p0) & (t < p0 + 10.0))]
+        f_a = 1.0 / ta
+        rec = {"n_obs": n, "f_a": f_a, "cycles": len(h), "seconds": sec,
+               "theta_mean_abs_error_t_ge_10": mae, "best_lag": best, "theta_mean_abs_error_at_best_lag": min(lag_err),
+               "peak_ratio_mean": float(np.mean(peaks)), "momentum_rel_error_mean_t_ge_10": float(err[late].mean()),
+               "momentum_rel_error_end": float(err[-1]),
+               "trace": [[round(float(a), 4), round(float(b), 6)] for a, b in zip(t[::max(1, len(t) // 200)], h[::max(1, len(t) // 200), 0])]}
+        out["runs"][f"{f_a:.1f}"] = rec
+        log(f"bench: euler f_a={f_a:.1f} (n_obs {n}): {len(h)} cycles in {sec:.2f}s, |theta - truth| {mae:.5f}, "
+            f"best lag {best:.2f} ({min(lag_err):.5f}), peaks {np.mean(peaks):.3f}, momentum error {err[late].mean():.3f}")
+    print(json.dumps(out), flush=True)
+
+
+def bench_euler(args):
+    """Dual filter of the acoustic case at the Sec. 5 size (800/200 nodes,
+    N = 100, 80 sensors, an analysis every 30 steps): dual cycles/s of the
+    captured cycle replayed over observations already in HBM."""
+    import torch
+
+    import paper_2012_10091_amd as m
+    from synthetic import configs, fields
+    cfg = configs.euler_inlet(precision=args.dual_precision)
+    tctx = m.Context(cfg)
+    idx, comp = fields.probes_for(cfg)
+    tctx.set_probes(torch.as_tensor(idx, device="cuda"), torch.as_tensor(comp, device="cuda"))
+    n_cyc = args.warmup + args.steps
+    O = euler_observations(m, cfg, tctx, (cfg.n_obs,), t_end=(n_cyc + 1) * cfg.n_obs * cfg.dt)
+    obs, tf = O[cfg.n_obs]
+    obs, tf = obs[:n_cyc], tf[:n_cyc]
+    log(f"bench: euler workload {cfg.name} {cfg.precision} ready")
+    sec, h, _, ctx, (mem, theta, clock) = euler_run(m, cfg, obs, tf, record=False, warmup=args.warmup)
+    cps = args.steps / sec
+    status = ctx.get_status()
+    log(f"bench: euler dual {cps:.1f} cycles/s over {args.steps} timed cycles, status {status}")
+    stream = torch.cuda.Stream()
+    scratch = mem.clone()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 20
+    with torch.cuda.stream(stream):
+        ctx.forecast_inlet(m.MENKF_COARSE, scratch, cfg.n_obs, theta, clock, stream=stream)
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.forecast_inlet(m.MENKF_COARSE, scratch, cfg.n_obs, theta, clock, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    avg_s = e0.elapsed_time(e1) / 1e3 / reps
+    flops = EULER_FLOPS_PER_POINT_STEP * cfg.n_members * cfg.nxc * cfg.n_obs
+    peak = FP64_VECTOR_PEAK_TFLOPS if cfg.precision == "f64" else FP32_VECTOR_PEAK_TFLOPS
+    achieved = flops / avg_s / 1e12
+    log(f"bench: euler member forecast {avg_s * 1e6:.1f} us per launch, {achieved:.3f} TFLOP/s")
+    out = {
+        "metric": "dual assimilation cycles/s, inlet-forced 1D Euler 800/200 N=100 (acoustic case, f_a = 55)",
+        "value": cps, "unit": "dual cycles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 / cps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": cfg.precision, "data": "synthetic",
+        "config": {"workload": cfg.name, "fine": cfg.nx, "coarse": cfg.nxc, "members": cfg.n_members,
+                   "probes": cfg.n_probes, "steps_per_cycle": cfg.n_obs, "status_word": status},
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None,
+            "kernel": f"euler_inlet_window<{'double' if cfg.precision == 'f64' else 'float'}> "
+                      f"({cfg.n_members} members x 3 x {cfg.nxc} nodes x {cfg.n_obs} steps, LDS-resident)",
+            "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def with_gain_mode(cfg, mode):
     """The workload configuration with another menkf gain mode."""
     import dataclasses
@@ -737,6 +960,8 @@ def main():
         return bench_batch(args)
     if args.workload == "inlet_dual":
         return dual_study(args) if args.dual_study else bench_dual(args)
+    if args.workload == "euler_dual":
+        return euler_study(args) if args.dual_study else bench_euler(args)
     if args.traffic_probe:
         return traffic_probe(args)
     import torch
