@@ -15,6 +15,8 @@
  *       menkf_gain                Algo. 3 steps 3,4,7,8 (gain) and Algo. 4 step 5 (gain of x*)
  *       menkf_update              Algo. 3 step 8 (member update) and Algo. 4 step 5 (delta^C)
  *       menkf_prolong_smooth      Algo. 4 steps 5-6: x' = x^F_f + Pi_F(delta^C), relaxed iteration
+ *   dual estimation of inlet parameters (Sec. 2.1.3, Algo. 2), inlet-forced models only
+ *       menkf_forecast_inlet, menkf_param_perturb, menkf_param_update, menkf_dual_cycle
  *
  * Conventions shared by every call
  *   - Every pointer argument named *_dev is DEVICE memory on the context's
@@ -24,7 +26,8 @@
  *     context uses them.
  *   - State arrays hold float (MENKF_F32 contexts) or double (MENKF_F64
  *     contexts), passed as void*.  Layout: [nb][F][ny][nx], x fastest,
- *     members outermost; F = 1 (Burgers, ny = 1) or 4 (rho, rho u, rho v, E).
+ *     members outermost; F = 1 (Burgers, ny = 1), 3 (1D Euler: rho, rho u,
+ *     rho E; ny = 1) or 4 (rho, rho u, rho v, E).
  *   - Calls are asynchronous on the given stream (NULL = default stream),
  *     allocate nothing, never synchronise and never read device results
  *     on the host, so a sequence of them can be captured in a HIP graph.
