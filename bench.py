@@ -96,7 +96,7 @@ class Cycle:
         self.seed = cfg.seed + 5
         self.graph = None
         self.aux = torch.cuda.Stream()
-        self.overlap = False
+        self.overlap = True
 
     def autotune(self):
         """Pick the forecast schedules of both levels with the library's autotuner."""

@@ -453,10 +453,18 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  * coarse states, xstar and deltac one coarse state each, yobs n_probes
  * doubles (read when the cycle runs, so a captured cycle can be fed new
  * observations in place).  cycle = MENKF_CYCLE_DEVICE uses the context's
- * device counter.  aux_stream (optional, NULL = none): the fine forecast is
- * issued there, forked from and joined back into stream with two events
- * the context owns, so it overlaps the member forecast; results are the
- * same as without it. */
+ * device counter.  aux_stream (optional, NULL = none, not stream itself):
+ * the fine forecast is issued there, forked from and joined back into
+ * stream with two events the context owns.  With MENKF_GAIN_EXACT_R it
+ * runs beside the N_y x N_y factorisation: the member forecast comes
+ * first, the factorisation runs with d* = 0, and the x* column of the gain
+ * follows once x* is known through the identity
+ *   z* = Y^T (Y Y^T + s^2 I)^-1 d* = (s^2 I + Y^T Y)^-1 Y^T d*
+ * (the N_e x N_e system is factored on aux_stream too).  The member columns
+ * of Z are bitwise those of menkf_gain; z*, delta^C and the fine state
+ * agree with it to FP64 roundoff.  In the other gain modes the fine
+ * forecast runs beside the member forecast and results are bitwise the
+ * same as without aux_stream. */
 typedef struct {
     menkf_ctx *ctx;
     void *fine, *fine_prev, *members, *xstar, *deltac;

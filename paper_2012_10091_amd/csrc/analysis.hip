@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void obs_pack(const double *__restrict__ yraw,
                                                 const double *__restrict__ yobs, const double *__restrict__ eps,
                                                 uint64_t seed, uint64_t cycle, const uint64_t *__restrict__ dcycle,
                                                 double sigma, int sample_mode, double *__restrict__ Yk, int kdim,
-                                                double *__restrict__ A, int ld) {
+                                                double *__restrict__ A, int ld, int with_xstar) {
     // 16 probes per workgroup, the members of a probe split over 16 lanes
     // (member i goes to group i % 16); the member means are reduced in a
     // fixed order through LDS.
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void obs_pack(const double *__restrict__ yraw,
         if (sample_mode) yk[N + i] = (e - ebar) * scale;
     }
     for (int k = (sample_mode ? 2 * N : N) + g; k < kdim; k += 16) yk[k] = 0.0;
-    if (g == 0) B[(long long)N * ld] = yo - yraw[(long long)N * ldy + p];
+    if (g == 0) B[(long long)N * ld] = with_xstar ? yo - yraw[(long long)N * ldy + p] : 0.0;
 }
 
 // Zero the trailing (Schur) block and the padding rows of the extra block,
@@ -511,6 +511,120 @@ __global__ __launch_bounds__(256) void ens_assemble(const double *__restrict__ P
     }
 }
 
+// ----------------------------------------------------------------- deferred x* column
+// With R = s^2 I the x* column of the gain has the exact form
+//   z* = Y^T (Y Y^T + s^2 I)^-1 d* = (s^2 I + Y^T Y)^-1 Y^T d*,
+// so it can be formed after the fine forecast while the N_y x N_y
+// factorisation (run with d* = 0) proceeds.  M^-1 with M = s^2 I + Y^T Y
+// comes out of the small augmented system [[M, .], [I, 0]] (lm = 2 npm
+// rows) factored for its first npm columns: its Schur block is -M^-1.
+//
+// Partial Grams over probe chunks: part[c][t] = sum over the probes p of
+// chunk c of Y[p][64 bi + r] Y[p][64 bj + q] for the lower tile t = (bi, bj);
+// 4 x 4 entries per thread, probes staged 32 at a time through LDS.
+__global__ __launch_bounds__(256) void gram_y_partial(const double *__restrict__ Yk, int kdim, int nyp, int pc,
+                                                      double *__restrict__ part) {
+    __shared__ double sa[32][64], sb[32][64];
+    const int t = blockIdx.x, c = blockIdx.y;
+    int bi, bj;
+    tri_index(t, bi, bj);
+    const int r0 = (threadIdx.x >> 4) * 4, q0 = (threadIdx.x & 15) * 4;
+    double acc[4][4] = {};
+    const int p_begin = c * pc, p_end = min(nyp, p_begin + pc);
+    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+            const int pp = e >> 6, col = e & 63;
+            const bool in = p0 + pp < p_end;
+            sa[pp][col] = in ? Yk[(long long)(p0 + pp) * kdim + bi * 64 + col] : 0.0;
+            sb[pp][col] = in ? Yk[(long long)(p0 + pp) * kdim + bj * 64 + col] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int pp = 0; pp < 32; ++pp) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = sa[pp][r0 + u];
+                b[u] = sb[pp][q0 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+    }
+    double *out = part + ((long long)c * gridDim.x + t) * 4096;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(r0 + u) * 64 + q0 + v] = acc[u][v];
+}
+
+// The small augmented system, lower triangle: rows a < npm hold
+// M = s^2 I + Y^T Y (identity on the padding), rows npm + e hold e_e^T in
+// the first npm columns and zeros in the Schur block.  The chunk partials
+// are summed in chunk order.
+__global__ __launch_bounds__(256) void gram_y_assemble(const double *__restrict__ part, int nchunk, int ntile,
+                                                       int N, int npm, double s2, double *__restrict__ Mg) {
+    const int lm = 2 * npm;
+    const long long tot = (long long)lm * lm;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(t / lm), b = (int)(t - (long long)a * lm);
+        if (b > a) continue;
+        double v = 0.0;
+        if (a < npm) {
+            if (a < N && b < N) {
+                const int bi = a >> 6, bj = b >> 6;
+                const int tile = bi * (bi + 1) / 2 + bj;
+                const double *pp = part + (long long)tile * 4096 + (a & 63) * 64 + (b & 63);
+                for (int c = 0; c < nchunk; ++c) v += pp[(long long)c * ntile * 4096];
+                if (a == b) v += s2;
+            } else {
+                v = a == b ? 1.0 : 0.0;
+            }
+        } else if (b < npm) {
+            v = (b == a - npm) ? 1.0 : 0.0;
+        }
+        Mg[t] = v;
+    }
+}
+
+// z* = M^-1 Y^T (y^o - H(x*)) for the factored small system Mg (its Schur
+// block is -M^-1, lower triangle), written to zstar (zero-padded to npad)
+// and to column N of z64.  One workgroup of 1024 threads: member i's dot
+// product over the probes is split over 4 groups, combined in a fixed order.
+__global__ __launch_bounds__(1024) void xstar_gain(const double *__restrict__ hx, const double *__restrict__ yobs,
+                                                   const double *__restrict__ Yk, int kdim, int Ny, int N, int npad,
+                                                   const double *__restrict__ Mg, int npm, double *__restrict__ z64,
+                                                   double *__restrict__ zstar, const int32_t *__restrict__ info) {
+    __shared__ double vp[4][256];
+    __shared__ double v[256];
+    if (*info != 0) return;
+    const int t = threadIdx.x, i = t & 255, g = t >> 8;
+    double acc = 0.0;
+    if (i < N)
+        for (int p = g; p < Ny; p += 4) acc += Yk[(long long)p * kdim + i] * (yobs[p] - hx[p]);
+    vp[g][i] = acc;
+    __syncthreads();
+    if (g == 0) v[i] = (vp[0][i] + vp[1][i]) + (vp[2][i] + vp[3][i]);
+    __syncthreads();
+    if (t < npad) {
+        double z = 0.0;
+        if (t < N) {
+            const int lm = 2 * npm;
+            const double *S = Mg + (long long)npm * lm + npm;
+            for (int b = 0; b < N; ++b) {
+                const double m = t >= b ? S[(long long)t * lm + b] : S[(long long)b * lm + t];
+                z -= m * v[b];
+            }
+            z64[(long long)N * N + t] = z;
+        }
+        zstar[t] = z;
+    }
+}
+
 // ----------------------------------------------------------------- Z from the Schur block
 // Z[i][j] = -M[N+1+i][j] with M the trailing block (rows/cols from nyp).
 // z64[j][i] = Z[i][j]; zstar[i] = Z[i][N]; zt holds Z^T for the member
@@ -751,14 +865,15 @@ static hipError_t extract_gain(const Plan &p, const double *M, int ld, int n0, c
     return hipGetLastError();
 }
 
-hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, const double *yobs, uint64_t seed,
-                       uint64_t cycle, const double *eps, const int32_t *idx, const int32_t *comp, void *ws,
-                       hipStream_t s, bool advance_cycle) {
-    char *w = (char *)ws;
+// Observation, anomalies, innovations and S (steps 1-4); with defer_xstar
+// the x* row is left out (d* = 0 in the factorisation) and, for R = s^2 I,
+// the small system of the deferred x* column is assembled from Y.
+static hipError_t gain_front(const Plan &p, const void *members, const void *xstar, const double *yobs,
+                             uint64_t seed, uint64_t cycle, const double *eps, const int32_t *idx,
+                             const int32_t *comp, char *w, hipStream_t s, bool defer_xstar) {
     int32_t *info = (int32_t *)(w + p.off_info);
     double *yraw = (double *)(w + p.off_scratch);
     double *A = (double *)(w + p.off_a);
-    double *Linv = (double *)(w + p.off_linv);
     double *Yk = (double *)(w + p.off_yb);
     const int N = p.N;
     const long long stride = p.nc * p.F;
@@ -770,8 +885,8 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     if ((e = set_lds((const void *)chol_panel, lds)) != hipSuccess) return e;
     if ((e = set_lds((const void *)chol_update, lds)) != hipSuccess) return e;
     if ((e = set_lds((const void *)syrk_f64_mfma, lds)) != hipSuccess) return e;
-    // 1. H^C of the members and of x*
-    dim3 g1((p.Ny + 255) / 256, N + 1);
+    // 1. H^C of the members (and of x*)
+    dim3 g1((p.Ny + 255) / 256, defer_xstar ? N : N + 1);
     if (f64)
         hipLaunchKernelGGL(obs_eval<double>, g1, dim3(256), 0, s, (const double *)members, stride, N,
                            (const double *)xstar, idx, comp, p.Ny, yraw, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
@@ -784,10 +899,36 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
     // 2. clear the Schur block, reset status
     hipLaunchKernelGGL(zero_extra, dim3(256), dim3(256), 0, s, A, p.ld, p.nyp, p.mext, info);
     // 3. anomalies, innovations, perturbations (FP64)
-    uint64_t *dcycle = cycle == MENKF_CYCLE_DEVICE ? (uint64_t *)(w + p.off_info + 64) : nullptr;
+    const uint64_t *dcycle = cycle == MENKF_CYCLE_DEVICE ? (const uint64_t *)(w + p.off_info + 64) : nullptr;
     hipLaunchKernelGGL(obs_pack, dim3((p.nyp + 15) / 16), dim3(256), 0, s, yraw, p.nyp, N, p.Ny, p.nyp, yobs, eps,
-                       seed, cycle, (const uint64_t *)dcycle, p.cfg.obs_sigma, sample, Yk, p.kdim, A, p.ld);
+                       seed, cycle, dcycle, p.cfg.obs_sigma, sample, Yk, p.kdim, A, p.ld, defer_xstar ? 0 : 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (p.cfg.gain_mode == MENKF_GAIN_ENSEMBLE_SPACE) return hipSuccess;
+    // 4. S = Y Y^T + R (+ identity on the padding), FP64 MFMA
+    const int nbs = p.nyp / CHOL_NB;
+    hipLaunchKernelGGL(syrk_f64_mfma, dim3(nbs * (nbs + 1) / 2), dim3(256), lds, s, (const double *)Yk, p.kdim, p.Ny,
+                       sample ? 0.0 : rdiag, A, p.ld);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (defer_xstar) {
+        // 4''. M = s^2 I + Y^T Y in the small augmented system
+        const int nt = p.npm / CHOL_NB, ntile = nt * (nt + 1) / 2;
+        hipLaunchKernelGGL(gram_y_partial, dim3(ntile, p.gchunks), dim3(256), 0, s, (const double *)Yk, p.kdim,
+                           p.nyp, p.gpc, (double *)(w + p.off_gpart));
+        hipLaunchKernelGGL(gram_y_assemble, dim3(64), dim3(256), 0, s, (const double *)(w + p.off_gpart), p.gchunks,
+                           ntile, N, p.npm, rdiag, (double *)(w + p.off_mg));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Factorisation and the gain factors (steps 5-6).
+static hipError_t gain_back(const Plan &p, uint64_t cycle, char *w, hipStream_t s, bool advance_cycle) {
+    int32_t *info = (int32_t *)(w + p.off_info);
+    double *A = (double *)(w + p.off_a);
+    double *Linv = (double *)(w + p.off_linv);
+    uint64_t *dcycle = (cycle == MENKF_CYCLE_DEVICE && advance_cycle) ? (uint64_t *)(w + p.off_info + 64) : nullptr;
+    const size_t lds = 2 * 64 * LDP * sizeof(double);
+    hipError_t e;
     if (p.cfg.gain_mode == MENKF_GAIN_ENSEMBLE_SPACE) {
         // 4'. P = E E^T of the extra rows, then the N_e x N_e system
         double *P = (double *)(w + p.off_p), *As = (double *)(w + p.off_as);
@@ -795,21 +936,62 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
         if ((e = set_lds((const void *)gram_extra, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(gram_extra, dim3(mb * (mb + 1) / 2), dim3(256), lds, s, (const double *)A, p.ld, p.nyp,
                            p.mextp, P);
-        hipLaunchKernelGGL(ens_assemble, dim3(256), dim3(256), 0, s, (const double *)P, p.mextp, N, p.npm, p.lds,
+        hipLaunchKernelGGL(ens_assemble, dim3(256), dim3(256), 0, s, (const double *)P, p.mextp, p.N, p.npm, p.lds,
                            p.cfg.obs_sigma * p.cfg.obs_sigma, As);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = chol_blocked(As, p.lds, p.npm / CHOL_NB, Linv, info, lds, s)) != hipSuccess) return e;
-        return extract_gain(p, As, p.lds, p.npm, w, advance_cycle ? dcycle : nullptr, s);
+        return extract_gain(p, As, p.lds, p.npm, w, dcycle, s);
     }
-    // 4. S = Y Y^T + R (+ identity on the padding), FP64 MFMA
-    const int nbs = p.nyp / CHOL_NB;
-    hipLaunchKernelGGL(syrk_f64_mfma, dim3(nbs * (nbs + 1) / 2), dim3(256), lds, s, (const double *)Yk, p.kdim, p.Ny,
-                       sample ? 0.0 : rdiag, A, p.ld);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // 5. blocked Cholesky of the first nyp columns, Schur complement on the rest
-    if ((e = chol_blocked(A, p.ld, nbs, Linv, info, lds, s)) != hipSuccess) return e;
+    if ((e = chol_blocked(A, p.ld, p.nyp / CHOL_NB, Linv, info, lds, s)) != hipSuccess) return e;
     // 6. Z
-    return extract_gain(p, A, p.ld, p.nyp, w, advance_cycle ? dcycle : nullptr, s);
+    return extract_gain(p, A, p.ld, p.nyp, w, dcycle, s);
+}
+
+hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, const double *yobs, uint64_t seed,
+                       uint64_t cycle, const double *eps, const int32_t *idx, const int32_t *comp, void *ws,
+                       hipStream_t s, bool advance_cycle) {
+    char *w = (char *)ws;
+    hipError_t e = gain_front(p, members, xstar, yobs, seed, cycle, eps, idx, comp, w, s, false);
+    if (e != hipSuccess) return e;
+    return gain_back(p, cycle, w, s, advance_cycle);
+}
+
+hipError_t launch_gain_deferred_front(const Plan &p, const void *members, const double *yobs, uint64_t seed,
+                                      uint64_t cycle, const int32_t *idx, const int32_t *comp, void *ws,
+                                      hipStream_t s) {
+    if (!p.defer_ok) return hipErrorInvalidValue;
+    return gain_front(p, members, nullptr, yobs, seed, cycle, nullptr, idx, comp, (char *)ws, s, true);
+}
+
+hipError_t launch_gain_deferred_back(const Plan &p, uint64_t cycle, void *ws, hipStream_t s) {
+    return gain_back(p, cycle, (char *)ws, s, true);
+}
+
+hipError_t launch_xstar_factor(const Plan &p, void *ws, hipStream_t s) {
+    char *w = (char *)ws;
+    const size_t lds = 2 * 64 * LDP * sizeof(double);
+    return chol_blocked((double *)(w + p.off_mg), 2 * p.npm, p.npm / CHOL_NB, (double *)(w + p.off_mlinv),
+                        (int32_t *)(w + p.off_info), lds, s);
+}
+
+hipError_t launch_xstar_gain(const Plan &p, const void *xstar, const double *yobs, const int32_t *idx,
+                             const int32_t *comp, void *ws, hipStream_t s) {
+    char *w = (char *)ws;
+    double *hx = (double *)(w + p.off_scratch) + (long long)p.N * p.nyp;
+    dim3 g1((p.Ny + 255) / 256, 1);
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(obs_eval<double>, g1, dim3(256), 0, s, (const double *)nullptr, 0LL, 0,
+                           (const double *)xstar, idx, comp, p.Ny, hx, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
+                           p.nxc, p.nyc, p.open, p.obs_field);
+    else
+        hipLaunchKernelGGL(obs_eval<float>, g1, dim3(256), 0, s, (const float *)nullptr, 0LL, 0,
+                           (const float *)xstar, idx, comp, p.Ny, hx, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
+                           p.nxc, p.nyc, p.open, p.obs_field);
+    hipLaunchKernelGGL(xstar_gain, dim3(1), dim3(1024), 0, s, (const double *)hx, yobs, (const double *)(w + p.off_yb),
+                       p.kdim, p.Ny, p.N, p.npad, (const double *)(w + p.off_mg), p.npm, (double *)(w + p.off_z),
+                       (double *)(w + p.off_zstar), (const int32_t *)(w + p.off_info));
+    return hipGetLastError();
 }
 
 

@@ -176,6 +176,15 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
         p->off_trial = take(coarse);
         p->off_thf = take((size_t)p->N * 2 * 8);
     }
+    p->defer_ok = cfg->gain_mode == MENKF_GAIN_EXACT_R ? 1 : 0;
+    if (p->defer_ok) {
+        const int nt = p->npm / CHOL_NB;
+        p->gchunks = p->nyp / 32 < 64 ? p->nyp / 32 : 64;
+        p->gpc = ((p->nyp + p->gchunks - 1) / p->gchunks + 31) / 32 * 32;
+        p->off_mg = take((size_t)(2 * p->npm) * (2 * p->npm) * 8);
+        p->off_mlinv = take(64 * 64 * 8);
+        p->off_gpart = take((size_t)p->gchunks * (nt * (nt + 1) / 2) * 4096 * 8);
+    }
     p->ws_bytes = o;
     for (int l = 0; l < 2; ++l) {
         ns_tile_shape(cfg->precision, 0, &p->sched[l].tile_x, &p->sched[l].tile_y);
@@ -645,8 +654,34 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         return fail(ctx, MENKF_E_ARG, "menkf_cycle: null buffer");
     if (a->nsteps < 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: nsteps must be >= 1");
     if (a->feedback != 0 && a->feedback != 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: feedback must be 0 or 1");
+    if (!ctx->idx) return fail(ctx, MENKF_E_ARG, "probes not set (menkf_set_probes)");
     menkf_status st;
-    if (a->aux_stream && a->aux_stream != stream) {
+    if (a->aux_stream && a->aux_stream != stream && p.defer_ok) {
+        // The fine forecast, x* and the small system of the x* column run on
+        // the second stream while the N_y x N_y factorisation (with d* = 0)
+        // runs on the first; z* follows once both are done.
+        hipStream_t s0 = (hipStream_t)stream, s1 = (hipStream_t)a->aux_stream;
+        st = menkf_forecast(ctx, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, stream);
+        if (st != MENKF_OK) return st;
+        hipError_t e = launch_gain_deferred_front(p, a->members, a->yobs, a->seed, a->cycle, ctx->idx, ctx->comp,
+                                                  ctx->ws, s0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (gain)");
+        if ((e = hipEventRecord(ctx->ev_fork, s0)) == hipSuccess) e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
+        st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
+        if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, a->aux_stream);
+        hipError_t e1 = st == MENKF_OK ? launch_xstar_factor(p, ctx->ws, s1) : hipSuccess;
+        hipError_t e0 = launch_gain_deferred_back(p, a->cycle, ctx->ws, s0);
+        // join also after a failed issue, so that a capture stays well formed
+        e = hipEventRecord(ctx->ev_join, s1);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s0, ctx->ev_join, 0);
+        if (st != MENKF_OK) return st;
+        if (e1 != hipSuccess) return hip_fail(ctx, e1, "menkf_cycle (x* system)");
+        if (e0 != hipSuccess) return hip_fail(ctx, e0, "menkf_cycle (gain)");
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (join)");
+        e = launch_xstar_gain(p, a->xstar, a->yobs, ctx->idx, ctx->comp, ctx->ws, s0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (x* column)");
+    } else if (a->aux_stream && a->aux_stream != stream) {
         hipStream_t s0 = (hipStream_t)stream, s1 = (hipStream_t)a->aux_stream;
         hipError_t e = hipEventRecord(ctx->ev_fork, s0);
         if (e == hipSuccess) e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
@@ -658,12 +693,14 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         if (e == hipSuccess) e = hipStreamWaitEvent(s0, ctx->ev_join, 0);
         if (st != MENKF_OK) return st;
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (join)");
+        st = menkf_restrict(ctx, a->fine, a->xstar, stream);
+        if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);
     } else {
         st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, stream);
         if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, stream);
+        if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, stream);
+        if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);
     }
-    if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, stream);
-    if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);
     if (st == MENKF_OK) st = menkf_update(ctx, a->members, a->deltac, stream);
     if (st == MENKF_OK)
         st = menkf_prolong_smooth(ctx, a->deltac, a->fine, a->fine_prev, a->n_sweeps, a->alpha, a->prolong_mode,

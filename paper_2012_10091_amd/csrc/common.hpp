@@ -175,6 +175,10 @@ struct Plan {
     int open;
     int obs_field;             // field the 1D observation reads (rho u for the Euler model)
     size_t off_trial, off_thf;
+    // deferred x* column (R = s^2 I): small system [[s^2 I + Y^T Y, .], [I, 0]],
+    // its Linv scratch, and the chunked partial Grams of Y
+    int defer_ok, gchunks, gpc;
+    size_t off_mg, off_mlinv, off_gpart;
 };
 
 constexpr int CHOL_NB = 64;
@@ -220,6 +224,16 @@ hipError_t launch_gain(const Plan &p, const void *members, const void *xstar, co
                        uint64_t seed, uint64_t cycle, const double *eps, const int32_t *idx,
                        const int32_t *comp, void *ws, hipStream_t s, bool advance_cycle = true);
 hipError_t launch_get_gain(const Plan &p, double *z, void *ws, hipStream_t s);
+// the gain with the x* column deferred: front (observation of the members,
+// anomalies, S, small system), back (factorisation, Z with z* = 0), the
+// small system's factorisation, then z* once x* is known
+hipError_t launch_gain_deferred_front(const Plan &p, const void *members, const double *yobs, uint64_t seed,
+                                      uint64_t cycle, const int32_t *idx, const int32_t *comp, void *ws,
+                                      hipStream_t s);
+hipError_t launch_gain_deferred_back(const Plan &p, uint64_t cycle, void *ws, hipStream_t s);
+hipError_t launch_xstar_factor(const Plan &p, void *ws, hipStream_t s);
+hipError_t launch_xstar_gain(const Plan &p, const void *xstar, const double *yobs, const int32_t *idx,
+                             const int32_t *comp, void *ws, hipStream_t s);
 hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipStream_t s);
 hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, double *y,
                           const int32_t *idx, const int32_t *comp, hipStream_t s);
