@@ -283,6 +283,40 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
     }
 
 
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def update_gemm_utilisation(cfg, cyc, reps=20):
+    """The member update X Z (the anomaly GEMM of the analysis) timed alone:
+    menkf_update on a scratch copy of the members with the gain factors of
+    the last cycle, HIP events on its own stream.  MFMA work counts the
+    BF16x3 products (3 x 2 N (N + 1) points); HBM bytes are one read and
+    one write of the members (the minimum for an in-place update)."""
+    import torch
+    stream = torch.cuda.Stream()
+    scratch = cyc.members.clone()
+    dc = torch.empty_like(cyc.dc)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        cyc.ctx.update(scratch, dc, stream=stream)
+        e0.record(stream)
+        for _ in range(reps):
+            cyc.ctx.update(scratch, dc, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    avg = e0.elapsed_time(e1) / 1e3 / reps
+    N = cfg.n_members
+    npts = cfg.n_coarse * 4
+    terms = 3
+    flops = terms * 2.0 * N * (N + 1) * npts
+    nbytes = 2.0 * N * npts * 4
+    return {"kernel": "update_bf16 (X Z, BF16x3 on MFMA, FP32 accumulation)", "avg_launch_us": avg * 1e6,
+            "mfma_tflops": flops / avg / 1e12, "mfma_frac_of_bf16_peak": flops / avg / 1e12 / BF16_MFMA_PEAK_TFLOPS,
+            "hbm_gbs": nbytes / avg / 1e9, "hbm_frac": nbytes / avg / 1e9 / HBM_PEAK_GBS}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ns_stage_64x4x256sq_traffic.md")
 
 
@@ -1028,6 +1062,9 @@ def main():
         log(f"bench: no trained weights at {wpath}; learned variant not timed")
     rl = stage_kernel_roofline(cfg, plain)
     log(f"bench: stage kernel avg {rl['avg_launch_us']:.1f} us, contract {rl['achieved']:.0f} GB/s")
+    ug = update_gemm_utilisation(cfg, plain)
+    log(f"bench: member update {ug['avg_launch_us']:.1f} us, MFMA {ug['mfma_tflops']:.0f} TFLOP/s "
+        f"({100 * ug['mfma_frac_of_bf16_peak']:.1f} % of BF16 peak), HBM {ug['hbm_gbs']:.0f} GB/s")
     out = {
         "metric": METRIC,
         "value": value,
@@ -1048,6 +1085,7 @@ def main():
             "schedules": {k: {"tile": list(v["tile"]), "member_chunk": v["member_chunk"]} for k, v in tuned.items()}
             if tuned else "default",
             "precision": "FP32 stencils, FP64 innovation covariance/Cholesky/gain of x*, BF16x3 member update",
+            "anomaly_gemm": ug,
             "variants": variants,
         },
         "roofline": {

@@ -96,7 +96,10 @@ def test_cycle_equals_the_calls_it_stands_for(aux):
 
 
 @pytest.mark.parametrize("cfg,ztol", [(configs.tiny_2d(), 1e-9), (configs.ragged_2d(), 1e-9),
-                                      (configs.CONFIGS["C1"], 1e-9)], ids=["tiny2d", "ragged2d", "C1-f64"])
+                                      (configs.CONFIGS["C1"], 1e-9),
+                                      (configs.tiny_2d(n_members=2, n_probes=3), 1e-9),
+                                      (configs.tiny_1d(precision="f64", n_members=2, n_probes=1), 1e-9)],
+                         ids=["tiny2d", "ragged2d", "C1-f64", "tiny2d-N2-Ny3", "tiny1d-f64-N2-Ny1"])
 def test_deferred_xstar_column_matches_the_factorisation(cfg, ztol):
     """The x* column of Z from the deferred path (second stream) equals the
     one of the N_y x N_y factorisation to FP64 roundoff; the member columns

@@ -197,6 +197,9 @@ ANALYSIS_CASES = [
     ("tiny2d-f32-N40", configs.tiny_2d(precision="f32", n_members=40, n_probes=70), 1e-9, 1e-4, 1e-5),
     ("C2-f32-N256", configs.CONFIGS["C2"], 1e-9, 1e-4, 1e-5),
     ("ragged2d-f32-plainbf16", configs.ragged_2d(precision="f32").with_(name="plain"), 1e-9, 2e-2, 1e-3),
+    # degenerate ends: two members (rank-one anomalies), a single probe
+    ("tiny1d-f64-N2-Ny1", configs.tiny_1d(precision="f64", n_members=2, n_probes=1), 1e-10, 1e-10, 1e-10),
+    ("tiny2d-f32-N2-Ny3", configs.tiny_2d(precision="f32", n_members=2, n_probes=3), 1e-9, 1e-4, 1e-5),
 ]
 
 
