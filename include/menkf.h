@@ -184,7 +184,7 @@ menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state_dev, int3
  * speed only, never results: every tile shape and chunking evaluates the
  * same arithmetic per grid point, so forecasts are bitwise identical.
  *   tile_x, tile_y  grid points per 256-thread workgroup of the 2D stencil,
- *                   one of 32x16, 64x8, 32x8, 16x16, 64x4, 32x32, 64x16 (FP32) or
+ *                   one of 32x16, 64x8, 32x8, 16x16, 64x4 (FP32) or
  *                   32x8, 16x8, 16x16, 64x4 (FP64); 0, 0 = the first of
  *                   the list.  Ignored by the 1D model.
  *   member_chunk    states advanced together through a whole forecast

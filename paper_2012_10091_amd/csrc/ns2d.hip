@@ -314,10 +314,8 @@ struct NSLauncher {
 
 // Stencil tile shapes (TX x TY points per 256-thread workgroup).  LDS per
 // workgroup: (2 (TX+8)(TY+8) + 9 (TX+4)(TY+4)) elements, e.g. 33.6 KB for
-// 32 x 16 in FP32; the 4-point-per-thread tiles 32 x 32 and 64 x 16 (59.5
-// and 62.8 KB) recompute fewer halo points per interior point.  The first
-// entry of each list is the default.
-static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}, {32, 32}, {64, 16}};
+// 32 x 16 in FP32.  The first entry of each list is the default.
+static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}};
 static const int kTilesF64[][2] = {{32, 8}, {16, 8}, {16, 16}, {64, 4}};
 
 int ns_tile_count(int precision) {
@@ -358,8 +356,6 @@ static hipError_t with_tile(int ti, const Fn &f) {
         case 2: return f.template run<32, 8>();
         case 3: return f.template run<16, 16>();
         case 4: return f.template run<64, 4>();
-        case 5: return f.template run<32, 32>();
-        case 6: return f.template run<64, 16>();
         default: return f.template run<32, 16>();
         }
     }
