@@ -591,37 +591,72 @@ __global__ __launch_bounds__(256) void gram_y_assemble(const double *__restrict_
     }
 }
 
-// z* = M^-1 Y^T (y^o - H(x*)) for the factored small system Mg (its Schur
-// block is -M^-1, lower triangle), written to zstar (zero-padded to npad)
-// and to column N of z64.  One workgroup of 1024 threads: member i's dot
-// product over the probes is split over 4 groups, combined in a fixed order.
-__global__ __launch_bounds__(1024) void xstar_gain(const double *__restrict__ hx, const double *__restrict__ yobs,
-                                                   const double *__restrict__ Yk, int kdim, int Ny, int N, int npad,
-                                                   const double *__restrict__ Mg, int npm, double *__restrict__ z64,
-                                                   double *__restrict__ zstar, const int32_t *__restrict__ info) {
-    __shared__ double vp[4][256];
-    __shared__ double v[256];
-    if (*info != 0) return;
-    const int t = threadIdx.x, i = t & 255, g = t >> 8;
+// Y^T (y^o - H(x*)) in partial sums over the probe chunks of the Gram:
+// part[c][i] for member i.  The chunk's probes are split over the four
+// waves (16 consecutive probes per wave at a time) and the wave sums are
+// combined in wave order through LDS.
+__global__ __launch_bounds__(1024) void xstar_partial(const double *__restrict__ hx, const double *__restrict__ yobs,
+                                                      const double *__restrict__ Yk, int kdim, int Ny, int N, int pc,
+                                                      double *__restrict__ part) {
+    __shared__ double red[4][256];
+    const int c = blockIdx.x, i = threadIdx.x & 255, w = threadIdx.x >> 8;
+    const int p0 = c * pc, p1 = min(Ny, p0 + pc);
     double acc = 0.0;
-    if (i < N)
-        for (int p = g; p < Ny; p += 4) acc += Yk[(long long)p * kdim + i] * (yobs[p] - hx[p]);
-    vp[g][i] = acc;
-    __syncthreads();
-    if (g == 0) v[i] = (vp[0][i] + vp[1][i]) + (vp[2][i] + vp[3][i]);
-    __syncthreads();
-    if (t < npad) {
-        double z = 0.0;
-        if (t < N) {
-            const int lm = 2 * npm;
-            const double *S = Mg + (long long)npm * lm + npm;
-            for (int b = 0; b < N; ++b) {
-                const double m = t >= b ? S[(long long)t * lm + b] : S[(long long)b * lm + t];
-                z -= m * v[b];
-            }
-            z64[(long long)N * N + t] = z;
+    if (i < N) {
+        for (int q = p0 + 16 * w; q < p1; q += 64) {
+            const int qe = min(q + 16, p1);
+#pragma unroll 4
+            for (int p = q; p < qe; ++p) acc += Yk[(long long)p * kdim + i] * (yobs[p] - hx[p]);
         }
-        zstar[t] = z;
+    }
+    red[w][i] = acc;
+    __syncthreads();
+    if (w == 0 && i < N) part[(long long)c * 256 + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+}
+
+// z* = M^-1 v with v the chunk sums (in chunk order) and M^-1 = -(Schur
+// block of the factored small system Mg, lower triangle), staged in LDS in
+// 64-row slabs; written to zstar (zero-padded to npad) and to column N of
+// z64.
+__global__ __launch_bounds__(256) void xstar_gain(const double *__restrict__ part, int nchunk, int N, int npad,
+                                                  const double *__restrict__ Mg, int npm, double *__restrict__ z64,
+                                                  double *__restrict__ zstar, const int32_t *__restrict__ info) {
+    __shared__ double v[256];
+    __shared__ double slab[64][65];
+    if (*info != 0) return;
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    if (t < N) {
+#pragma unroll 8
+        for (int c = 0; c < nchunk; ++c) acc += part[(long long)c * 256 + t];
+    }
+    v[t] = acc;
+    const int lm = 2 * npm;
+    const double *S = Mg + (long long)npm * lm + npm;
+    double z = 0.0;
+    // thread t takes row t of M^-1 against v; the 64 x 64 sub-blocks
+    // (rows r0.., columns b0..) are staged one at a time, each entry read from
+    // the stored lower triangle
+    for (int b0 = 0; b0 < N; b0 += 64) {
+        __syncthreads();   // v written; the previous slab is no longer read
+        for (int r0 = 0; r0 < npad && r0 < 256; r0 += 64) {
+            for (int e = t; e < 64 * 64; e += 256) {
+                const int rr = r0 + (e >> 6), bb = b0 + (e & 63);
+                double m = 0.0;
+                if (rr < N && bb < N) m = rr >= bb ? S[(long long)rr * lm + bb] : S[(long long)bb * lm + rr];
+                slab[e >> 6][e & 63] = m;
+            }
+            __syncthreads();
+            if (t >= r0 && t < r0 + 64 && t < N) {
+                const int bend = min(64, N - b0);
+                for (int bb = 0; bb < bend; ++bb) z -= slab[t - r0][bb] * v[b0 + bb];
+            }
+            __syncthreads();
+        }
+    }
+    if (t < npad) {
+        if (t < N) z64[(long long)N * N + t] = z;
+        zstar[t] = t < N ? z : 0.0;
     }
 }
 
@@ -909,15 +944,6 @@ static hipError_t gain_front(const Plan &p, const void *members, const void *xst
     hipLaunchKernelGGL(syrk_f64_mfma, dim3(nbs * (nbs + 1) / 2), dim3(256), lds, s, (const double *)Yk, p.kdim, p.Ny,
                        sample ? 0.0 : rdiag, A, p.ld);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (defer_xstar) {
-        // 4''. M = s^2 I + Y^T Y in the small augmented system
-        const int nt = p.npm / CHOL_NB, ntile = nt * (nt + 1) / 2;
-        hipLaunchKernelGGL(gram_y_partial, dim3(ntile, p.gchunks), dim3(256), 0, s, (const double *)Yk, p.kdim,
-                           p.nyp, p.gpc, (double *)(w + p.off_gpart));
-        hipLaunchKernelGGL(gram_y_assemble, dim3(64), dim3(256), 0, s, (const double *)(w + p.off_gpart), p.gchunks,
-                           ntile, N, p.npm, rdiag, (double *)(w + p.off_mg));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     return hipSuccess;
 }
 
@@ -971,6 +997,15 @@ hipError_t launch_gain_deferred_back(const Plan &p, uint64_t cycle, void *ws, hi
 hipError_t launch_xstar_factor(const Plan &p, void *ws, hipStream_t s) {
     char *w = (char *)ws;
     const size_t lds = 2 * 64 * LDP * sizeof(double);
+    // M = s^2 I + Y^T Y from the FP64 anomalies (untouched by the N_y x N_y
+    // factorisation running beside), in the small augmented system
+    const int nt = p.npm / CHOL_NB, ntile = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(gram_y_partial, dim3(ntile, p.gchunks), dim3(256), 0, s, (const double *)(w + p.off_yb),
+                       p.kdim, p.nyp, p.gpc, (double *)(w + p.off_gpart));
+    hipLaunchKernelGGL(gram_y_assemble, dim3(64), dim3(256), 0, s, (const double *)(w + p.off_gpart), p.gchunks,
+                       ntile, p.N, p.npm, p.cfg.obs_sigma * p.cfg.obs_sigma, (double *)(w + p.off_mg));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     return chol_blocked((double *)(w + p.off_mg), 2 * p.npm, p.npm / CHOL_NB, (double *)(w + p.off_mlinv),
                         (int32_t *)(w + p.off_info), lds, s);
 }
@@ -988,9 +1023,12 @@ hipError_t launch_xstar_gain(const Plan &p, const void *xstar, const double *yob
         hipLaunchKernelGGL(obs_eval<float>, g1, dim3(256), 0, s, (const float *)nullptr, 0LL, 0,
                            (const float *)xstar, idx, comp, p.Ny, hx, p.nyp, 1, p.dim, p.nx, p.ny, p.cfg.ratio,
                            p.nxc, p.nyc, p.open, p.obs_field);
-    hipLaunchKernelGGL(xstar_gain, dim3(1), dim3(1024), 0, s, (const double *)hx, yobs, (const double *)(w + p.off_yb),
-                       p.kdim, p.Ny, p.N, p.npad, (const double *)(w + p.off_mg), p.npm, (double *)(w + p.off_z),
-                       (double *)(w + p.off_zstar), (const int32_t *)(w + p.off_info));
+    double *part = (double *)(w + p.off_gpart);   // the Gram partials are consumed by now
+    hipLaunchKernelGGL(xstar_partial, dim3(p.gchunks), dim3(1024), 0, s, (const double *)hx, yobs,
+                       (const double *)(w + p.off_yb), p.kdim, p.Ny, p.N, p.gpc, part);
+    hipLaunchKernelGGL(xstar_gain, dim3(1), dim3(256), 0, s, (const double *)part, p.gchunks, p.N, p.npad,
+                       (const double *)(w + p.off_mg), p.npm, (double *)(w + p.off_z), (double *)(w + p.off_zstar),
+                       (const int32_t *)(w + p.off_info));
     return hipGetLastError();
 }
 
