@@ -622,17 +622,22 @@ menkf_status menkf_dual_cycle(const menkf_dual_args *a, menkf_stream stream) {
     if (e == hipSuccess) e = launch_param_update(p, thf, a->theta, a->theta_mean, ctx->ws, s);
     // state filter: members with theta_a, the fine run with its mean (on
     // the second stream if given: one workgroup beside the members')
-    if (e == hipSuccess && aux) {
+    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_dual_cycle");
+    if (aux) {
         e = hipEventRecord(ctx->ev_fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(aux, ctx->ev_fork, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_dual_cycle (fork)");
     }
-    if (e == hipSuccess)
-        e = launch_inlet_forecast(p, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->theta_mean, a->clock,
-                                  aux ? aux : s);
-    if (e == hipSuccess && aux) e = hipEventRecord(ctx->ev_join, aux);
-    if (e == hipSuccess)
-        e = launch_inlet_forecast(p, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, a->theta, a->clock, s);
-    if (e == hipSuccess && aux) e = hipStreamWaitEvent(s, ctx->ev_join, 0);
+    hipError_t ef = launch_inlet_forecast(p, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->theta_mean, a->clock,
+                                          aux ? aux : s);
+    e = launch_inlet_forecast(p, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, a->theta, a->clock, s);
+    if (aux) {
+        // join also after a failed issue, so that a capture stays well formed
+        hipError_t ej = hipEventRecord(ctx->ev_join, aux);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(s, ctx->ev_join, 0);
+        if (ej != hipSuccess) return hip_fail(ctx, ej, "menkf_dual_cycle (join)");
+    }
+    if (ef != hipSuccess) return hip_fail(ctx, ef, "menkf_dual_cycle (fine forecast)");
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_dual_cycle");
     menkf_status st = menkf_restrict(ctx, a->fine, a->xstar, stream);
     if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);
