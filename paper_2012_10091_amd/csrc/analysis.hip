@@ -202,95 +202,139 @@ __device__ __forceinline__ void tri_index(int t, int &bi, int &bj) {
 // complement).  Every kernel exits if the status word is set.
 constexpr int LDP = 65;  // padded LDS row (doubles)
 
+// 1/p for the pivot chain: the hardware reciprocal refined by two Newton
+// steps (y <- y + y (1 - p y)); its dependent chain is about half that of
+// the correctly rounded division, and the pivot reciprocal is the longest
+// part of a pivot step.
+__device__ __forceinline__ double pivot_recip(double p) {
+    double y = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-p, y, 1.0);
+    return fma(y, e, y);
+}
+
 // Factor the 64x64 diagonal block and invert its factor in one sweep of
 // 64 pivot steps.  W is the block being reduced (columns are never rescaled
-// in place) and Xw the rows of the inverse in unscaled form; at step j,
-// with piv = W[j][j],
-//   W[r][c]  -= W[r][j] W[c][j] / piv    (j < c <= r)      Schur update
-//   Xw[r][c] -= W[r][j] Xw[j][c] / piv   (r > j, c <= j)   inverse rows
-// and at the end L[r][c] = W[r][c] / d_c with d_c = sqrt(W[c][c]),
-// L^-1[r][c] = Xw[r][c] / d_r.
-// Thread t owns row r = t / 4 and the 16 columns c = 4 i + t % 4 of both W
-// and Xw in registers.  Step j only needs column j of W and row j of Xw from
-// other threads: their owners publish them to a double-buffered LDS slot,
-// so each pivot costs one barrier.  The step loop is unrolled at compile
-// time so that register indices are static.
+// in place) and X the rows of the inverse in unscaled form; at step j,
+// with m_r = W[r][j] / W[j][j] for r > j (0 otherwise),
+//   W[r][c] -= m_r W[c][j]   (c > j)        Schur update
+//   X[r][c] -= m_r X[j][c]   (all c)        inverse rows (X[j][c] = 0 for c > j)
+// and at the end L[r][c] = W[r][c] / d_c with d_c = sqrt(W[c][c]) at its
+// step, L^-1[r][c] = X[r][c] / d_r.
+// Thread t owns the 4x4 blocks (rows 4a..4a+3, columns 4b..4b+3, a = t / 16,
+// b = t % 16) of W and X in registers.  Step j publishes, double-buffered in
+// LDS, the column v = W[:, j] with zeros at rows <= j (so the update of
+// finished columns and of column j itself is a no-op and needs no test),
+// the row X[j][:] and 1/W[j][j]; every owned entry is then updated with
+// m = v * (1/W[j][j]): one barrier per pivot, no per-column branches.
+// The entries the next step publishes (column j + 1, row j + 1 of X, the
+// pivot, whose owner computes its reciprocal) are updated and written first
+// so that their latency overlaps the rest of the update.  A pivot that is
+// not positive publishes -1 as its reciprocal; it is recorded and the
+// sweep runs to the end (no early exit inside the pivot loop) before the
+// status word is set.
 // The block is read from src (row stride lds_: global A or an LDS copy) and
 // the factor written to Ak (row stride ld).  256 threads; must be entered by
 // the whole workgroup.
 __device__ __forceinline__ void chol_diag_block(const double *src, long long lds_, double *__restrict__ Ak,
                                                 long long ld, int k, double *__restrict__ Linv,
                                                 int32_t *__restrict__ info) {
-    __shared__ double colbuf[2][64];
-    __shared__ double rowbuf[2][64];
-    __shared__ double dsq[64];
+    __shared__ __attribute__((aligned(16))) double colbuf[2][64];
+    __shared__ __attribute__((aligned(16))) double rowbuf[2][64];
+    __shared__ double invbuf[2];
+    __shared__ double pivbuf[64];
     const int t = threadIdx.x;
-    const int r = t >> 2, q = t & 3;
-    double w[16], x[16];
+    const int a = t >> 4, b = t & 15;
+    double w[4][4], x[4][4];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int c = 4 * i + q;
-        w[i] = c <= r ? src[(long long)r * lds_ + c] : 0.0;
-        x[i] = c == r ? 1.0 : 0.0;
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = 4 * a + i, c = 4 * b + q;
+            w[i][q] = c <= r ? src[(long long)r * lds_ + c] : 0.0;
+            x[i][q] = c == r ? 1.0 : 0.0;
+        }
+    // step 0's column, row and pivot
+    if (b == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) colbuf[0][4 * a + i] = 4 * a + i > 0 ? w[i][0] : 0.0;
     }
+    if (a == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rowbuf[0][4 * b + q] = x[0][q];
+    }
+    if (t == 0) {
+        const double p = w[0][0];
+        pivbuf[0] = p;
+        invbuf[0] = p > 0.0 ? pivot_recip(p) : -1.0;
+    }
+    __syncthreads();
     int bad = 0;
-    // Pivot step: every thread reads one published value per owned column
-    // (row j of Xw for c <= j, column j of W otherwise).  Which of the two a
-    // column group takes is known at compile time except for the group that
-    // holds column j.  Rows r <= j use m = 0.  W is updated above its
-    // diagonal too: those entries are never read, and leaving out the mask
-    // keeps the step free of per-column selects.
-#define MENKF_DIAG_STEP(J)                                                   \
-    if (!bad) {                                                              \
-        constexpr int b_ = (J) & 1, ji_ = (J) >> 2, jq_ = (J) & 3;           \
-        if (q == jq_) colbuf[b_][r] = w[ji_];                                \
-        if (r == (J)) {                                                      \
-            _Pragma("unroll") for (int i = 0; i < 16; ++i)                   \
-                rowbuf[b_][4 * i + q] = x[i];                                \
-        }                                                                    \
-        __syncthreads();                                                     \
-        const double piv = colbuf[b_][J];                                    \
-        if (t == 0) dsq[J] = piv;                                            \
-        bad = (piv > 0.0) ? 0 : (J) + 1;                                     \
-        const double inv = 1.0 / piv;                                        \
-        const double m = r > (J) ? colbuf[b_][r] * inv : 0.0;                \
-        _Pragma("unroll") for (int i = 0; i < 16; ++i) {                     \
-            const int c = 4 * i + q;                                         \
-            if (4 * i + 3 <= (J)) {                                          \
-                x[i] -= m * rowbuf[b_][c];                                   \
-            } else if (4 * i > (J)) {                                        \
-                w[i] -= m * colbuf[b_][c];                                   \
-            } else {                                                         \
-                const bool lo = c <= (J);                                    \
-                const double v = lo ? rowbuf[b_][c] : colbuf[b_][c];         \
-                const double nv = (lo ? x[i] : w[i]) - m * v;                \
-                x[i] = lo ? nv : x[i];                                       \
-                w[i] = lo ? w[i] : nv;                                       \
-            }                                                                \
-        }                                                                    \
+    for (int jb = 0; jb < 16; ++jb) {
+#pragma unroll
+        for (int jc = 0; jc < 4; ++jc) {
+            const int j = 4 * jb + jc;
+            const int buf = jc & 1;
+            // every read of the step is issued before any is used
+            const double inv = invbuf[buf];
+            const double2 *cb = (const double2 *)colbuf[buf];
+            const double2 *rb = (const double2 *)rowbuf[buf];
+            const double2 cr0 = cb[2 * a], cr1 = cb[2 * a + 1];
+            const double2 vc0 = cb[2 * b], vc1 = cb[2 * b + 1];
+            const double2 xr0 = rb[2 * b], xr1 = rb[2 * b + 1];
+            if (!(inv > 0.0) && bad == 0) bad = j + 1;
+            const double m[4] = {cr0.x * inv, cr0.y * inv, cr1.x * inv, cr1.y * inv};
+            const double v[4] = {vc0.x, vc0.y, vc1.x, vc1.y};
+            const double xr[4] = {xr0.x, xr0.y, xr1.x, xr1.y};
+            const int jc1 = (jc + 1) & 3;   // local column / row of index j + 1
+            const int jb1 = (j + 1) >> 2;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[i][jc1] -= m[i] * v[jc1];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[jc1][q] -= m[jc1] * xr[q];
+            if (j + 1 < 64) {
+                if (b == jb1) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) colbuf[buf ^ 1][4 * a + i] = 4 * a + i > j + 1 ? w[i][jc1] : 0.0;
+                    if (a == jb1) {
+                        const double p = w[jc1][jc1];
+                        pivbuf[j + 1] = p;
+                        invbuf[buf ^ 1] = p > 0.0 ? pivot_recip(p) : -1.0;
+                    }
+                }
+                if (a == jb1) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) rowbuf[buf ^ 1][4 * b + q] = x[jc1][q];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q != jc1) w[i][q] -= m[i] * v[q];
+                    if (i != jc1) x[i][q] -= m[i] * xr[q];
+                }
+            __syncthreads();
+        }
     }
-#define MENKF_DIAG_STEP4(J) MENKF_DIAG_STEP(J) MENKF_DIAG_STEP(J + 1) MENKF_DIAG_STEP(J + 2) MENKF_DIAG_STEP(J + 3)
-#define MENKF_DIAG_STEP16(J) MENKF_DIAG_STEP4(J) MENKF_DIAG_STEP4(J + 4) MENKF_DIAG_STEP4(J + 8) MENKF_DIAG_STEP4(J + 12)
-    MENKF_DIAG_STEP16(0)
-    MENKF_DIAG_STEP16(16)
-    MENKF_DIAG_STEP16(32)
-    MENKF_DIAG_STEP16(48)
-#undef MENKF_DIAG_STEP16
-#undef MENKF_DIAG_STEP4
-#undef MENKF_DIAG_STEP
     if (bad) {
         if (t == 0) *info = k * 64 + bad;
         return;
     }
+    __shared__ double dsq[64];
+    if (t < 64) dsq[t] = sqrt(pivbuf[t]);     // pivots -> d_c
     __syncthreads();
-    if (t < 64) dsq[t] = sqrt(dsq[t]);     // pivots -> d_c
-    __syncthreads();
-    const double dr = dsq[r];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int c = 4 * i + q;
-        if (c <= r) Ak[(long long)r * ld + c] = c == r ? dr : w[i] / dsq[c];
-        Linv[r * 64 + c] = c <= r ? x[i] / dr : 0.0;
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * a + i;
+        const double dr = dsq[r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * b + q;
+            if (c <= r) Ak[(long long)r * ld + c] = c == r ? dr : w[i][q] / dsq[c];
+            Linv[r * 64 + c] = c <= r ? x[i][q] / dr : 0.0;
+        }
     }
 }
 
