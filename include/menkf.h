@@ -457,7 +457,11 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  * the fine forecast is issued there, forked from and joined back into
  * stream with two events the context owns.  With MENKF_GAIN_EXACT_R it
  * runs beside the N_y x N_y factorisation: the member forecast comes
- * first, the factorisation runs with d* = 0, and the x* column of the gain
+ * first, the factorisation runs with d* = 0 (the fine forecast is forked
+ * from it once each remaining trailing update has at most three tiles per
+ * compute unit, so that it fills the GPU beside the latency-bound late
+ * block steps rather than the throughput-bound early ones), and the x*
+ * column of the gain
  * follows once x* is known through the identity
  *   z* = Y^T (Y Y^T + s^2 I)^-1 d* = (s^2 I + Y^T Y)^-1 Y^T d*
  * (the N_e x N_e system is factored on aux_stream too).  The member columns

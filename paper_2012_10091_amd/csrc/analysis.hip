@@ -911,9 +911,24 @@ hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, d
 
 // Blocked Cholesky of the first nbs * 64 columns of the ld x ld matrix M
 // (lower triangle, row-major), Schur complement on the remaining rows.
-static hipError_t chol_blocked(double *A, int ld, int nbs, double *Linv, int32_t *info, size_t lds, hipStream_t s) {
+// With mark set, the event is recorded on s as soon as every trailing
+// update still to be issued has at most mark_tiles tiles (before the first
+// launch if that already holds): from there on the block steps are bound by
+// the latency of the diagonal factorisations and leave most of the GPU
+// idle, which is when a caller forks independent work off this point.
+static hipError_t chol_blocked(double *A, int ld, int nbs, double *Linv, int32_t *info, size_t lds, hipStream_t s,
+                               hipEvent_t mark = nullptr, int mark_tiles = 0) {
     hipError_t e;
     const int nblk = ld / CHOL_NB;
+    auto tiles = [nblk](int k) {
+        const int below = nblk - k - 1;
+        return below > 0 ? below * (below + 1) / 2 : 0;
+    };
+    bool marked = false;
+    if (mark && tiles(0) <= mark_tiles) {
+        if ((e = hipEventRecord(mark, s)) != hipSuccess) return e;
+        marked = true;
+    }
     hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, ld, 0, Linv, info);
     for (int k = 0; k < nbs; ++k) {
         const int below = nblk - k - 1;
@@ -925,6 +940,10 @@ static hipError_t chol_blocked(double *A, int ld, int nbs, double *Linv, int32_t
             hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, A, ld, k + 1, Linv, info);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (mark && !marked && (k + 1 >= nbs || tiles(k + 1) <= mark_tiles)) {
+            if ((e = hipEventRecord(mark, s)) != hipSuccess) return e;
+            marked = true;
+        }
     }
     return hipSuccess;
 }
@@ -992,7 +1011,8 @@ static hipError_t gain_front(const Plan &p, const void *members, const void *xst
 }
 
 // Factorisation and the gain factors (steps 5-6).
-static hipError_t gain_back(const Plan &p, uint64_t cycle, char *w, hipStream_t s, bool advance_cycle) {
+static hipError_t gain_back(const Plan &p, uint64_t cycle, char *w, hipStream_t s, bool advance_cycle,
+                            hipEvent_t mark = nullptr, int mark_tiles = 0) {
     int32_t *info = (int32_t *)(w + p.off_info);
     double *A = (double *)(w + p.off_a);
     double *Linv = (double *)(w + p.off_linv);
@@ -1013,7 +1033,7 @@ static hipError_t gain_back(const Plan &p, uint64_t cycle, char *w, hipStream_t 
         return extract_gain(p, As, p.lds, p.npm, w, dcycle, s);
     }
     // 5. blocked Cholesky of the first nyp columns, Schur complement on the rest
-    if ((e = chol_blocked(A, p.ld, p.nyp / CHOL_NB, Linv, info, lds, s)) != hipSuccess) return e;
+    if ((e = chol_blocked(A, p.ld, p.nyp / CHOL_NB, Linv, info, lds, s, mark, mark_tiles)) != hipSuccess) return e;
     // 6. Z
     return extract_gain(p, A, p.ld, p.nyp, w, dcycle, s);
 }
@@ -1034,8 +1054,9 @@ hipError_t launch_gain_deferred_front(const Plan &p, const void *members, const 
     return gain_front(p, members, nullptr, yobs, seed, cycle, nullptr, idx, comp, (char *)ws, s, true);
 }
 
-hipError_t launch_gain_deferred_back(const Plan &p, uint64_t cycle, void *ws, hipStream_t s) {
-    return gain_back(p, cycle, (char *)ws, s, true);
+hipError_t launch_gain_deferred_back(const Plan &p, uint64_t cycle, void *ws, hipStream_t s, hipEvent_t mark,
+                                     int mark_tiles) {
+    return gain_back(p, cycle, (char *)ws, s, true, mark, mark_tiles);
 }
 
 hipError_t launch_xstar_factor(const Plan &p, void *ws, hipStream_t s) {

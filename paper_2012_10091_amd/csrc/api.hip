@@ -21,6 +21,7 @@ struct menkf_ctx {
     const int32_t *idx = nullptr;
     const int32_t *comp = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // menkf_cycle with an aux stream
+    int n_cus = 256;                                     // compute units of the workspace's device
     char err[512] = {0};
     ~menkf_ctx() {
         if (ev_fork) hipEventDestroy(ev_fork);
@@ -232,6 +233,10 @@ menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws, size_t bytes) {
     hipError_t e = hipSuccess;
     if (!ctx->ev_fork) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess && !ctx->ev_join) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+    int dev = 0, ncu = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && ncu > 0) ctx->n_cus = ncu;
     if (e == hipSuccess) e = launch_set_word((int32_t *)((char *)ws + ctx->plan.off_info), 0, nullptr);
     if (e == hipSuccess) e = launch_set_word64((uint64_t *)((char *)ws + ctx->plan.off_info + 64), 1, nullptr);
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_set_workspace");
@@ -671,12 +676,19 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         hipError_t e = launch_gain_deferred_front(p, a->members, a->yobs, a->seed, a->cycle, ctx->idx, ctx->comp,
                                                   ctx->ws, s0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (gain)");
-        if ((e = hipEventRecord(ctx->ev_fork, s0)) == hipSuccess) e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
+        // The factorisation is issued first and records the fork event once
+        // its remaining trailing updates fit about three workgroups per
+        // compute unit: the early block steps, bound by the throughput of
+        // their updates, run alone, and the fine forecast fills the GPU
+        // beside the later ones, which are bound by the latency of the
+        // diagonal factorisations.
+        hipError_t e0 = launch_gain_deferred_back(p, a->cycle, ctx->ws, s0, ctx->ev_fork, 3 * ctx->n_cus);
+        if (e0 != hipSuccess) (void)hipEventRecord(ctx->ev_fork, s0);   // keep the fork well formed
+        e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
         st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
         if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, a->aux_stream);
         hipError_t e1 = st == MENKF_OK ? launch_xstar_factor(p, ctx->ws, s1) : hipSuccess;
-        hipError_t e0 = launch_gain_deferred_back(p, a->cycle, ctx->ws, s0);
         // join also after a failed issue, so that a capture stays well formed
         e = hipEventRecord(ctx->ev_join, s1);
         if (e == hipSuccess) e = hipStreamWaitEvent(s0, ctx->ev_join, 0);

@@ -230,7 +230,10 @@ hipError_t launch_get_gain(const Plan &p, double *z, void *ws, hipStream_t s);
 hipError_t launch_gain_deferred_front(const Plan &p, const void *members, const double *yobs, uint64_t seed,
                                       uint64_t cycle, const int32_t *idx, const int32_t *comp, void *ws,
                                       hipStream_t s);
-hipError_t launch_gain_deferred_back(const Plan &p, uint64_t cycle, void *ws, hipStream_t s);
+// The factorisation of the deferred gain; mark is recorded on s once the
+// remaining trailing updates have at most mark_tiles tiles each.
+hipError_t launch_gain_deferred_back(const Plan &p, uint64_t cycle, void *ws, hipStream_t s, hipEvent_t mark,
+                                     int mark_tiles);
 hipError_t launch_xstar_factor(const Plan &p, void *ws, hipStream_t s);
 hipError_t launch_xstar_gain(const Plan &p, const void *xstar, const double *yobs, const int32_t *idx,
                              const int32_t *comp, void *ws, hipStream_t s);
