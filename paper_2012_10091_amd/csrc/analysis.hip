@@ -240,6 +240,10 @@ __device__ __forceinline__ double pivot_recip(double p) {
 __device__ __forceinline__ void chol_diag_block(const double *src, long long lds_, double *__restrict__ Ak,
                                                 long long ld, int k, double *__restrict__ Linv,
                                                 int32_t *__restrict__ info) {
+    // The pivot chain is the critical path of the factorisation and issues
+    // little; when other kernels share its compute unit (a forecast on a
+    // second stream), the highest wave priority lets it issue first.
+    __builtin_amdgcn_s_setprio(3);
     __shared__ __attribute__((aligned(16))) double colbuf[2][64];
     __shared__ __attribute__((aligned(16))) double rowbuf[2][64];
     __shared__ double invbuf[2];
@@ -466,6 +470,7 @@ __global__ __launch_bounds__(256) void chol_panel(double *__restrict__ A, int ld
                                                   const int32_t *__restrict__ info) {
     extern __shared__ double smem_d[];
     if (*info != 0) return;
+    __builtin_amdgcn_s_setprio(3);   // on the factorisation's critical path, like the diagonal block
     const int i = k + 1 + blockIdx.x;
     double *Aik = A + (long long)(i * 64) * ld + k * 64;
     // X = A_ik Linv^T, in place (A_ik is staged in LDS before any write)
@@ -487,6 +492,7 @@ __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int l
     const double *Ljk = A + (long long)(j * 64) * ld + k * 64;
     double *Aij = A + (long long)(i * 64) * ld + j * 64;
     const bool lookahead = blockIdx.x == 0 && k + 1 < nbs;
+    if (lookahead) __builtin_amdgcn_s_setprio(3);   // the look-ahead tile leads to the next pivot chain
     // the 16 entries of A_ij this thread updates, loaded while the MFMA runs
     double old[16];
     {
