@@ -464,7 +464,8 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  * column of the gain
  * follows once x* is known through the identity
  *   z* = Y^T (Y Y^T + s^2 I)^-1 d* = (s^2 I + Y^T Y)^-1 Y^T d*
- * (the N_e x N_e system is factored on aux_stream too).  The member columns
+ * (the N_e x N_e system, which needs only the anomalies, is factored on
+ * aux_stream too, forked right after the gain's front end).  The member columns
  * of Z are bitwise those of menkf_gain; z*, delta^C and the fine state
  * agree with it to FP64 roundoff.  In the other gain modes the fine
  * forecast runs beside the member forecast and results are bitwise the

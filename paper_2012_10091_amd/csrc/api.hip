@@ -21,11 +21,13 @@ struct menkf_ctx {
     const int32_t *idx = nullptr;
     const int32_t *comp = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // menkf_cycle with an aux stream
+    hipEvent_t ev_front = nullptr;                       // end of the gain's front end (deferred path)
     int n_cus = 256;                                     // compute units of the workspace's device
     char err[512] = {0};
     ~menkf_ctx() {
         if (ev_fork) hipEventDestroy(ev_fork);
         if (ev_join) hipEventDestroy(ev_join);
+        if (ev_front) hipEventDestroy(ev_front);
     }
 };
 
@@ -233,6 +235,7 @@ menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws, size_t bytes) {
     hipError_t e = hipSuccess;
     if (!ctx->ev_fork) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess && !ctx->ev_join) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess && !ctx->ev_front) e = hipEventCreateWithFlags(&ctx->ev_front, hipEventDisableTiming);
     int dev = 0, ncu = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -676,19 +679,24 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         hipError_t e = launch_gain_deferred_front(p, a->members, a->yobs, a->seed, a->cycle, ctx->idx, ctx->comp,
                                                   ctx->ws, s0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (gain)");
-        // The factorisation is issued first and records the fork event once
-        // its remaining trailing updates fit about three workgroups per
-        // compute unit: the early block steps, bound by the throughput of
-        // their updates, run alone, and the fine forecast fills the GPU
-        // beside the later ones, which are bound by the latency of the
-        // diagonal factorisations.
+        // The small system of the x* column needs only the anomalies: it is
+        // forked right after the front end and runs beside the first block
+        // steps of the factorisation.
+        if ((e = hipEventRecord(ctx->ev_front, s0)) == hipSuccess) e = hipStreamWaitEvent(s1, ctx->ev_front, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
+        hipError_t e1 = launch_xstar_factor(p, ctx->ws, s1);
+        // The factorisation is issued next and records the second fork
+        // event once its remaining trailing updates fit about three
+        // workgroups per compute unit: the early block steps, bound by the
+        // throughput of their updates, run without the fine forecast, which
+        // then fills the GPU beside the later ones, bound by the latency of
+        // the diagonal factorisations.
         hipError_t e0 = launch_gain_deferred_back(p, a->cycle, ctx->ws, s0, ctx->ev_fork, 3 * ctx->n_cus);
         if (e0 != hipSuccess) (void)hipEventRecord(ctx->ev_fork, s0);   // keep the fork well formed
         e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
         st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
         if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, a->aux_stream);
-        hipError_t e1 = st == MENKF_OK ? launch_xstar_factor(p, ctx->ws, s1) : hipSuccess;
         // join also after a failed issue, so that a capture stays well formed
         e = hipEventRecord(ctx->ev_join, s1);
         if (e == hipSuccess) e = hipStreamWaitEvent(s0, ctx->ev_join, 0);
