@@ -95,11 +95,21 @@ def test_cycle_equals_the_calls_it_stands_for(aux):
     assert a["ctx"].get_status() == 0
 
 
+def _mid_fork_cfg():
+    # 4096 probes: 64 block steps whose first trailing updates have more
+    # tiles than three per compute unit, so the second stream's fine
+    # forecast is forked from inside the factorisation (and the x* system
+    # right after the gain's front end)
+    return configs.tiny_2d(nx=256, ny=256, n_members=16, n_probes=4096, seed=2012 + 41)
+
+
 @pytest.mark.parametrize("cfg,ztol", [(configs.tiny_2d(), 1e-9), (configs.ragged_2d(), 1e-9),
                                       (configs.CONFIGS["C1"], 1e-9),
                                       (configs.tiny_2d(n_members=2, n_probes=3), 1e-9),
-                                      (configs.tiny_1d(precision="f64", n_members=2, n_probes=1), 1e-9)],
-                         ids=["tiny2d", "ragged2d", "C1-f64", "tiny2d-N2-Ny3", "tiny1d-f64-N2-Ny1"])
+                                      (configs.tiny_1d(precision="f64", n_members=2, n_probes=1), 1e-9),
+                                      (_mid_fork_cfg(), 1e-9)],
+                         ids=["tiny2d", "ragged2d", "C1-f64", "tiny2d-N2-Ny3", "tiny1d-f64-N2-Ny1",
+                              "256sq-Ny4096-mid-fork"])
 def test_deferred_xstar_column_matches_the_factorisation(cfg, ztol):
     """The x* column of Z from the deferred path (second stream) equals the
     one of the N_y x N_y factorisation to FP64 roundoff; the member columns
@@ -123,6 +133,34 @@ def test_deferred_xstar_column_matches_the_factorisation(cfg, ztol):
     assert rel_l2(za[N], zb[N]) < ztol, rel_l2(za[N], zb[N])
     assert rel_l2(to_np(a[4]), to_np(b[4])) < (1e-9 if cfg.precision == "f64" else 1e-6)
     assert ctx_a.get_status() == 0
+
+
+def test_two_stream_cycle_graph_replays_match_eager_at_a_mid_fork_size():
+    """menkf_cycle with a second stream, captured once and replayed three
+    times with eager cycles and synchronisations in between: every replay
+    is bitwise the eager cycle (both forks of the second stream, the one
+    inside the factorisation included)."""
+    import paper_2012_10091_amd as m
+    cfg = _mid_fork_cfg()
+    g_i, e_i = _instance(cfg), _instance(cfg)
+    side_g, side_e = torch.cuda.Stream(), torch.cuda.Stream()
+    stream = torch.cuda.Stream()
+    say("graph of a two-stream cycle at 4096 probes, 3 replays against eager cycles")
+    with torch.cuda.stream(stream):
+        m.Graph.begin(stream)
+        g_i["ctx"].cycle(g_i["fine"], g_i["prev"], g_i["members"], g_i["xs"], g_i["dc"], g_i["y"], cfg.seed + 5,
+                         1, cfg.n_obs, n_sweeps=1, aux_stream=side_g)
+        graph = m.Graph.end(stream)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        e_i["ctx"].cycle(e_i["fine"], e_i["prev"], e_i["members"], e_i["xs"], e_i["dc"], e_i["y"], cfg.seed + 5,
+                         1, cfg.n_obs, n_sweeps=1, aux_stream=side_e)
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        stream.synchronize()
+        assert torch.equal(g_i["members"], e_i["members"]), rep
+        assert torch.equal(g_i["fine"], e_i["fine"]), rep
+    assert g_i["ctx"].get_status() == 0 and e_i["ctx"].get_status() == 0
 
 
 def test_c1_cycles_fp64_with_the_deferred_column_match_oracle():
