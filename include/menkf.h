@@ -169,6 +169,9 @@ menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws_dev, size_t bytes);
  * copies the tables to the host once (synchronously) and rejects nodes
  * outside the fine grid or components other than 0 (1D) / 0, 1 (2D). */
 menkf_status menkf_set_probes(menkf_ctx *ctx, const int32_t *idx_dev, const int32_t *comp_dev);
+/* The same call under the name of the observation-setting step: identical
+ * arguments, contract and errors. */
+menkf_status menkf_set_observations(menkf_ctx *ctx, const int32_t *idx_dev, const int32_t *comp_dev);
 
 /* Explicit forecast (state-evolution equation; Algo. 4 step 2 for
  * level = MENKF_FINE with nb = 1, Algo. 3 step 2 for level = MENKF_COARSE
@@ -332,6 +335,25 @@ typedef struct {
 
 menkf_status menkf_net_train_workspace_size(int32_t batch, int32_t crop, size_t *bytes);
 menkf_status menkf_net_train_step(const menkf_net_train *t, menkf_stream stream);
+
+/* The training step in its three phases, on the same descriptor and
+ * workspace (menkf_net_train_step = forward, backward, and Adam when
+ * apply_adam is set; the three calls in that order give bitwise its
+ * results):
+ *   menkf_net_forward:  layer activations of the crops into the workspace,
+ *                       the batch loss into loss_dev and its gradient with
+ *                       respect to the network output (workspace);
+ *   menkf_net_backward: the parameter gradient into grad, from what the
+ *                       last menkf_net_forward on this workspace left
+ *                       (calling it without one reads stale activations);
+ *   menkf_net_adam:     the Adam update of params (moments adam_m, adam_v,
+ *                       1-based step; apply_adam is not read) from grad,
+ *                       then the BF16 repack into wpacked if it is set.
+ * Argument checks as for menkf_net_train_step (Adam needs its moment
+ * buffers and step >= 1). */
+menkf_status menkf_net_forward(const menkf_net_train *t, menkf_stream stream);
+menkf_status menkf_net_backward(const menkf_net_train *t, menkf_stream stream);
+menkf_status menkf_net_adam(const menkf_net_train *t, menkf_stream stream);
 
 /* Synchronise the stream and read the device status word into *info
  * (0 = fine, j+1 = first non-positive pivot at column j).  Returns

@@ -109,6 +109,7 @@ SIGNATURES = {
     "menkf_workspace_size": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
     "menkf_set_workspace": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "menkf_set_probes": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "menkf_set_observations": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "menkf_forecast": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "menkf_set_schedule": (c_int32, [c_void_p, c_int32, ctypes.POINTER(MenkfSchedule)]),
     "menkf_get_schedule": (c_int32, [c_void_p, c_int32, ctypes.POINTER(MenkfSchedule)]),
@@ -126,6 +127,9 @@ SIGNATURES = {
     "menkf_net_pack": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "menkf_net_train_workspace_size": (c_int32, [c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "menkf_net_train_step": (c_int32, [ctypes.POINTER(MenkfNetTrain), c_void_p]),
+    "menkf_net_forward": (c_int32, [ctypes.POINTER(MenkfNetTrain), c_void_p]),
+    "menkf_net_backward": (c_int32, [ctypes.POINTER(MenkfNetTrain), c_void_p]),
+    "menkf_net_adam": (c_int32, [ctypes.POINTER(MenkfNetTrain), c_void_p]),
     "menkf_observe": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
     "menkf_diagnostics": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -163,6 +163,14 @@ class Context:
         self._probes = (idx.contiguous(), comp.contiguous())
         self._check(self.lib.menkf_set_probes(self.handle, _ptr(self._probes[0]), _ptr(self._probes[1])))
 
+    def set_observations(self, idx: torch.Tensor, comp: torch.Tensor):
+        """menkf_set_observations: the same call as set_probes."""
+        for t in (idx, comp):
+            if t.dtype != torch.int32 or not t.is_cuda or t.numel() != self.Ny:
+                raise ValueError("probe tables must be CUDA int32 tensors of n_probes entries")
+        self._probes = (idx.contiguous(), comp.contiguous())
+        self._check(self.lib.menkf_set_observations(self.handle, _ptr(self._probes[0]), _ptr(self._probes[1])))
+
     def forecast(self, level: int, state: torch.Tensor, nsteps: int, prev: Optional[torch.Tensor] = None,
                  stream=None):
         shape = self.fine_shape if level == MENKF_FINE else self.coarse_shape
@@ -537,15 +545,12 @@ class Trainer:
         self.workspace = torch.empty(n.value, dtype=torch.uint8, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
 
-    def step(self, dproj, xf, target, crops, apply_adam=True, stream=None):
-        """dproj, xf, target: (npairs, 4, H, W) float32 CUDA; crops: (batch, 3) int32 CUDA."""
+    def _desc(self, dproj, xf, target, crops, apply_adam):
         for t in (dproj, xf, target):
             if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 4:
                 raise ValueError("fields must be contiguous float32 CUDA (npairs, 4, H, W)")
         if crops.dtype != torch.int32 or tuple(crops.shape) != (self.batch, 3) or not crops.is_cuda:
             raise ValueError("crops must be int32 CUDA (batch, 3)")
-        if apply_adam:
-            self.step_count += 1
         d = _lib.MenkfNetTrain()
         d.params, d.grad = self.net.params.data_ptr(), self.grad.data_ptr()
         d.adam_m, d.adam_v = self.m.data_ptr(), self.v.data_ptr()
@@ -564,8 +569,33 @@ class Trainer:
         d.loss_dev = self.loss.data_ptr()
         d.workspace_dev = self.workspace.data_ptr()
         d.workspace_bytes = self.workspace.numel()
-        st = self.lib.menkf_net_train_step(ctypes.byref(d), _stream(stream))
+        return d
+
+    def _call(self, fn, d, stream):
+        st = fn(ctypes.byref(d), _stream(stream))
         if st != 0:
             raise MenkfError(st, last_error(None))
+
+    def step(self, dproj, xf, target, crops, apply_adam=True, stream=None):
+        """dproj, xf, target: (npairs, 4, H, W) float32 CUDA; crops: (batch, 3) int32 CUDA."""
+        if apply_adam:
+            self.step_count += 1
+        d = self._desc(dproj, xf, target, crops, apply_adam)
+        self._call(self.lib.menkf_net_train_step, d, stream)
         return self.loss
+
+    def forward(self, dproj, xf, target, crops, stream=None):
+        """menkf_net_forward: activations and the batch loss (returned tensor)."""
+        self._call(self.lib.menkf_net_forward, self._desc(dproj, xf, target, crops, False), stream)
+        return self.loss
+
+    def backward(self, dproj, xf, target, crops, stream=None):
+        """menkf_net_backward: the parameter gradient (self.grad) from the last forward."""
+        self._call(self.lib.menkf_net_backward, self._desc(dproj, xf, target, crops, False), stream)
+        return self.grad
+
+    def adam(self, dproj, xf, target, crops, stream=None):
+        """menkf_net_adam: one Adam update of the parameters from self.grad."""
+        self.step_count += 1
+        self._call(self.lib.menkf_net_adam, self._desc(dproj, xf, target, crops, True), stream)
 

@@ -267,6 +267,10 @@ menkf_status menkf_set_probes(menkf_ctx *ctx, const int32_t *idx, const int32_t 
     return MENKF_OK;
 }
 
+menkf_status menkf_set_observations(menkf_ctx *ctx, const int32_t *idx, const int32_t *comp) {
+    return menkf_set_probes(ctx, idx, comp);
+}
+
 #define NEED_WS(ctx)                                                                         \
     do {                                                                                     \
         if (!(ctx)) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");                        \
@@ -501,22 +505,50 @@ menkf_status menkf_net_train_workspace_size(int32_t batch, int32_t crop, size_t 
     return MENKF_OK;
 }
 
-menkf_status menkf_net_train_step(const menkf_net_train *t, menkf_stream stream) {
-    if (!t) return fail(nullptr, MENKF_E_ARG, "null train descriptor");
+static menkf_status check_train(const menkf_net_train *t, bool adam, const char *who) {
+    if (!t) return fail(nullptr, MENKF_E_ARG, "%s: null train descriptor", who);
     if (!t->params || !t->grad || !t->dproj || !t->xf || !t->target || !t->crops_dev || !t->loss_dev ||
         !t->workspace_dev)
-        return fail(nullptr, MENKF_E_ARG, "null pointer in the train descriptor");
-    if (t->apply_adam && (!t->adam_m || !t->adam_v || t->step < 1))
-        return fail(nullptr, MENKF_E_ARG, "Adam needs moment buffers and step >= 1");
+        return fail(nullptr, MENKF_E_ARG, "%s: null pointer in the train descriptor", who);
+    if (adam && (!t->adam_m || !t->adam_v || t->step < 1))
+        return fail(nullptr, MENKF_E_ARG, "%s: Adam needs moment buffers and step >= 1", who);
     if (t->npairs < 1 || t->H < 8 || t->W < 8 || t->batch < 1 || t->crop < 1)
-        return fail(nullptr, MENKF_E_ARG, "bad sizes in the train descriptor");
+        return fail(nullptr, MENKF_E_ARG, "%s: bad sizes in the train descriptor", who);
     size_t need = 0;
     menkf_status st = menkf_net_train_workspace_size(t->batch, t->crop, &need);
     if (st != MENKF_OK) return st;
     if (t->workspace_bytes < need)
-        return fail(nullptr, MENKF_E_WORKSPACE, "train workspace of %zu bytes < %zu required", t->workspace_bytes, need);
+        return fail(nullptr, MENKF_E_WORKSPACE, "%s: train workspace of %zu bytes < %zu required", who,
+                    t->workspace_bytes, need);
+    return MENKF_OK;
+}
+
+menkf_status menkf_net_train_step(const menkf_net_train *t, menkf_stream stream) {
+    menkf_status st = check_train(t, t && t->apply_adam, "menkf_net_train_step");
+    if (st != MENKF_OK) return st;
     const hipError_t e = launch_net_train_step(t, (hipStream_t)stream);
     return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_net_train_step");
+}
+
+menkf_status menkf_net_forward(const menkf_net_train *t, menkf_stream stream) {
+    menkf_status st = check_train(t, false, "menkf_net_forward");
+    if (st != MENKF_OK) return st;
+    const hipError_t e = launch_net_forward(t, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_net_forward");
+}
+
+menkf_status menkf_net_backward(const menkf_net_train *t, menkf_stream stream) {
+    menkf_status st = check_train(t, false, "menkf_net_backward");
+    if (st != MENKF_OK) return st;
+    const hipError_t e = launch_net_backward(t, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_net_backward");
+}
+
+menkf_status menkf_net_adam(const menkf_net_train *t, menkf_stream stream) {
+    menkf_status st = check_train(t, true, "menkf_net_adam");
+    if (st != MENKF_OK) return st;
+    const hipError_t e = launch_net_adam(t, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(nullptr, e, "menkf_net_adam");
 }
 
 menkf_status menkf_get_status(menkf_ctx *ctx, int32_t *info, int32_t clear, menkf_stream stream) {

@@ -248,6 +248,9 @@ hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, voi
                               int fallback, void *ws, hipStream_t s);
 hipError_t launch_net_pack(const float *prm, void *wk, hipStream_t s);
 hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s);
+hipError_t launch_net_forward(const menkf_net_train *t, hipStream_t s);
+hipError_t launch_net_backward(const menkf_net_train *t, hipStream_t s);
+hipError_t launch_net_adam(const menkf_net_train *t, hipStream_t s);
 size_t net_train_workspace(int B, int C);
 
 }  // namespace menkf

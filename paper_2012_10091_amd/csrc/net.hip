@@ -480,7 +480,13 @@ size_t net_train_workspace(int B, int C) { return train_layout(B, C).total; }
 
 static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s) {
+// The training step in three phases sharing the descriptor's workspace:
+// forward (layer activations, the loss and its gradient with respect to
+// the output), backward (the parameter gradient, from the activations the
+// forward phase left) and Adam (the update and the repacked BF16 weights).
+enum { TRAIN_FORWARD = 1, TRAIN_BACKWARD = 2, TRAIN_ADAM = 4 };
+
+static hipError_t net_train_phases(const menkf_net_train *t, int phases, hipStream_t s) {
     const TrainLayout L = train_layout(t->batch, t->crop);
     char *w = (char *)t->workspace_dev;
     TrainShapes sh;
@@ -504,33 +510,38 @@ hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s) {
     const float *P = t->params;
     float *G = t->grad;
     const int B = sh.B;
-    hipLaunchKernelGGL(train_gather, dim3(nblk((long long)sh.H0 * sh.H0 * B)), dim3(256), 0, s, t->dproj, t->xf,
-                       t->target, t->crops_dev, t->H, t->W, sh, nc, in0, tgt);
-    hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
-                       (const __bf16 *)in0, 8, sh.H0, P + P_W1, P + P_B1, 32, B, (void *)a1);
-    hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
-                       (const __bf16 *)a1, 32, sh.H1, P + P_W2, P + P_B2, 32, B, (void *)a2);
-    hipLaunchKernelGGL(train_conv_fwd<false>, dim3(nblk((long long)sh.H3 * sh.H3 * 4 * B)), dim3(256), 0, s,
-                       (const __bf16 *)a2, 32, sh.H2, P + P_W3, P + P_B3, 4, B, (void *)out);
-    const long long nout = (long long)B * 4 * sh.H3 * sh.H3;
-    int nbm = (int)nblk(nout);
-    if (nbm > 1024) nbm = 1024;
-    hipLaunchKernelGGL(train_mse, dim3(nbm), dim3(256), 0, s, (const float *)out, (const float *)tgt, nout, g3, part);
-    hipLaunchKernelGGL(train_loss_final, dim3(1), dim3(64), 0, s, (const double *)part, nbm, nout, t->loss_dev);
-    // layer 3
-    hipLaunchKernelGGL(train_conv_bwd_weight, dim3(4 * 32), dim3(256), 0, s, (const float *)g3, 4, sh.H3,
-                       (const __bf16 *)a2, 32, B, G + P_W3, G + P_B3);
-    hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
-                       (const float *)g3, 4, sh.H3, P + P_W3, (const __bf16 *)a2, 32, B, g2);
-    // layer 2
-    hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 32), dim3(256), 0, s, (const float *)g2, 32, sh.H2,
-                       (const __bf16 *)a1, 32, B, G + P_W2, G + P_B2);
-    hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
-                       (const float *)g2, 32, sh.H2, P + P_W2, (const __bf16 *)a1, 32, B, g1);
-    // layer 1
-    hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 8), dim3(256), 0, s, (const float *)g1, 32, sh.H1,
-                       (const __bf16 *)in0, 8, B, G + P_W1, G + P_B1);
-    if (t->apply_adam) {
+    if (phases & TRAIN_FORWARD) {
+        hipLaunchKernelGGL(train_gather, dim3(nblk((long long)sh.H0 * sh.H0 * B)), dim3(256), 0, s, t->dproj, t->xf,
+                           t->target, t->crops_dev, t->H, t->W, sh, nc, in0, tgt);
+        hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
+                           (const __bf16 *)in0, 8, sh.H0, P + P_W1, P + P_B1, 32, B, (void *)a1);
+        hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
+                           (const __bf16 *)a1, 32, sh.H1, P + P_W2, P + P_B2, 32, B, (void *)a2);
+        hipLaunchKernelGGL(train_conv_fwd<false>, dim3(nblk((long long)sh.H3 * sh.H3 * 4 * B)), dim3(256), 0, s,
+                           (const __bf16 *)a2, 32, sh.H2, P + P_W3, P + P_B3, 4, B, (void *)out);
+        const long long nout = (long long)B * 4 * sh.H3 * sh.H3;
+        int nbm = (int)nblk(nout);
+        if (nbm > 1024) nbm = 1024;
+        hipLaunchKernelGGL(train_mse, dim3(nbm), dim3(256), 0, s, (const float *)out, (const float *)tgt, nout, g3,
+                           part);
+        hipLaunchKernelGGL(train_loss_final, dim3(1), dim3(64), 0, s, (const double *)part, nbm, nout, t->loss_dev);
+    }
+    if (phases & TRAIN_BACKWARD) {
+        // layer 3
+        hipLaunchKernelGGL(train_conv_bwd_weight, dim3(4 * 32), dim3(256), 0, s, (const float *)g3, 4, sh.H3,
+                           (const __bf16 *)a2, 32, B, G + P_W3, G + P_B3);
+        hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
+                           (const float *)g3, 4, sh.H3, P + P_W3, (const __bf16 *)a2, 32, B, g2);
+        // layer 2
+        hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 32), dim3(256), 0, s, (const float *)g2, 32, sh.H2,
+                           (const __bf16 *)a1, 32, B, G + P_W2, G + P_B2);
+        hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
+                           (const float *)g2, 32, sh.H2, P + P_W2, (const __bf16 *)a1, 32, B, g1);
+        // layer 1
+        hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 8), dim3(256), 0, s, (const float *)g1, 32, sh.H1,
+                           (const __bf16 *)in0, 8, B, G + P_W1, G + P_B1);
+    }
+    if (phases & TRAIN_ADAM) {
         const float c1 = 1.0f - powf(t->beta1, (float)t->step);
         const float c2 = 1.0f - powf(t->beta2, (float)t->step);
         hipLaunchKernelGGL(train_adam, dim3(nblk(P_N)), dim3(256), 0, s, t->params, (const float *)G, t->adam_m,
@@ -539,5 +550,17 @@ hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s) {
     }
     return hipGetLastError();
 }
+
+hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s) {
+    return net_train_phases(t, TRAIN_FORWARD | TRAIN_BACKWARD | (t->apply_adam ? TRAIN_ADAM : 0), s);
+}
+
+hipError_t launch_net_forward(const menkf_net_train *t, hipStream_t s) { return net_train_phases(t, TRAIN_FORWARD, s); }
+
+hipError_t launch_net_backward(const menkf_net_train *t, hipStream_t s) {
+    return net_train_phases(t, TRAIN_BACKWARD, s);
+}
+
+hipError_t launch_net_adam(const menkf_net_train *t, hipStream_t s) { return net_train_phases(t, TRAIN_ADAM, s); }
 
 }  // namespace menkf

@@ -164,3 +164,28 @@ def test_training_reduces_loss():
     # the repacked BF16 weights follow the master copy
     w3 = m.unpack_params(gnet.params.cpu())[4]
     assert float(w3.abs().max()) > 0
+
+
+def test_training_phases_equal_the_fused_step():
+    """menkf_net_forward, menkf_net_backward and menkf_net_adam in that order
+    give bitwise the loss, gradient, parameters, Adam moments and packed
+    weights of menkf_net_train_step, over several steps."""
+    import paper_2012_10091_amd as m
+    cfg, dproj, xf, target, crops = _train_case(seed=5)
+    p = _params(cfg, last_gain=1.0)
+    fused, split = _gpu_net(p), _gpu_net(p)
+    ta = m.Trainer(fused, batch=3, crop=10, lr=2e-3)
+    tb = m.Trainer(split, batch=3, crop=10, lr=2e-3)
+    args = (to_dev(dproj, F32), to_dev(xf, F32), to_dev(target, F32), torch.as_tensor(crops, device="cuda"))
+    say("training phases vs the fused step, 4 steps")
+    for k in range(4):
+        la = float(ta.step(*args).item())
+        lb = float(tb.forward(*args).item())
+        tb.backward(*args)
+        tb.adam(*args)
+        torch.cuda.synchronize()
+        assert la == lb, (k, la, lb)
+        assert torch.equal(ta.grad, tb.grad), k
+        assert torch.equal(fused.params, split.params), k
+        assert torch.equal(ta.m, tb.m) and torch.equal(ta.v, tb.v), k
+        assert torch.equal(fused.wpacked, split.wpacked), k
