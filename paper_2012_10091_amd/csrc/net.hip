@@ -113,19 +113,29 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
                                                        int r, int nxc, int nyc, int tiles_x, int total_tiles,
                                                        int fallback, int32_t *__restrict__ fb_count,
                                                        const int32_t *__restrict__ info) {
-    __shared__ __align__(16) __bf16 in0[NP0 * 8];
-    __shared__ __align__(16) __bf16 act1[NP1 * 32];
-    __shared__ __align__(16) __bf16 act2[NP2 * 32];
-    __shared__ float dps[4][NP3];
-    __shared__ float outb[4][NP3];
-    __shared__ float red[3][256];
+    // LDS in three regions, reused as the layers go (3 workgroups per CU):
+    //   A: the input activations in0 and, after them, the coarse window of
+    //      delta^C (both dead once layer 1 has run), then layer 2's output act2
+    //   B: layer 1's output act1, then (dead after layer 2) the network
+    //      output outb and the guard's partial sums
+    //   D: the prolonged delta^C at the tile points (read by the epilogue)
+    constexpr int CWMAX = 26;   // R0 / r + 5 <= 25 for r >= 1
+    constexpr int IN0_B = NP0 * 8 * 2, CWIN_B = 4 * CWMAX * CWMAX * 4, ACT2_B = NP2 * 32 * 2;
+    constexpr int REG_A = (IN0_B + CWIN_B > ACT2_B ? IN0_B + CWIN_B : ACT2_B);
+    constexpr int ACT1_B = NP1 * 32 * 2, OUTB_B = 4 * NP3 * 4, RED_B = 3 * 4 * 4;
+    constexpr int REG_B = (ACT1_B > OUTB_B + RED_B ? ACT1_B : OUTB_B + RED_B);
+    static_assert(IN0_B % 16 == 0 && REG_A % 16 == 0 && REG_B % 16 == 0, "16-byte aligned regions");
+    __shared__ __align__(16) unsigned char lds_net[REG_A + REG_B + 4 * NP3 * 4];
+    __bf16 *in0 = reinterpret_cast<__bf16 *>(lds_net);
+    float (*cwin)[CWMAX][CWMAX] = reinterpret_cast<float (*)[CWMAX][CWMAX]>(lds_net + IN0_B);
+    __bf16 *act2 = reinterpret_cast<__bf16 *>(lds_net);
+    __bf16 *act1 = reinterpret_cast<__bf16 *>(lds_net + REG_A);
+    float (*outb)[NP3] = reinterpret_cast<float (*)[NP3]>(lds_net + REG_A);
+    float (*red)[4] = reinterpret_cast<float (*)[4]>(lds_net + REG_A + OUTB_B);
+    float (*dps)[NP3] = reinterpret_cast<float (*)[NP3]>(lds_net + REG_A + REG_B);
     // coarse window of delta^C under the tile + halo 3 (unwrapped coarse
     // origin cx0, cy0; at most CWMAX points per side for r >= 1) and the
     // Lagrange weights of the r sub-positions
-    // the window lives in the act2 buffer, which the loader does not use
-    constexpr int CWMAX = 26;   // R0 / r + 5 <= 25 for r >= 1
-    static_assert(4 * CWMAX * CWMAX * sizeof(float) <= sizeof(__bf16) * NP2 * 32, "window fits in act2");
-    float (*cwin)[CWMAX][CWMAX] = reinterpret_cast<float (*)[CWMAX][CWMAX]>(act2);
     __shared__ float wts[64][4];
     __shared__ int s_fx[R0], s_fy[R0];   // periodic fine column / row offset
     if (*info != 0) return;
@@ -220,20 +230,25 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
     }
     bool use_net = true;
     if (fallback) {
-        red[0][tid] = s_o;
-        red[1][tid] = s_d;
-        red[2][tid] = bad;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (tid < h) {
-                red[0][tid] += red[0][tid + h];
-                red[1][tid] += red[1][tid + h];
-                red[2][tid] += red[2][tid + h];
-            }
-            __syncthreads();
+        // tile sums: within each wave by butterfly shuffles, then over the
+        // four waves' partials (one barrier)
+        float so = s_o, sd = s_d, sb = bad;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            so += __shfl_xor(so, off);
+            sd += __shfl_xor(sd, off);
+            sb += __shfl_xor(sb, off);
         }
-        const float no = red[0][0], nd = red[1][0];
-        use_net = red[2][0] == 0.0f && isfinite(no) && no <= nc.guard * nc.guard * nd;
+        if (lane == 0) {
+            red[0][wave] = so;
+            red[1][wave] = sd;
+            red[2][wave] = sb;
+        }
+        __syncthreads();
+        const float no = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+        const float nd = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        const float nbad = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+        use_net = nbad == 0.0f && isfinite(no) && no <= nc.guard * nc.guard * nd;
         if (!use_net && tid == 0 && fb_count) atomicAdd(fb_count, 1);
     }
     if (gx < nx && gy < ny) {
