@@ -235,3 +235,42 @@ def test_euler_model_limits_are_accepted():
         st, h, lib = _euler(**kw)
         assert st == 0, (kw, lib.menkf_last_error(None))
         lib.menkf_destroy(h)
+
+
+E_ARG, E_WORKSPACE = -1, -7   # menkf_status codes of the header
+
+
+def test_training_phases_validate_on_the_host():
+    """menkf_net_forward / _backward / _adam reject bad descriptors before
+    any device work, like menkf_net_train_step (status codes only, no GPU)."""
+    from paper_2012_10091_amd import _lib as L
+    lib = _lib()
+    for name in ("menkf_net_train_step", "menkf_net_forward", "menkf_net_backward", "menkf_net_adam"):
+        fn = getattr(lib, name)
+        assert fn(None, None) == E_ARG, name
+        d = L.MenkfNetTrain()           # all pointers NULL
+        assert fn(ctypes.byref(d), None) == E_ARG, name
+    # a complete descriptor (dummy, never dereferenced: validation fails
+    # first) without Adam moments: only the Adam phase refuses it
+    d = L.MenkfNetTrain()
+    for f in ("params", "grad", "dproj", "xf", "target", "crops_dev", "loss_dev", "workspace_dev"):
+        setattr(d, f, 256)
+    d.npairs, d.H, d.W, d.batch, d.crop, d.step = 1, 32, 32, 1, 8, 1
+    d.workspace_bytes = 0
+    assert lib.menkf_net_adam(ctypes.byref(d), None) == E_ARG
+    # with moments but no workspace: every phase reports the workspace
+    d.adam_m, d.adam_v = 256, 256
+    for name in ("menkf_net_forward", "menkf_net_backward", "menkf_net_adam"):
+        assert getattr(lib, name)(ctypes.byref(d), None) == E_WORKSPACE, name
+
+
+def test_set_observations_is_set_probes():
+    lib = _lib()
+    assert lib.menkf_set_observations(None, None, None) == E_ARG
+    st, h, lib = _create()
+    assert st == 0
+    try:
+        assert lib.menkf_set_observations(h, None, None) == E_ARG
+        assert lib.menkf_set_probes(h, None, None) == E_ARG
+    finally:
+        lib.menkf_destroy(h)
