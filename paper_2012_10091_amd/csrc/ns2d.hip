@@ -55,7 +55,10 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     constexpr int NB = BX * BY, NC = CX * CY;
     static_assert(BX + BY <= 256, "box coordinate tables are filled by one pass of the workgroup");
     __shared__ T su[NB], sv[NB];
-    __shared__ T sm[NC], sn[NC], sEp[NC], sp[NC], sT[NC], sqx[NC], sqy[NC], suy[NC], svx[NC];
+    // m, n, E+p, p and T carry one slot past the inner box that the ring of
+    // the box writes to, so that phase 1 stores without a branch
+    __shared__ T sm[NC + 1], sn[NC + 1], sEp[NC + 1], sp[NC + 1], sT[NC + 1];
+    __shared__ T sqx[NC], sqy[NC], suy[NC], svx[NC];
     __shared__ int s_col[BX], s_row[BY];   // periodic global column / row offset of the box
 
     if (MODE == SWEEP && *info != 0) return;   // RESID is a diagnostic: no status gate
@@ -109,42 +112,44 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     else if (threadIdx.x < BX + BY) s_row[threadIdx.x - BX] = wrap(ty0 - 4 + (int)threadIdx.x - BX, ny) * nx;
     __syncthreads();
 
-    // phase 1: all loads of the box are issued before any is consumed
+    // phase 1: all loads of the box are issued before any is consumed.  They
+    // are unconditional (E of the outer ring is read and not used; the tail
+    // of the last pass re-reads the last box point): a load under a branch
+    // makes the compiler wait for it before the next pass's loads go out.
     constexpr int IT1 = (NB + 255) / 256;
     T r_rho[IT1], r_m[IT1], r_n[IT1], r_E[IT1];
+    int vo1[IT1];
 #pragma unroll
     for (int k = 0; k < IT1; ++k) {
-        const int i = threadIdx.x + k * 256;
-        if (i < NB) {
-            const int by = i / BX, bx = i - by * BX;
-            const int vo = (s_row[by] + s_col[bx]) * (int)sizeof(T);
-            r_rho[k] = buf_load<T>(b_in, vo, 0);
-            r_m[k] = buf_load<T>(b_in, vo, fstride);
-            r_n[k] = buf_load<T>(b_in, vo, 2 * fstride);
-            if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) r_E[k] = buf_load<T>(b_in, vo, 3 * fstride);
-        }
+        const int i = min((int)threadIdx.x + k * 256, NB - 1);
+        const int by = i / BX, bx = i - by * BX;
+        vo1[k] = (s_row[by] + s_col[bx]) * (int)sizeof(T);
     }
 #pragma unroll
     for (int k = 0; k < IT1; ++k) {
-        const int i = threadIdx.x + k * 256;
-        if (i < NB) {
-            const int by = i / BX, bx = i - by * BX;
-            const T rho = r_rho[k], m = r_m[k], n = r_n[k];
-            const T ir = recip(rho);
-            const T u = m * ir, v = n * ir;
-            su[i] = u;
-            sv[i] = v;
-            if (bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2) {
-                const T E = r_E[k];
-                const T p = c.gm1 * (E - T(0.5) * (m * u + n * v));
-                const int ci = (by - 2) * CX + (bx - 2);
-                sm[ci] = m;
-                sn[ci] = n;
-                sEp[ci] = E + p;
-                sp[ci] = p;
-                sT[ci] = c.tfac * p * ir;
-            }
-        }
+        r_rho[k] = buf_load<T>(b_in, vo1[k], 0);
+        r_m[k] = buf_load<T>(b_in, vo1[k], fstride);
+        r_n[k] = buf_load<T>(b_in, vo1[k], 2 * fstride);
+        r_E[k] = buf_load<T>(b_in, vo1[k], 3 * fstride);
+    }
+#pragma unroll
+    for (int k = 0; k < IT1; ++k) {
+        // the tail rewrites the last box point with the value it already has
+        const int i = min((int)threadIdx.x + k * 256, NB - 1);
+        const int by = i / BX, bx = i - by * BX;
+        const T rho = r_rho[k], m = r_m[k], n = r_n[k], E = r_E[k];
+        const T ir = recip(rho);
+        const T u = m * ir, v = n * ir;
+        su[i] = u;
+        sv[i] = v;
+        const bool inner = bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2;
+        const int ci = inner ? (by - 2) * CX + (bx - 2) : NC;
+        const T p = c.gm1 * (E - T(0.5) * (m * u + n * v));
+        sm[ci] = m;
+        sn[ci] = n;
+        sEp[ci] = E + p;
+        sp[ci] = p;
+        sT[ci] = c.tfac * p * ir;
     }
     __syncthreads();
 
