@@ -16,8 +16,10 @@
 //
 // Kernel structure (one launch per RK stage, all members of a level in one
 // grid): a workgroup owns a TX x TY tile of one member and stages, in LDS,
-//   phase 1: u, v on the tile + halo 4; m, n, E+p, p, T on the tile + halo 2
-//   phase 2: u_y, v_x and the viscous work fluxes (tau.u) on the tile + halo 2
+//   phase 1: u, v on the tile + halo 4; m, n, p, T on the tile + halo 2
+//   phase 2: u_y, v_x and the energy fluxes tau.u - (E+p)(u, v) on the tile
+//            + halo 2 (by linearity one difference operator per direction
+//            covers the convective and the viscous-work flux of E)
 //   phase 3: F(q) at the tile points, then the stage epilogue
 // The epilogue fuses the Runge-Kutta combination so that each stage reads
 // and writes every field once:
@@ -35,6 +37,7 @@ template <typename T>
 struct NSCoef {
     T i12hx, i12hy, i12hx2, i12hy2;
     T gm1, tfac, mu, kappa;
+    T epfac;  // gamma / (gamma - 1): E + p = epfac p + (m u + n v) / 2
     T dt, w;  // w = alpha / D for the sweep
 };
 
@@ -43,6 +46,22 @@ enum { ST1 = 1, ST2 = 2, ST3 = 3, ST4 = 4, SWEEP = 5, RESID = 6 };
 // 1/rho: the hardware reciprocal in FP32 (within 1 ulp), exact division in FP64.
 __device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+
+// Per-point records of the LDS tiles: the values a stencil reads at one
+// neighbour sit together, so each neighbour costs one wide LDS read at an
+// immediate offset from a single base.
+template <typename T>
+struct alignas(2 * sizeof(T)) NSuv {
+    T u, v;
+};
+template <typename T>
+struct alignas(4 * sizeof(T)) NSmnpt {
+    T m, n, p, tt;   // momenta, pressure, temperature
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) NSgd {
+    T g, d;   // energy flux g and the cross derivative d differenced along the same direction
+};
 
 template <typename T, int TX, int TY, int MODE>
 __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, const T *__restrict__ q0,
@@ -54,11 +73,13 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     constexpr int CX = TX + 4, CY = TY + 4;   // inner box with halo 2
     constexpr int NB = BX * BY, NC = CX * CY;
     static_assert(BX + BY <= 256, "box coordinate tables are filled by one pass of the workgroup");
-    __shared__ T su[NB], sv[NB];
-    // m, n, E+p, p and T carry one slot past the inner box that the ring of
-    // the box writes to, so that phase 1 stores without a branch
-    __shared__ T sm[NC + 1], sn[NC + 1], sEp[NC + 1], sp[NC + 1], sT[NC + 1];
-    __shared__ T sqx[NC], sqy[NC], suy[NC], svx[NC];
+    __shared__ NSuv<T> suv[NB];
+    // (m, n, p, T) carries one slot past the inner box that the ring of the
+    // box writes to, so that phase 1 stores without a branch
+    __shared__ NSmnpt<T> smp[NC + 1];
+    // differenced along x: (tau.u)_x - (E+p) u and u_y; along y:
+    // (tau.u)_y - (E+p) v and v_x
+    __shared__ NSgd<T> sgx[NC], sgy[NC];
     __shared__ int s_col[BX], s_row[BY];   // periodic global column / row offset of the box
 
     if (MODE == SWEEP && *info != 0) return;   // RESID is a diagnostic: no status gate
@@ -140,16 +161,11 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         const T rho = r_rho[k], m = r_m[k], n = r_n[k], E = r_E[k];
         const T ir = recip(rho);
         const T u = m * ir, v = n * ir;
-        su[i] = u;
-        sv[i] = v;
+        suv[i] = NSuv<T>{u, v};
         const bool inner = bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2;
         const int ci = inner ? (by - 2) * CX + (bx - 2) : NC;
         const T p = c.gm1 * (E - T(0.5) * (m * u + n * v));
-        sm[ci] = m;
-        sn[ci] = n;
-        sEp[ci] = E + p;
-        sp[ci] = p;
-        sT[ci] = c.tfac * p * ir;
+        smp[ci] = NSmnpt<T>{m, n, p, c.tfac * p * ir};
     }
     __syncthreads();
 
@@ -161,20 +177,27 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         const int i = threadIdx.x + 256 * k2;
         if (i >= NC) break;
         const int cy = i / CX, cx = i - cy * CX;
-        const int b = (cy + 2) * BX + (cx + 2);
-        const T ux = (su[b - 2] - T(8) * su[b - 1] + T(8) * su[b + 1] - su[b + 2]) * c.i12hx;
-        const T vx = (sv[b - 2] - T(8) * sv[b - 1] + T(8) * sv[b + 1] - sv[b + 2]) * c.i12hx;
-        const T uy = (su[b - 2 * BX] - T(8) * su[b - BX] + T(8) * su[b + BX] - su[b + 2 * BX]) * c.i12hy;
-        const T vy = (sv[b - 2 * BX] - T(8) * sv[b - BX] + T(8) * sv[b + BX] - sv[b + 2 * BX]) * c.i12hy;
+        // the box point (cx + 2, cy + 2) is pu[2 BX + 2]; every neighbour
+        // read is pu[] at a non-negative constant (an immediate LDS offset)
+        const NSuv<T> *pu = suv + (cy * BX + cx);
+        const NSuv<T> w0 = pu[2 * BX + 2];
+        const NSuv<T> xl2 = pu[2 * BX], xl1 = pu[2 * BX + 1], xr1 = pu[2 * BX + 3], xr2 = pu[2 * BX + 4];
+        const NSuv<T> yl2 = pu[2], yl1 = pu[BX + 2], yr1 = pu[3 * BX + 2], yr2 = pu[4 * BX + 2];
+        const T ux = (xl2.u - T(8) * xl1.u + T(8) * xr1.u - xr2.u) * c.i12hx;
+        const T vx = (xl2.v - T(8) * xl1.v + T(8) * xr1.v - xr2.v) * c.i12hx;
+        const T uy = (yl2.u - T(8) * yl1.u + T(8) * yr1.u - yr2.u) * c.i12hy;
+        const T vy = (yl2.v - T(8) * yl1.v + T(8) * yr1.v - yr2.v) * c.i12hy;
         const T div = ux + vy;
         const T txx = c.mu * (T(2) * ux - T(2.0 / 3.0) * div);
         const T tyy = c.mu * (T(2) * vy - T(2.0 / 3.0) * div);
         const T txy = c.mu * (uy + vx);
-        const T u = su[b], v = sv[b];
-        sqx[i] = txx * u + txy * v;
-        sqy[i] = txy * u + tyy * v;
-        suy[i] = uy;
-        svx[i] = vx;
+        const T u = w0.u, v = w0.v;
+        const NSmnpt<T> a0 = smp[i];
+        const T ep = c.epfac * a0.p + T(0.5) * (a0.m * u + a0.n * v);   // E + p from the state
+        // the energy equation's convective and viscous-work fluxes share one
+        // difference operator per direction
+        sgx[i] = NSgd<T>{(txx * u + txy * v) - ep * u, uy};
+        sgy[i] = NSgd<T>{(txy * u + tyy * v) - ep * v, vx};
     }
     __syncthreads();
 
@@ -185,48 +208,59 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         const int ty = i / TX, tx = i - ty * TX;
         const int gx = tx0 + tx, gy = ty0 + ty;
         if (i >= TX * TY || gx >= nx || gy >= ny) continue;
-        const int ci = (ty + 2) * CX + (tx + 2);
-        const int b = (ty + 4) * BX + (tx + 4);
-#define D1X(A) ((A[ci - 2] - T(8) * A[ci - 1] + T(8) * A[ci + 1] - A[ci + 2]) * c.i12hx)
-#define D1Y(A) ((A[ci - 2 * CX] - T(8) * A[ci - CX] + T(8) * A[ci + CX] - A[ci + 2 * CX]) * c.i12hy)
-#define D2XB(A) ((-A[b - 2] + T(16) * A[b - 1] - T(30) * A[b] + T(16) * A[b + 1] - A[b + 2]) * c.i12hx2)
-#define D2YB(A) \
-    ((-A[b - 2 * BX] + T(16) * A[b - BX] - T(30) * A[b] + T(16) * A[b + BX] - A[b + 2 * BX]) * c.i12hy2)
-#define D2XC(A) ((-A[ci - 2] + T(16) * A[ci - 1] - T(30) * A[ci] + T(16) * A[ci + 1] - A[ci + 2]) * c.i12hx2)
-#define D2YC(A) \
-    ((-A[ci - 2 * CX] + T(16) * A[ci - CX] - T(30) * A[ci] + T(16) * A[ci + CX] - A[ci + 2 * CX]) * c.i12hy2)
-        // fluxes at the x-neighbours (offset k) and y-neighbours
-        T fxm[4], fxn[4], fxE[4], fym[4], fyn[4], fyE[4];
-        const int offs[4] = {-2, -1, 1, 2};
+        // the tile point is inner point (tx + 2, ty + 2) = pc[2 CX + 2] and
+        // box point (tx + 4, ty + 4) = pb[2 BX + 2]: every read below is at a
+        // non-negative constant from these bases (an immediate LDS offset)
+        const int ec = ty * CX + tx, eb = (ty + 2) * BX + tx + 2;
+        const NSuv<T> *pb = suv + eb;
+        const NSmnpt<T> *pc = smp + ec;
+        const NSgd<T> *pgx = sgx + ec, *pgy = sgy + ec;
+        constexpr int OC = 2 * CX + 2, OB = 2 * BX + 2;
+        // neighbour values along x (offset k) and along y, in the order
+        // -2, -1, +1, +2 of the stencils
+        T xm[4], xfm[4], xfn[4], xg[4], xuy[4], xT[4], xu[4], xv[4];
+        T yn[4], yfm[4], yfn[4], yg[4], yvx[4], yT[4], yu[4], yv[4];
+        constexpr int offs[4] = {-2, -1, 1, 2};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int o = offs[k];
-            const int cx_ = ci + o, bx_ = b + o;
-            const T ux_ = su[bx_];
-            fxm[k] = sm[cx_] * ux_ + sp[cx_];
-            fxn[k] = sn[cx_] * ux_;
-            fxE[k] = sEp[cx_] * ux_;
-            const int cy_ = ci + o * CX, by_ = b + o * BX;
-            const T vy_ = sv[by_];
-            fym[k] = sm[cy_] * vy_;
-            fyn[k] = sn[cy_] * vy_ + sp[cy_];
-            fyE[k] = sEp[cy_] * vy_;
+            const NSuv<T> wx = pb[OB + o];
+            const NSmnpt<T> ax = pc[OC + o];
+            const NSgd<T> gx_ = pgx[OC + o];
+            xm[k] = ax.m;
+            xfm[k] = ax.m * wx.u + ax.p;
+            xfn[k] = ax.n * wx.u;
+            xg[k] = gx_.g;
+            xuy[k] = gx_.d;
+            xT[k] = ax.tt;
+            xu[k] = wx.u;
+            xv[k] = wx.v;
+            const NSuv<T> wy = pb[OB + o * BX];
+            const NSmnpt<T> ay = pc[OC + o * CX];
+            const NSgd<T> gy_ = pgy[OC + o * CX];
+            yn[k] = ay.n;
+            yfm[k] = ay.m * wy.v;
+            yfn[k] = ay.n * wy.v + ay.p;
+            yg[k] = gy_.g;
+            yvx[k] = gy_.d;
+            yT[k] = ay.tt;
+            yu[k] = wy.u;
+            yv[k] = wy.v;
         }
+        const NSuv<T> w0 = pb[OB];
+        const T T0 = pc[OC].tt;
 #define DF(F, h) ((F[0] - T(8) * F[1] + T(8) * F[2] - F[3]) * h)
-        const T k_rho = -(D1X(sm) + D1Y(sn));
-        const T k_m = -(DF(fxm, c.i12hx) + DF(fym, c.i12hy)) +
-                      c.mu * (T(4.0 / 3.0) * D2XB(su) + D2YB(su) + T(1.0 / 3.0) * D1Y(svx));
-        const T k_n = -(DF(fxn, c.i12hx) + DF(fyn, c.i12hy)) +
-                      c.mu * (D2XB(sv) + T(4.0 / 3.0) * D2YB(sv) + T(1.0 / 3.0) * D1X(suy));
-        const T k_E = -(DF(fxE, c.i12hx) + DF(fyE, c.i12hy)) + D1X(sqx) + D1Y(sqy) +
-                      c.kappa * (D2XC(sT) + D2YC(sT));
+#define D2(F, f0, h) ((-F[0] + T(16) * F[1] - T(30) * (f0) + T(16) * F[2] - F[3]) * h)
+        const T k_rho = -(DF(xm, c.i12hx) + DF(yn, c.i12hy));
+        const T k_m = -(DF(xfm, c.i12hx) + DF(yfm, c.i12hy)) +
+                      c.mu * (T(4.0 / 3.0) * D2(xu, w0.u, c.i12hx2) + D2(yu, w0.u, c.i12hy2) +
+                              T(1.0 / 3.0) * DF(yvx, c.i12hy));
+        const T k_n = -(DF(xfn, c.i12hx) + DF(yfn, c.i12hy)) +
+                      c.mu * (D2(xv, w0.v, c.i12hx2) + T(4.0 / 3.0) * D2(yv, w0.v, c.i12hy2) +
+                              T(1.0 / 3.0) * DF(xuy, c.i12hx));
+        const T k_E = DF(xg, c.i12hx) + DF(yg, c.i12hy) + c.kappa * (D2(xT, T0, c.i12hx2) + D2(yT, T0, c.i12hy2));
 #undef DF
-#undef D1X
-#undef D1Y
-#undef D2XB
-#undef D2YB
-#undef D2XC
-#undef D2YC
+#undef D2
         const T kk[4] = {k_rho, k_m, k_n, k_E};
         const int vo = (gy * nx + gx) * (int)sizeof(T);
         const buf_t b_next = buf_rsrc(snext ? snext + mbase : sin_, mbytes);
@@ -271,6 +305,7 @@ static NSCoef<T> ns_coef(const Plan &p, int level, double alpha) {
     c.i12hx2 = (T)(1.0 / (12.0 * hx * hx));
     c.i12hy2 = (T)(1.0 / (12.0 * hy * hy));
     c.gm1 = (T)(g - 1.0);
+    c.epfac = (T)(g / (g - 1.0));
     c.tfac = (T)(g * ma * ma);
     c.mu = (T)mu;
     c.kappa = (T)(mu * cp / p.cfg.prandtl);
@@ -318,8 +353,9 @@ struct NSLauncher {
 };
 
 // Stencil tile shapes (TX x TY points per 256-thread workgroup).  LDS per
-// workgroup: (2 (TX+8)(TY+8) + 9 (TX+4)(TY+4)) elements, e.g. 33.6 KB for
-// 32 x 16 in FP32.  The first entry of each list is the default.
+// workgroup: (2 (TX+8)(TY+8) + 8 (TX+4)(TY+4) + 4) elements, e.g. 30.7 KB
+// for 32 x 16 in FP32 (five workgroups per compute unit).  The first entry
+// of each list is the default.
 static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}};
 static const int kTilesF64[][2] = {{32, 8}, {16, 8}, {16, 16}, {64, 4}};
 
