@@ -263,9 +263,9 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
     avg_s = ev0.elapsed_time(ev1) / 1e3 / launches
     pts = cfg.n_members * cfg.nxc * cfg.nyc / n_chunks      # points per launch (equal chunks)
     state_bytes = pts * 4 * 4
-    # kernel contract: 16 state passes per RK4 step over 4 launches (stage 1: 1R 2W,
-    # stages 2-3: 3R 2W, stage 4: 2R 1W) -> 4 passes per launch on average
-    contract = 4.0 * state_bytes
+    # kernel contract: 13 state passes per RK4 step over 4 launches (stage 1: 1R 1W,
+    # stage 2: 2R 2W, stage 3: 2R 1W, stage 4: 3R 1W) -> 3.25 passes per launch
+    contract = 3.25 * state_bytes
     minimum = 2.0 * state_bytes / 4.0      # one read + one write of the state per step
     return {
         "kernel": f"ns_stage<float,{sc['tile'][0]},{sc['tile'][1]},*> (ensemble RK4 stage, "

@@ -21,12 +21,15 @@
 //            + halo 2 (by linearity one difference operator per direction
 //            covers the convective and the viscous-work flux of E)
 //   phase 3: F(q) at the tile points, then the stage epilogue
-// The epilogue fuses the Runge-Kutta combination so that each stage reads
-// and writes every field once:
-//   stage 1: acc = q + dt/6 k1,      s1 = q + dt/2 k1      (+ x_{k-1} copy)
-//   stage 2: acc += dt/3 k2,         s2 = q + dt/2 k2
-//   stage 3: acc += dt/3 k3,         s1 = q + dt k3
-//   stage 4: q = acc + dt/6 k4
+// The epilogue fuses the classical RK4 combination
+//   q' = q + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+// with the partial sum carried where it costs no extra pass: dt/6 k1 and
+// dt/3 k3 are recovered as (s1 - q)/3 and (s3 - q)/3 from the stage states
+// that are read anyway, so a step moves 13 state passes instead of 16:
+//   stage 1: s1 = q + dt/2 k1                              (+ x_{k-1} copy)
+//   stage 2: acc = q + (s1 - q)/3 + dt/3 k2,  s2 = q + dt/2 k2
+//   stage 3: s3 = q + dt k3
+//   stage 4: q = acc + (s3 - q)/3 + dt/6 k4
 //   sweep  : x' = x + (alpha/D)(x_prev + dt F(x) - x)     (relaxed Jacobi)
 //   resid  : r = x_prev + dt F(x) - x                      (implicit-Euler residual)
 #include "common.hpp"
@@ -64,9 +67,9 @@ struct alignas(2 * sizeof(T)) NSgd {
 };
 
 template <typename T, int TX, int TY, int MODE>
-__global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, const T *__restrict__ q0,
+__global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, const T *q0,
                                                 T *__restrict__ acc, T *__restrict__ snext,
-                                                T *__restrict__ qout, T *__restrict__ prev, int nx, int ny,
+                                                T *qout, T *__restrict__ prev, int nx, int ny,
                                                 int tiles_x, int tiles_per_member, int total_blocks,
                                                 NSCoef<T> c, const int32_t *__restrict__ info) {
     constexpr int BX = TX + 8, BY = TY + 8;   // box with halo 4
@@ -100,9 +103,11 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     const buf_t b_acc = buf_rsrc(acc ? acc + mbase : sin_, mbytes);
 
     // operands of the Runge-Kutta combination at the owned points, fetched
-    // first so that their latency overlaps the stencil phases
+    // first so that their latency overlaps the stencil phases (stage 4
+    // updates q in place: q0 and qout are the same array, each point read
+    // and then written by the same thread)
     constexpr int IT3 = (TX * TY + 255) / 256;
-    constexpr int NPRE = (MODE == ST1 || MODE == ST4) ? 1 : 2;
+    constexpr int NPRE = (MODE == ST1 || MODE == ST3) ? 1 : (MODE == ST4 ? 3 : 2);
     T pre[IT3][NPRE][4];
 #pragma unroll
     for (int k = 0; k < IT3; ++k) {
@@ -114,12 +119,16 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
                 if (MODE == ST1) {
-                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);
+                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);      // q
+                } else if (MODE == ST3) {
+                    pre[k][0][f] = buf_load<T>(b_q0, vo, f * fstride);      // q
                 } else if (MODE == ST4) {
-                    pre[k][0][f] = buf_load<T>(b_acc, vo, f * fstride);
-                } else if (MODE == ST2 || MODE == ST3) {
-                    pre[k][0][f] = buf_load<T>(b_acc, vo, f * fstride);
-                    pre[k][NPRE - 1][f] = buf_load<T>(b_q0, vo, f * fstride);
+                    pre[k][0][f] = buf_load<T>(b_acc, vo, f * fstride);     // acc
+                    pre[k][1][f] = buf_load<T>(b_q0, vo, f * fstride);      // q
+                    pre[k][NPRE - 1][f] = buf_load<T>(b_in, vo, f * fstride);   // s3
+                } else if (MODE == ST2) {
+                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);      // s1
+                    pre[k][NPRE - 1][f] = buf_load<T>(b_q0, vo, f * fstride);   // q
                 } else {
                     pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);
                     pre[k][NPRE - 1][f] = buf_load<T>(b_q0, vo, f * fstride);
@@ -269,19 +278,17 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             const int so = f * fstride;
-            const T a0 = pre[k3][0][f], a1 = pre[k3][NPRE - 1][f];
-            if (MODE == ST1) {
-                buf_store(a0 + c.dt * T(1.0 / 6.0) * kk[f], b_acc, vo, so);
+            const T a0 = pre[k3][0][f], a1 = pre[k3][NPRE > 1 ? 1 : 0][f], a2 = pre[k3][NPRE - 1][f];
+            if (MODE == ST1) {   // a0 = q
                 buf_store(a0 + c.dt * T(0.5) * kk[f], b_next, vo, so);
                 if (prev) buf_store(a0, b_prev, vo, so);
-            } else if (MODE == ST2) {
-                buf_store(a0 + c.dt * T(1.0 / 3.0) * kk[f], b_acc, vo, so);
+            } else if (MODE == ST2) {   // a0 = s1, a1 = q
+                buf_store(a1 + (a0 - a1) * T(1.0 / 3.0) + c.dt * T(1.0 / 3.0) * kk[f], b_acc, vo, so);
                 buf_store(a1 + c.dt * T(0.5) * kk[f], b_next, vo, so);
-            } else if (MODE == ST3) {
-                buf_store(a0 + c.dt * T(1.0 / 3.0) * kk[f], b_acc, vo, so);
-                buf_store(a1 + c.dt * kk[f], b_next, vo, so);
-            } else if (MODE == ST4) {
-                buf_store(a0 + c.dt * T(1.0 / 6.0) * kk[f], b_out, vo, so);
+            } else if (MODE == ST3) {   // a0 = q
+                buf_store(a0 + c.dt * kk[f], b_next, vo, so);
+            } else if (MODE == ST4) {   // a0 = acc, a1 = q, a2 = s3
+                buf_store(a0 + (a2 - a1) * T(1.0 / 3.0) + c.dt * T(1.0 / 6.0) * kk[f], b_out, vo, so);
             } else if (MODE == SWEEP) {
                 buf_store(a0 + c.w * (a1 + c.dt * kk[f] - a0), b_out, vo, so);
             } else {
@@ -342,10 +349,10 @@ struct NSLauncher {
             T *pchunk = prev ? prev + m0 * msz : nullptr;
             for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
                 T *pv = step == nsteps - 1 ? pchunk : nullptr;
-                e = stage<ST1>(q, nullptr, a, t1, nullptr, pv, nx, ny, cb, c, nullptr, st);
+                e = stage<ST1>(q, nullptr, nullptr, t1, nullptr, pv, nx, ny, cb, c, nullptr, st);
                 if (e == hipSuccess) e = stage<ST2>(t1, q, a, t2, nullptr, nullptr, nx, ny, cb, c, nullptr, st);
-                if (e == hipSuccess) e = stage<ST3>(t2, q, a, t1, nullptr, nullptr, nx, ny, cb, c, nullptr, st);
-                if (e == hipSuccess) e = stage<ST4>(t1, nullptr, a, nullptr, q, nullptr, nx, ny, cb, c, nullptr, st);
+                if (e == hipSuccess) e = stage<ST3>(t2, q, nullptr, t1, nullptr, nullptr, nx, ny, cb, c, nullptr, st);
+                if (e == hipSuccess) e = stage<ST4>(t1, q, a, nullptr, q, nullptr, nx, ny, cb, c, nullptr, st);
             }
         }
         return e;
