@@ -480,7 +480,7 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  * stream with two events the context owns.  With MENKF_GAIN_EXACT_R it
  * runs beside the N_y x N_y factorisation: the member forecast comes
  * first, the factorisation runs with d* = 0 (the fine forecast is forked
- * from it once each remaining trailing update has at most three tiles per
+ * from it once each remaining trailing update has at most four tiles per
  * compute unit, so that it fills the GPU beside the latency-bound late
  * block steps rather than the throughput-bound early ones), and the x*
  * column of the gain

@@ -723,7 +723,7 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         // throughput of their updates, run without the fine forecast, which
         // then fills the GPU beside the later ones, bound by the latency of
         // the diagonal factorisations.
-        hipError_t e0 = launch_gain_deferred_back(p, a->cycle, ctx->ws, s0, ctx->ev_fork, 3 * ctx->n_cus);
+        hipError_t e0 = launch_gain_deferred_back(p, a->cycle, ctx->ws, s0, ctx->ev_fork, 4 * ctx->n_cus);
         if (e0 != hipSuccess) (void)hipEventRecord(ctx->ev_fork, s0);   // keep the fork well formed
         e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
