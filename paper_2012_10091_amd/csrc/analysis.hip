@@ -765,9 +765,27 @@ __global__ __launch_bounds__(256) void update_bf16(float *__restrict__ X, float 
     if (*info != 0) return;
     const long long p0 = (long long)blockIdx.x * PW;
     const int tid = threadIdx.x;
-    for (int e = tid; e < NPAD * PW; e += 256) {
-        const int i = e / PW, p = e - i * PW;
-        xs[e] = (i < N && p0 + p < npts) ? X[(long long)i * npts + p0 + p] : 0.0f;
+    // staging: batches of loads in flight together, unconditional (rows and
+    // points past the end re-read a valid element, and zero is stored)
+    constexpr int NLD = NPAD * PW / 256;
+    constexpr int BATCH = NLD % 16 == 0 ? 16 : 8;
+    static_assert(NLD % BATCH == 0, "whole batches");
+    for (int q0 = 0; q0 < NLD; q0 += BATCH) {
+        float v[BATCH];
+#pragma unroll
+        for (int q = 0; q < BATCH; ++q) {
+            const int e = tid + (q0 + q) * 256;
+            const int i = e / PW, p = e - i * PW;
+            const int ic = i < N ? i : N - 1;
+            const long long pc = p0 + p < npts ? p0 + p : npts - 1;
+            v[q] = X[(long long)ic * npts + pc];
+        }
+#pragma unroll
+        for (int q = 0; q < BATCH; ++q) {
+            const int e = tid + (q0 + q) * 256;
+            const int i = e / PW, p = e - i * PW;
+            xs[e] = (i < N && p0 + p < npts) ? v[q] : 0.0f;
+        }
     }
     __syncthreads();
     if (tid < PW) {
@@ -798,19 +816,30 @@ __global__ __launch_bounds__(256) void update_bf16(float *__restrict__ X, float 
             if constexpr (TERMS == 3) bfrag_lo[ks][e] = (__bf16)(v - (float)hi);
         }
     }
+    // Z fragments are fetched KG k-steps at a time, all before their MFMAs
+    constexpr int KS = NPAD / 16;
+    constexpr int KG = KS % 4 == 0 ? 4 : 2;
 #pragma unroll
     for (int mt = msub; mt < NPAD / 32; mt += MSPLIT) {
         f32x16 acc = {};
         const __bf16 *za = zt + (long long)(mt * 32 + (l & 31)) * NPAD + (l >> 5) * 8;
 #pragma unroll
-        for (int ks = 0; ks < NPAD / 16; ++ks) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(za + ks * 16);
-            if constexpr (TERMS == 3) {
-                const bf16x8 alo = *reinterpret_cast<const bf16x8 *>(za + NPAD * NPAD + ks * 16);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bfrag[ks], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfrag_lo[ks], acc, 0, 0, 0);
+        for (int k0 = 0; k0 < KS; k0 += KG) {
+            bf16x8 a[KG], alo[TERMS == 3 ? KG : 1];
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                a[g] = *reinterpret_cast<const bf16x8 *>(za + (k0 + g) * 16);
+                if constexpr (TERMS == 3) alo[g] = *reinterpret_cast<const bf16x8 *>(za + NPAD * NPAD + (k0 + g) * 16);
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfrag[ks], acc, 0, 0, 0);
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                const int ks = k0 + g;
+                if constexpr (TERMS == 3) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[g], bfrag[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[g], bfrag_lo[ks], acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[g], bfrag[ks], acc, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
