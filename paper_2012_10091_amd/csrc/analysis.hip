@@ -326,18 +326,24 @@ __device__ __forceinline__ void chol_diag_block(const double *src, long long lds
         if (t == 0) *info = k * 64 + bad;
         return;
     }
-    __shared__ double dsq[64];
-    if (t < 64) dsq[t] = sqrt(pivbuf[t]);     // pivots -> d_c
+    // pivots -> d_c and 1/d_c, one division per pivot: the 32 entries of
+    // each thread are then scaled by multiplications
+    __shared__ double dsq[64], rdsq[64];
+    if (t < 64) {
+        const double d = sqrt(pivbuf[t]);
+        dsq[t] = d;
+        rdsq[t] = 1.0 / d;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int r = 4 * a + i;
-        const double dr = dsq[r];
+        const double dr = dsq[r], rdr = rdsq[r];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int c = 4 * b + q;
-            if (c <= r) Ak[(long long)r * ld + c] = c == r ? dr : w[i][q] / dsq[c];
-            Linv[r * 64 + c] = c <= r ? x[i][q] / dr : 0.0;
+            if (c <= r) Ak[(long long)r * ld + c] = c == r ? dr : w[i][q] * rdsq[c];
+            Linv[r * 64 + c] = c <= r ? x[i][q] * rdr : 0.0;
         }
     }
 }
