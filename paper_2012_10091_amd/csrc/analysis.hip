@@ -525,7 +525,13 @@ __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int l
 
 // ----------------------------------------------------------------- ensemble-space gain
 // Gram of the extra rows E = [D; d*; Y] (mextp x nyp, rows of A from nyp):
-// P = E E^T, lower 64 x 64 tiles, FP64 MFMA over the whole probe range.
+// P = E E^T, lower 64 x 64 tiles on FP64 MFMA, split over the probes: grid
+// (tiles, ksplit), workgroup (t, z) forms tile t over probes
+// [z kc, (z + 1) kc) into its own partial tile, and gram_extra_sum adds the
+// ksplit partials of a tile in the order z = 0, 1, ... (without the split
+// the six tiles at C3 run 64 K chunks each on six compute units).
+// Without a split (the partial tiles would not fit the scratch): P = E E^T
+// in one pass over the probes.
 __global__ __launch_bounds__(256) void gram_extra(const double *__restrict__ A, int ld, int nyp, int mextp,
                                                   double *__restrict__ P) {
     extern __shared__ double smem_d[];
@@ -536,6 +542,30 @@ __global__ __launch_bounds__(256) void gram_extra(const double *__restrict__ A, 
     mfma_nt_64_acc(E + (long long)(bi * 64) * ld, ld, E + (long long)(bj * 64) * ld, ld, nyp, acc, smem_d,
                    smem_d + 64 * LDP);
     for_each_acc(acc, [&](int r, int c, double v) { P[(long long)(bi * 64 + r) * mextp + bj * 64 + c] = v; });
+}
+
+__global__ __launch_bounds__(256) void gram_extra_part(const double *__restrict__ A, int ld, int nyp, int kc,
+                                                       double *__restrict__ part) {
+    extern __shared__ double smem_d[];
+    int bi, bj;
+    tri_index(blockIdx.x, bi, bj);
+    const double *E = A + (long long)nyp * ld + (long long)blockIdx.y * kc;
+    f64x4 acc[2][2] = {};
+    mfma_nt_64_acc(E + (long long)(bi * 64) * ld, ld, E + (long long)(bj * 64) * ld, ld, kc, acc, smem_d,
+                   smem_d + 64 * LDP);
+    double *dst = part + ((long long)blockIdx.y * gridDim.x + blockIdx.x) * 4096;
+    for_each_acc(acc, [&](int r, int c, double v) { dst[r * 64 + c] = v; });
+}
+
+__global__ __launch_bounds__(256) void gram_extra_sum(const double *__restrict__ part, int ntile, int ksplit,
+                                                      int mextp, double *__restrict__ P) {
+    int bi, bj;
+    tri_index(blockIdx.x, bi, bj);
+    for (int e = threadIdx.x; e < 4096; e += 256) {
+        double v = 0.0;
+        for (int z = 0; z < ksplit; ++z) v += part[((long long)z * ntile + blockIdx.x) * 4096 + e];
+        P[(long long)(bi * 64 + (e >> 6)) * mextp + bj * 64 + (e & 63)] = v;
+    }
 }
 
 // The small augmented system of the ensemble-space gain, lds x lds with
@@ -1063,10 +1093,29 @@ static hipError_t gain_back(const Plan &p, uint64_t cycle, char *w, hipStream_t 
     if (p.cfg.gain_mode == MENKF_GAIN_ENSEMBLE_SPACE) {
         // 4'. P = E E^T of the extra rows, then the N_e x N_e system
         double *P = (double *)(w + p.off_p), *As = (double *)(w + p.off_as);
-        const int mb = p.mextp / CHOL_NB;
-        if ((e = set_lds((const void *)gram_extra, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(gram_extra, dim3(mb * (mb + 1) / 2), dim3(256), lds, s, (const double *)A, p.ld, p.nyp,
-                           p.mextp, P);
+        const int mb = p.mextp / CHOL_NB, ntile = mb * (mb + 1) / 2;
+        // the probe range is split so that the partial tiles fit the
+        // observation scratch, which obs_pack has consumed by now
+        size_t cap = (size_t)(p.N + 1) * p.nyp * 8;
+        if (cap < 4096 * 8) cap = 4096 * 8;
+        int ks = 1;
+        for (int c = 16; c > 1; c /= 2)
+            if ((p.nyp / 64) % c == 0 && (size_t)c * ntile * 4096 * 8 <= cap) {
+                ks = c;
+                break;
+            }
+        if (ks == 1) {
+            if ((e = set_lds((const void *)gram_extra, lds)) != hipSuccess) return e;
+            hipLaunchKernelGGL(gram_extra, dim3(ntile), dim3(256), lds, s, (const double *)A, p.ld, p.nyp, p.mextp,
+                               P);
+        } else {
+            if ((e = set_lds((const void *)gram_extra_part, lds)) != hipSuccess) return e;
+            double *part = (double *)(w + p.off_scratch);
+            hipLaunchKernelGGL(gram_extra_part, dim3(ntile, ks), dim3(256), lds, s, (const double *)A, p.ld, p.nyp,
+                               p.nyp / ks, part);
+            hipLaunchKernelGGL(gram_extra_sum, dim3(ntile), dim3(256), 0, s, (const double *)part, ntile, ks,
+                               p.mextp, P);
+        }
         hipLaunchKernelGGL(ens_assemble, dim3(256), dim3(256), 0, s, (const double *)P, p.mextp, p.N, p.npm, p.lds,
                            p.cfg.obs_sigma * p.cfg.obs_sigma, As);
         if ((e = hipGetLastError()) != hipSuccess) return e;
