@@ -557,15 +557,26 @@ __global__ __launch_bounds__(256) void gram_extra_part(const double *__restrict_
     for_each_acc(acc, [&](int r, int c, double v) { dst[r * 64 + c] = v; });
 }
 
+// grid (tiles, 16): one element of a tile per thread, its partials loaded
+// together (z beyond ksplit re-reads the last one and adds zero) and added
+// in the order z = 0, 1, ...
+constexpr int GRAM_KSPLIT_MAX = 16;
+
 __global__ __launch_bounds__(256) void gram_extra_sum(const double *__restrict__ part, int ntile, int ksplit,
                                                       int mextp, double *__restrict__ P) {
     int bi, bj;
     tri_index(blockIdx.x, bi, bj);
-    for (int e = threadIdx.x; e < 4096; e += 256) {
-        double v = 0.0;
-        for (int z = 0; z < ksplit; ++z) v += part[((long long)z * ntile + blockIdx.x) * 4096 + e];
-        P[(long long)(bi * 64 + (e >> 6)) * mextp + bj * 64 + (e & 63)] = v;
+    const int e = blockIdx.y * 256 + threadIdx.x;
+    double pv[GRAM_KSPLIT_MAX];
+#pragma unroll
+    for (int z = 0; z < GRAM_KSPLIT_MAX; ++z) {
+        const int zc = z < ksplit ? z : ksplit - 1;
+        pv[z] = part[((long long)zc * ntile + blockIdx.x) * 4096 + e];
     }
+    double v = 0.0;
+#pragma unroll
+    for (int z = 0; z < GRAM_KSPLIT_MAX; ++z) v += z < ksplit ? pv[z] : 0.0;
+    P[(long long)(bi * 64 + (e >> 6)) * mextp + bj * 64 + (e & 63)] = v;
 }
 
 // The small augmented system of the ensemble-space gain, lds x lds with
@@ -726,11 +737,23 @@ __global__ __launch_bounds__(256) void xstar_gain(const double *__restrict__ par
     for (int b0 = 0; b0 < N; b0 += 64) {
         __syncthreads();   // v written; the previous slab is no longer read
         for (int r0 = 0; r0 < npad && r0 < 256; r0 += 64) {
-            for (int e = t; e < 64 * 64; e += 256) {
+            // 16 loads in flight per thread, unconditional (outside the
+            // matrix a valid element is read and zero stored)
+            double mv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = t + 256 * q;
                 const int rr = r0 + (e >> 6), bb = b0 + (e & 63);
-                double m = 0.0;
-                if (rr < N && bb < N) m = rr >= bb ? S[(long long)rr * lm + bb] : S[(long long)bb * lm + rr];
-                slab[e >> 6][e & 63] = m;
+                const bool in = rr < N && bb < N;
+                const int rc = in ? rr : 0, bc = in ? bb : 0;
+                const long long idx = rc >= bc ? (long long)rc * lm + bc : (long long)bc * lm + rc;
+                const double m = S[idx];
+                mv[q] = in ? m : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = t + 256 * q;
+                slab[e >> 6][e & 63] = mv[q];
             }
             __syncthreads();
             if (t >= r0 && t < r0 + 64 && t < N) {
@@ -1099,7 +1122,7 @@ static hipError_t gain_back(const Plan &p, uint64_t cycle, char *w, hipStream_t 
         size_t cap = (size_t)(p.N + 1) * p.nyp * 8;
         if (cap < 4096 * 8) cap = 4096 * 8;
         int ks = 1;
-        for (int c = 16; c > 1; c /= 2)
+        for (int c = GRAM_KSPLIT_MAX; c > 1; c /= 2)
             if ((p.nyp / 64) % c == 0 && (size_t)c * ntile * 4096 * 8 <= cap) {
                 ks = c;
                 break;
@@ -1113,7 +1136,7 @@ static hipError_t gain_back(const Plan &p, uint64_t cycle, char *w, hipStream_t 
             double *part = (double *)(w + p.off_scratch);
             hipLaunchKernelGGL(gram_extra_part, dim3(ntile, ks), dim3(256), lds, s, (const double *)A, p.ld, p.nyp,
                                p.nyp / ks, part);
-            hipLaunchKernelGGL(gram_extra_sum, dim3(ntile), dim3(256), 0, s, (const double *)part, ntile, ks,
+            hipLaunchKernelGGL(gram_extra_sum, dim3(ntile, 16), dim3(256), 0, s, (const double *)part, ntile, ks,
                                p.mextp, P);
         }
         hipLaunchKernelGGL(ens_assemble, dim3(256), dim3(256), 0, s, (const double *)P, p.mextp, p.N, p.npm, p.lds,
