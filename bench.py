@@ -196,8 +196,10 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
             for k in ("plain", "learned", "plain_feedback")}
     ctx = runs["plain"].ctx
     truth = torch.as_tensor(fields.truth_ic(cfg), dtype=torch.float32, device="cuda").contiguous()
+    free = runs["plain"].fine.clone()          # the same fine model and initial state, no analysis
     out = torch.zeros(3, dtype=torch.float64, device="cuda")
-    rm = {"plain": [], "learned": [], "plain_feedback": []}
+    rm = {"plain": [], "learned": [], "plain_feedback": [], "free": []}
+    spread = []
     judge = []
     scratch = torch.empty_like(runs["plain"].fine)
     for c in range(1, n_cycles + 1):
@@ -225,6 +227,13 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
             cc.diagnostics(r.fine, truth, out=out)
             o = out.cpu().numpy()
             rm[k].append(float(np.sqrt(o[0] / o[1])))
+        ctx.forecast(m.MENKF_FINE, free, cfg.n_obs)
+        ctx.diagnostics(free, truth, out=out)
+        o = out.cpu().numpy()
+        rm["free"].append(float(np.sqrt(o[0] / o[1])))
+        if c == 1 or c == n_cycles:
+            o = ctx.spread(runs["plain"].members).cpu().numpy()
+            spread.append(float(np.sqrt(o[0] / o[1])))
     for r in runs.values():
         if r.ctx.get_status() != 0:
             raise RuntimeError("analysis failed in the RMSE comparison")
@@ -233,6 +242,9 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
     return {
         "plain_rmse": res["plain"], "learned_rmse": res["learned"],
         "ratio": res["learned"] / res["plain"], "equal_rmse": res["learned"] <= 1.05 * res["plain"],
+        "free_run_rmse": res["free"], "plain_below_free_run": 1.0 - res["plain"] / res["free"],
+        "learned_below_free_run": 1.0 - res["learned"] / res["free"],
+        "plain_member_spread_first_last": spread,
         "feedback_rmse": res["plain_feedback"], "feedback_ratio": res["plain_feedback"] / res["plain"],
         "cycles": n_cycles, "learned_every_cycle": True,
         "fallback_tiles": int(net.fallback_count.item()), "correction_distance_to_plain": judge,
@@ -274,8 +286,8 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
         "contract_bytes": contract,
         "traffic": measured_traffic(sc),
         "min_bytes": minimum,
-        "achieved": contract / avg_s / 1e9,
-        "achieved_min": minimum / avg_s / 1e9,
+        "achieved_contract": contract / avg_s / 1e9,
+        "achieved": minimum / avg_s / 1e9,
     }
 
 
@@ -313,6 +325,39 @@ def update_gemm_utilisation(cfg, cyc, reps=20):
             "hbm_gbs": nbytes / avg / 1e9, "hbm_frac": nbytes / avg / 1e9 / HBM_PEAK_GBS}
 
 
+FP64_PEAK_TFLOPS_MATRIX = 78.6
+MALL_NOTE = ("not split: FETCH_SIZE / WRITE_SIZE count the L2 <-> data-fabric traffic, which includes "
+             "Infinity Cache (MALL) hits; the counter list of rocprofv3 on this GPU exposes no MALL hit counter")
+
+
+def gain_fp64_utilisation(cfg, cyc, reps=5):
+    """The analysis (menkf_gain: observation of the members, anomalies, FP64
+    S = Y Y^T + R on FP64 MFMA, blocked FP64 Cholesky with the solves folded
+    in, Z = Y^T S^-1 [D | d*]) timed alone with HIP events on its own stream,
+    against its algorithmic FP64 work 2 N_y^2 N (S) + N_y^3 / 3 (Cholesky)
+    + 2 N_y^2 (N + 1) (solves) + 2 N_y N (N + 1) (Z)."""
+    import torch
+    stream = torch.cuda.Stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        cyc.ctx.gain(cyc.members, cyc.xs, cyc.y, 1, 1, stream=stream)
+        e0.record(stream)
+        for r in range(reps):
+            cyc.ctx.gain(cyc.members, cyc.xs, cyc.y, 1, 2 + r, stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    avg = e0.elapsed_time(e1) / 1e3 / reps
+    ny, n = float(cfg.n_probes), float(cfg.n_members)
+    parts = {"S": 2 * ny * ny * n, "cholesky": ny ** 3 / 3, "solves": 2 * ny * ny * (n + 1),
+             "Z": 2 * ny * n * (n + 1)}
+    flops = sum(parts.values())
+    return {"call": "menkf_gain (exact R, N_y x N_y FP64)", "avg_us": avg * 1e6, "flops": flops,
+            "flops_parts": parts, "tflops": flops / avg / 1e12,
+            "frac_of_fp64_peak": flops / avg / 1e12 / FP64_PEAK_TFLOPS_MATRIX}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ns_stage_64x4x256sq_traffic.md")
 
 
@@ -332,6 +377,19 @@ def measured_traffic(schedule):
     if vals.get("kernel_source_sha256") != h or vals.get("profiled_coarse_schedule") != tag:
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu), for the baseline's record."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return None
 
 
 def cpu_baseline(cfg):
@@ -368,6 +426,7 @@ def cpu_baseline(cfg):
         "value": 1.0 / per_cycle,
         "unit": "cycles/s",
         "cores": cores,
+        "cpu": cpu_model(),
         "kind": "oracle",
         "sample": (f"1 fine RK4 step ({t_fine_step:.2f}s), {nm} member steps ({t_member_step:.2f}s each), "
                    f"1 analysis ({t_analysis:.2f}s), prolong + 3 sweeps ({t_prolong:.2f}s); "
@@ -487,7 +546,7 @@ def dual_cpu_baseline(cfg, n_cycles=20):
     for _ in range(n_cycles):
         st, _ = dual.dual_cycle(cfg, st, y, idx, n_sweeps=1)
     sec = time.perf_counter() - t
-    return {"value": n_cycles / sec, "unit": "dual cycles/s", "cores": cores, "kind": "oracle",
+    return {"value": n_cycles / sec, "unit": "dual cycles/s", "cores": cores, "cpu": cpu_model(), "kind": "oracle",
             "sample": f"{n_cycles} dual cycles of the oracle at the full size ({sec:.1f}s)"}
 
 
@@ -1057,7 +1116,11 @@ def main():
     elif net is None:
         log(f"bench: no trained weights at {wpath}; learned variant not timed")
     rl = stage_kernel_roofline(cfg, plain)
-    log(f"bench: stage kernel avg {rl['avg_launch_us']:.1f} us, contract {rl['achieved']:.0f} GB/s")
+    log(f"bench: stage kernel avg {rl['avg_launch_us']:.1f} us, algorithmic {rl['achieved']:.0f} GB/s "
+        f"({100 * rl['achieved'] / HBM_PEAK_GBS:.1f} % of HBM peak), contract {rl['achieved_contract']:.0f} GB/s")
+    gu = gain_fp64_utilisation(cfg, plain)
+    log(f"bench: gain {gu['avg_us']:.0f} us, {gu['tflops']:.1f} TFLOP/s FP64 "
+        f"({100 * gu['frac_of_fp64_peak']:.1f} % of peak)")
     ug = update_gemm_utilisation(cfg, plain)
     log(f"bench: member update {ug['avg_launch_us']:.1f} us, MFMA {ug['mfma_tflops']:.0f} TFLOP/s "
         f"({100 * ug['mfma_frac_of_bf16_peak']:.1f} % of BF16 peak), HBM {ug['hbm_gbs']:.0f} GB/s")
@@ -1082,6 +1145,7 @@ def main():
             if tuned else "default",
             "precision": "FP32 stencils, FP64 innovation covariance/Cholesky/gain of x*, BF16x3 member update",
             "anomaly_gemm": ug,
+            "gain_fp64": gu,
             "variants": variants,
         },
         "roofline": {
@@ -1093,8 +1157,14 @@ def main():
             "traffic": rl["traffic"],
             "kernel": rl["kernel"],
             "avg_launch_us": rl["avg_launch_us"],
-            "bytes_per_launch": rl["contract_bytes"],
-            "frac_vs_step_minimum": rl["achieved_min"] / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": rl["min_bytes"],
+            "algorithmic_bytes": "one read and one write of the state per time step (2 F 4 B per point), "
+                                 "a quarter of it per RK4 stage launch",
+            "contract_bytes_per_launch": rl["contract_bytes"],
+            "contract_gbs": rl["achieved_contract"],
+            "contract_frac": rl["achieved_contract"] / HBM_PEAK_GBS,
+            "traffic_vs_algorithmic": (rl["traffic"] / rl["min_bytes"]) if rl["traffic"] else None,
+            "infinity_cache_split": MALL_NOTE,
         },
     }
     if args.cpu_baseline and not args.small:

@@ -381,6 +381,18 @@ menkf_status menkf_observe(menkf_ctx *ctx, int32_t level, const void *state_dev,
 menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa_dev, const void *xt_dev,
                                double *out_dev, menkf_stream stream);
 
+/* Ensemble spread of the coarse members (the ensemble estimate of the error
+ * covariance, P^e = X X^T with X = (x^(i) - mean) / sqrt(N_e - 1), Sec. 2.1.2),
+ * over the observed quantity (u in 1D Burgers, rho u in 1D Euler, the
+ * velocity pair (u, v) = (rho u, rho v) / rho in 2D), accumulated in FP64:
+ *   out_dev[0] = trace of P^e = sum_points sum_i (q^(i) - mean q)^2 / (nb - 1)
+ *   out_dev[1] = sum_points (mean q)^2   (sqrt(out[0] / out[1]) is the
+ *                relative spread, comparable with the relative RMSE)
+ *   out_dev[2] = number of non-finite values of q.
+ * members_dev: nb coarse states [nb][F][ny_c][nx_c], 2 <= nb <= n_members.
+ * Needs the workspace (reduction partials); asynchronous on stream. */
+menkf_status menkf_spread(menkf_ctx *ctx, const void *members_dev, int32_t nb, double *out_dev, menkf_stream stream);
+
 /* Residual of the fine-grid implicit-Euler system of the last step,
  * r = x_{k-1} + dt F(x) - x (fine states, r must not alias the inputs).
  * The conservativity indicator of Sec. 6 for a conserved field is

@@ -395,6 +395,17 @@ class Context:
         self._check(self.lib.menkf_diagnostics(self.handle, _ptr(xa), _ptr(xt), _ptr(out), _stream(stream)))
         return out
 
+    def spread(self, members: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """menkf_spread: (trace of the ensemble covariance, sum of the squared
+        mean, non-finite count) of the observed quantity of nb coarse states."""
+        self._state(members, self.coarse_shape, "members")
+        if members.dim() != len(self.coarse_shape) + 1:
+            raise ValueError("members must be a batch of coarse states")
+        if out is None:
+            out = torch.empty(3, dtype=torch.float64, device=self.device)
+        self._check(self.lib.menkf_spread(self.handle, _ptr(members), members.shape[0], _ptr(out), _stream(stream)))
+        return out
+
 
 class Graph:
     """A captured sequence of menkf_* calls (menkf_graph_* entry points)."""

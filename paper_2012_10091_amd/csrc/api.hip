@@ -585,6 +585,14 @@ menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa, const void *xt, d
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_diagnostics");
 }
 
+menkf_status menkf_spread(menkf_ctx *ctx, const void *members, int32_t nb, double *out, menkf_stream stream) {
+    NEED_WS(ctx);
+    if (!members || !out) return fail(ctx, MENKF_E_ARG, "null pointer");
+    if (nb < 2 || nb > ctx->plan.N) return fail(ctx, MENKF_E_ARG, "nb must be in [2, %d] (got %d)", ctx->plan.N, nb);
+    const hipError_t e = launch_spread(ctx->plan, members, nb, out, ctx->ws, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_spread");
+}
+
 menkf_status menkf_residual(menkf_ctx *ctx, const void *x, const void *xprev, void *r, menkf_stream stream) {
     if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
     if (!x || !xprev || !r) return fail(ctx, MENKF_E_ARG, "null pointer");

@@ -241,6 +241,7 @@ hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipSt
 hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, double *y,
                           const int32_t *idx, const int32_t *comp, hipStream_t s);
 hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, double *out, void *ws, hipStream_t s);
+hipError_t launch_spread(const Plan &p, const void *members, int nb, double *out, void *ws, hipStream_t s);
 hipError_t launch_set_word(int32_t *w, int32_t v, hipStream_t s);
 hipError_t launch_set_word64(uint64_t *w, uint64_t v, hipStream_t s);
 // learned prolongation

@@ -1,8 +1,11 @@
 // Diagnostics (Sec. 4, relative RMSE): sum (xa - xt)^2 and sum xt^2 over
 // the observed quantity (u in 1D Burgers, rho u in 1D Euler, (u, v) =
-// momentum/density in 2D) and the
-// count of non-finite entries of xa.  Deterministic two-pass reduction in
-// FP64: fixed per-block partials, then one block sums them in order.
+// momentum/density in 2D) and the count of non-finite entries of xa; and
+// the ensemble spread: the trace of the ensemble error covariance
+// P^e = X X^T (Sec. 2.1.2) over the same quantity of the coarse members,
+// with the squared ensemble mean for its normalisation.  Deterministic
+// two-pass reductions in FP64: fixed per-block partials, then one block
+// sums them in order.
 #include "common.hpp"
 
 namespace menkf {
@@ -49,12 +52,88 @@ __global__ __launch_bounds__(256) void diag_partial(const T *__restrict__ xa, co
     }
 }
 
-__global__ __launch_bounds__(64) void diag_final(const double *__restrict__ part, int nblocks, double *__restrict__ out) {
-    if (threadIdx.x < 3) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += part[3 * b + threadIdx.x];
-        out[threadIdx.x] = s;
+// Ensemble spread, one grid point per thread and loop: the members' values
+// q^(k) of the observed quantity are summed as deviations from the first
+// member's value (shifted sums s1 = sum d, s2 = sum d^2, d = q^(k) - q^(0)),
+// so sum_k (q^(k) - mean)^2 = s2 - s1^2 / nb and mean = q^(0) + s1 / nb
+// carry no cancellation of the mean's magnitude.  A single pass over the
+// members, all in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void spread_partial(const T *__restrict__ mem, int dim, long long nc,
+                                                      long long mstride, int nb, double inv_nm1,
+                                                      double *__restrict__ part) {
+    __shared__ double s0[256], s1[256], s2[256];
+    double a = 0.0, b = 0.0, c = 0.0;
+    const double inv_nb = 1.0 / (double)nb;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < nc; i += (long long)gridDim.x * 256) {
+        if (dim == 1) {
+            const double q0 = (double)mem[i];
+            double su = 0.0, sq = 0.0;
+            for (int k = 0; k < nb; ++k) {
+                const double q = (double)mem[k * mstride + i];
+                if (!isfinite(q)) c += 1.0;
+                const double d = q - q0;
+                su += d;
+                sq += d * d;
+            }
+            a += (sq - su * su * inv_nb) * inv_nm1;
+            const double mean = q0 + su * inv_nb;
+            b += mean * mean;
+        } else {
+            const double u0 = (double)mem[nc + i] / (double)mem[i];
+            const double v0 = (double)mem[2 * nc + i] / (double)mem[i];
+            double su = 0.0, squ = 0.0, sv = 0.0, sqv = 0.0;
+            for (int k = 0; k < nb; ++k) {
+                const T *mk = mem + k * mstride;
+                const double r = (double)mk[i];
+                const double u = (double)mk[nc + i] / r, v = (double)mk[2 * nc + i] / r;
+                if (!isfinite(u)) c += 1.0;
+                if (!isfinite(v)) c += 1.0;
+                const double du = u - u0, dv = v - v0;
+                su += du;
+                squ += du * du;
+                sv += dv;
+                sqv += dv * dv;
+            }
+            a += ((squ - su * su * inv_nb) + (sqv - sv * sv * inv_nb)) * inv_nm1;
+            const double mu = u0 + su * inv_nb, mv = v0 + sv * inv_nb;
+            b += mu * mu + mv * mv;
+        }
     }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    s2[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            s0[threadIdx.x] += s0[threadIdx.x + h];
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+            s2[threadIdx.x] += s2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = s0[0];
+        part[3 * blockIdx.x + 1] = s1[0];
+        part[3 * blockIdx.x + 2] = s2[0];
+    }
+}
+
+// Sum of the per-block partials in a fixed order: thread t adds partials
+// t, t + 256, ... of each quantity, then a tree over the 256 threads.
+__global__ __launch_bounds__(256) void diag_final(const double *__restrict__ part, int nblocks, double *__restrict__ out) {
+    __shared__ double s[3][256];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+        for (int q = 0; q < 3; ++q) a[q] += part[3 * b + q];
+    for (int q = 0; q < 3; ++q) s[q][threadIdx.x] = a[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            for (int q = 0; q < 3; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
 hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, double *out, void *ws, hipStream_t s) {
@@ -72,7 +151,27 @@ hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, dou
     else
         hipLaunchKernelGGL(diag_partial<float>, dim3(nb), dim3(256), 0, s, (const float *)xa, (const float *)xt, p.dim,
                            nf, part);
-    hipLaunchKernelGGL(diag_final, dim3(1), dim3(64), 0, s, (const double *)part, nb, out);
+    hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, s, (const double *)part, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_spread(const Plan &p, const void *members, int nb, double *out, void *ws, hipStream_t s) {
+    double *part = (double *)((char *)ws + p.off_scratch);
+    const long long nc = p.nc;
+    const long long mstride = (long long)p.F * nc;
+    // 1D: the observed field of every member (u for Burgers, rho u for Euler)
+    const size_t off = (size_t)p.obs_field * nc * p.tsize;
+    const void *m = (const char *)members + (p.dim == 1 ? off : 0);
+    int nblk = (int)((nc + 255) / 256);
+    if (nblk > DIAG_BLOCKS) nblk = DIAG_BLOCKS;
+    const double inv_nm1 = 1.0 / (double)(nb - 1);
+    if (p.cfg.precision == MENKF_F64)
+        hipLaunchKernelGGL(spread_partial<double>, dim3(nblk), dim3(256), 0, s, (const double *)m, p.dim, nc, mstride,
+                           nb, inv_nm1, part);
+    else
+        hipLaunchKernelGGL(spread_partial<float>, dim3(nblk), dim3(256), 0, s, (const float *)m, p.dim, nc, mstride,
+                           nb, inv_nm1, part);
+    hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, s, (const double *)part, nblk, out);
     return hipGetLastError();
 }
 

@@ -122,6 +122,29 @@ def test_forecast_c2_shapes_f32():
     del rs
 
 
+def test_forecast_c3_shapes_f32():
+    """The 2D workload's shapes: the 1024^2 fine state and 8 members on the
+    256^2 coarse grid, one whole observation window (20 RK4 steps), FP32
+    against the FP64 oracle from the same FP32 inputs."""
+    cfg = configs.CONFIGS["C3"].with_(n_members=8)
+    ctx, _, _ = make_ctx(cfg)
+    xf = _round(fields.truth_ic(cfg), cfg)
+    mem = _round(fields.member_ics(cfg), cfg)
+    say("forecast C3 shapes: fine", xf.shape, "coarse", mem.shape, "steps", cfg.n_obs)
+    xf_d, mem_d = to_dev(xf, F32), to_dev(mem, F32)
+    prev_d = torch.empty_like(xf_d)
+    ctx.forecast(0, xf_d, cfg.n_obs, prev=prev_d)
+    ctx.forecast(1, mem_d, cfg.n_obs)
+    o_f, o_p = Model(cfg, "fine").forecast(xf, cfg.n_obs)
+    o_m, _ = Model(cfg, "coarse").forecast(mem, cfg.n_obs)
+    e = (rel_l2(to_np(xf_d), o_f), rel_l2(to_np(prev_d), o_p), rel_l2(to_np(mem_d), o_m))
+    say(f"  rel-L2 fine {e[0]:.2e} prev {e[1]:.2e} members {e[2]:.2e}")
+    assert max(e) < 1e-5
+    g = to_np(mem_d)
+    for i in range(cfg.n_members):
+        assert rel_l2(g[i], o_m[i]) < 1e-5, i
+
+
 def test_forecast_conserves_totals_f64():
     cfg = configs.ragged_2d(precision="f64")
     ctx, _, _ = make_ctx(cfg)
@@ -319,6 +342,49 @@ def test_c1_cycles_fp64_match_oracle():
         assert rel_l2(to_np(st_g["fine"]), st_o.fine) < 1e-10, c
         assert rel_l2(to_np(st_g["members"]), st_o.members) < 1e-10, c
     assert ctx.get_status() == 0
+
+
+def test_c2_three_cycles_f32():
+    """Three whole cycles of the 1D workload at scale (16384 / 4096, N = 256,
+    1024 probes every 5 steps; FP32 states, BF16x3 member update, FP64
+    Cholesky of the 1024 x 1024 innovation covariance) against the oracle
+    run independently from the same initial states, observations and
+    perturbations (device Philox on the GPU, its NumPy twin in the oracle).
+    The analysed fine state and members stay within the analysis tolerance
+    after every cycle, the differences of earlier cycles carried along."""
+    cfg = configs.CONFIGS["C2"]
+    ctx, idx, comp = make_ctx(cfg)
+    truth = fields.truth_ic(cfg)
+    fine = _round(fields.model_ic(cfg), cfg)
+    mem = _round(fields.member_ics(cfg), cfg)
+    st_o = ocycle.State(fine=fine, members=mem)
+    st_g = {"fine": to_dev(fine, F32), "members": to_dev(mem, F32)}
+    mt = Model(cfg, "fine")
+    seed = cfg.seed + 5
+    for c in range(1, 4):
+        truth, _ = mt.forecast(truth, cfg.n_obs)
+        y = ocycle.observe_truth(cfg, truth, idx, comp) + fields.obs_noise(cfg, c)
+        say(f"C2 cycle {c}")
+        st_o = ocycle.cycle(cfg, st_o, y, idx, comp, n_sweeps=1, seed=seed)
+        _gpu_cycle(ctx, cfg, st_g, to_dev(y, F64), c, 1, seed)
+        e_f = rel_l2(to_np(st_g["fine"]), st_o.fine)
+        e_m = rel_l2(to_np(st_g["members"]), st_o.members)
+        say(f"  rel-L2 fine {e_f:.2e} members {e_m:.2e}")
+        assert e_f < 1e-3 and e_m < 1e-3, (c, e_f, e_m)
+    assert ctx.get_status() == 0
+
+
+def test_c2_member_window_from_gpu_state_f32():
+    """One C2 member window from identical inputs (the FP32 tolerance of a
+    forecast is stated for one window from the same states)."""
+    cfg = configs.CONFIGS["C2"]
+    ctx, _, _ = make_ctx(cfg)
+    mem = _round(fields.random_members_like(cfg), cfg)
+    d = to_dev(mem, F32)
+    say("C2 member window", mem.shape)
+    ctx.forecast(1, d, cfg.n_obs)
+    o_m, _ = Model(cfg, "coarse").forecast(mem, cfg.n_obs)
+    assert rel_l2(to_np(d), o_m) < 1e-5
 
 
 def test_graph_replay_matches_eager():
