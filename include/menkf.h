@@ -381,6 +381,22 @@ menkf_status menkf_observe(menkf_ctx *ctx, int32_t level, const void *state_dev,
 menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa_dev, const void *xt_dev,
                                double *out_dev, menkf_stream stream);
 
+/* menkf_diagnostics for callers that cannot allocate device memory or
+ * attach a workspace (code under HIP graph capture, serving loops, hosts
+ * that forbid hipMalloc): the same outputs from the same kernels, with the
+ * reduction partials (at most 3 x 512 doubles) in a static device array of
+ * 2048 doubles (16 KiB) that the library holds on every GPU it runs on until
+ * the process ends, instead of the context workspace.  The context needs no
+ * workspace.  Allocates nothing: no hipMalloc, hipFree or allocating library
+ * call.  The first call on a device looks the array's address up once
+ * (hipGetSymbolAddress) and keeps it; make that first call outside a graph
+ * capture.  A request needing more partials than the array holds returns
+ * MENKF_E_WORKSPACE (none does with the present block cap).  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (on two
+ * streams, or from two threads) race and must be serialised by the caller. */
+menkf_status menkf_diagnostics_noalloc(menkf_ctx *ctx, const void *xa_dev, const void *xt_dev, double *out_dev,
+                                       menkf_stream stream);
+
 /* Ensemble spread of the coarse members (the ensemble estimate of the error
  * covariance, P^e = X X^T with X = (x^(i) - mean) / sqrt(N_e - 1), Sec. 2.1.2),
  * over the observed quantity (u in 1D Burgers, rho u in 1D Euler, the

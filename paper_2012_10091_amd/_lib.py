@@ -134,6 +134,7 @@ SIGNATURES = {
     "menkf_diagnostics": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_residual": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_spread": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "menkf_diagnostics_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_ram_ratio": (c_double, [c_int32, c_int32, c_int32]),
     "menkf_cycle": (c_int32, [ctypes.POINTER(MenkfCycleArgs), c_void_p]),
     "menkf_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p)]),

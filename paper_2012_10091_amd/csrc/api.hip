@@ -585,6 +585,19 @@ menkf_status menkf_diagnostics(menkf_ctx *ctx, const void *xa, const void *xt, d
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_diagnostics");
 }
 
+menkf_status menkf_diagnostics_noalloc(menkf_ctx *ctx, const void *xa, const void *xt, double *out,
+                                       menkf_stream stream) {
+    if (!ctx) return fail(nullptr, MENKF_E_ARG, "ctx is NULL");
+    if (!xa || !xt || !out) return fail(ctx, MENKF_E_ARG, "null pointer");
+    const size_t need = diagnostics_noalloc_need(ctx->plan), cap = diagnostics_noalloc_capacity();
+    if (need > cap)
+        return fail(ctx, MENKF_E_WORKSPACE,
+                    "menkf_diagnostics_noalloc: the reduction needs %zu doubles of scratch, the static array holds %zu",
+                    need, cap);
+    const hipError_t e = launch_diagnostics_noalloc(ctx->plan, xa, xt, out, (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_diagnostics_noalloc");
+}
+
 menkf_status menkf_spread(menkf_ctx *ctx, const void *members, int32_t nb, double *out, menkf_stream stream) {
     NEED_WS(ctx);
     if (!members || !out) return fail(ctx, MENKF_E_ARG, "null pointer");

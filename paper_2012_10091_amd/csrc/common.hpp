@@ -242,6 +242,10 @@ hipError_t launch_observe(const Plan &p, int level, const void *state, int nb, d
                           const int32_t *idx, const int32_t *comp, hipStream_t s);
 hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, double *out, void *ws, hipStream_t s);
 hipError_t launch_spread(const Plan &p, const void *members, int nb, double *out, void *ws, hipStream_t s);
+// menkf_diagnostics with its partials in a static device array (no workspace)
+hipError_t launch_diagnostics_noalloc(const Plan &p, const void *xa, const void *xt, double *out, hipStream_t s);
+size_t diagnostics_noalloc_need(const Plan &p);   // doubles of the array one call uses
+size_t diagnostics_noalloc_capacity();              // doubles the array holds
 hipError_t launch_set_word(int32_t *w, int32_t v, hipStream_t s);
 hipError_t launch_set_word64(uint64_t *w, uint64_t v, hipStream_t s);
 // learned prolongation

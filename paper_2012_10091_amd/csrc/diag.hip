@@ -6,6 +6,8 @@
 // with the squared ensemble mean for its normalisation.  Deterministic
 // two-pass reductions in FP64: fixed per-block partials, then one block
 // sums them in order.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace menkf {
@@ -136,15 +138,20 @@ __global__ __launch_bounds__(256) void diag_final(const double *__restrict__ par
     if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
-hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, double *out, void *ws, hipStream_t s) {
-    double *part = (double *)((char *)ws + p.off_scratch);
+// Number of reduction workgroups of the diagnostics (each writes three partials).
+static int diagnostics_blocks(const Plan &p) {
+    const long long nb = (p.nf + 255) / 256;
+    return nb > DIAG_BLOCKS ? DIAG_BLOCKS : (int)nb;
+}
+
+static hipError_t diagnostics_into(const Plan &p, const void *xa, const void *xt, double *out, double *part,
+                                   hipStream_t s) {
     const long long nf = p.nf;
     // 1D: the observed field (u for Burgers, rho u for the Euler model)
     const size_t off = (size_t)p.obs_field * nf * p.tsize;
     xa = (const char *)xa + off;
     xt = (const char *)xt + off;
-    int nb = (int)((nf + 255) / 256);
-    if (nb > DIAG_BLOCKS) nb = DIAG_BLOCKS;
+    const int nb = diagnostics_blocks(p);
     if (p.cfg.precision == MENKF_F64)
         hipLaunchKernelGGL(diag_partial<double>, dim3(nb), dim3(256), 0, s, (const double *)xa, (const double *)xt,
                            p.dim, nf, part);
@@ -153,6 +160,52 @@ hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, dou
                            nf, part);
     hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, s, (const double *)part, nb, out);
     return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const Plan &p, const void *xa, const void *xt, double *out, void *ws, hipStream_t s) {
+    return diagnostics_into(p, xa, xt, out, (double *)((char *)ws + p.off_scratch), s);
+}
+
+// Reduction partials of the allocation-free diagnostics: a fixed device
+// array in place of the context workspace.  Every device the library runs
+// on holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device (the
+// array's name in host code is not a device address).
+constexpr int NOALLOC_DOUBLES = 2048;   // 16 KiB: room for 682 workgroups' partials
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// The scratch array's address on the current device, looked up once per
+// device (with that device current) and kept.
+static hipError_t noalloc_scratch(double **ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        double *a = nullptr;
+        e = hipGetSymbolAddress((void **)&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = a;
+    }
+    *ptr = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+size_t diagnostics_noalloc_need(const Plan &p) { return (size_t)3 * diagnostics_blocks(p); }
+size_t diagnostics_noalloc_capacity() { return NOALLOC_DOUBLES; }
+
+// Every partial the final sum reads is written by the same call first, so
+// the array needs no clearing between calls.
+hipError_t launch_diagnostics_noalloc(const Plan &p, const void *xa, const void *xt, double *out, hipStream_t s) {
+    double *part = nullptr;
+    const hipError_t e = noalloc_scratch(&part);
+    if (e != hipSuccess) return e;
+    return diagnostics_into(p, xa, xt, out, part, s);
 }
 
 hipError_t launch_spread(const Plan &p, const void *members, int nb, double *out, void *ws, hipStream_t s) {
