@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--sweeps", type=int, default=3)
     ap.add_argument("--rmse-cycles", type=int, default=100)
-    ap.add_argument("--judge-every", type=int, default=10)
+    ap.add_argument("--judge-every", type=int, default=10,
+                    help="the learned prolongation's judge: every n-th cycle the plain correction is formed and "
+                         "compared (and replaces the network's above the tolerance)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--weights", default=None)
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
@@ -190,10 +192,11 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
     import torch
     import paper_2012_10091_amd as m
     from synthetic import fields
-    runs = {k: Cycle(cfg, n_sweeps if k != "learned" else 0,
+    runs = {k: Cycle(cfg, n_sweeps,
                      mode=m.MENKF_PROLONG_LEARNED_FALLBACK if k == "learned" else m.MENKF_PROLONG_PLAIN,
                      net=net if k == "learned" else None)
             for k in ("plain", "learned", "plain_feedback")}
+    net.judge_stats.zero_()
     ctx = runs["plain"].ctx
     truth = torch.as_tensor(fields.truth_ic(cfg), dtype=torch.float32, device="cuda").contiguous()
     free = runs["plain"].fine.clone()          # the same fine model and initial state, no analysis
@@ -213,15 +216,17 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
             cc.restrict(r.fine, r.xs)
             cc.gain(r.members, r.xs, r.y, r.seed, c)
             cc.update(r.members, r.dc)
-            judging = k == "learned" and c % judge_every == 0
-            if judging:
-                xf_copy = r.fine.clone()
+            if k == "learned" and c % 10 == 0:
+                # the network's own correction (no judge) against the plain
+                # correction of the same analysis, on scratch copies
                 scratch.copy_(r.fine)
                 cc.prolong_smooth(r.dc, scratch, r.prev, n_sweeps=n_sweeps, alpha=0.5)
-            cc.prolong_smooth(r.dc, r.fine, r.prev, n_sweeps=r.n_sweeps, alpha=0.5, mode=r.mode, net=r.net)
-            if judging:
-                d = float(torch.linalg.vector_norm(r.fine - scratch) / torch.linalg.vector_norm(scratch - xf_copy))
+                nn = r.fine.clone()
+                cc.prolong_smooth(r.dc, nn, None, n_sweeps=0, mode=m.MENKF_PROLONG_LEARNED, net=r.net)
+                d = float(torch.linalg.vector_norm(nn - scratch) / torch.linalg.vector_norm(scratch - r.fine))
                 judge.append((c, d))
+                del nn
+            cc.prolong_smooth(r.dc, r.fine, r.prev, n_sweeps=r.n_sweeps, alpha=0.5, mode=r.mode, net=r.net)
             if k == "plain_feedback":
                 cc.recentre(r.members, r.fine)
             cc.diagnostics(r.fine, truth, out=out)
@@ -237,6 +242,7 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
     for r in runs.values():
         if r.ctx.get_status() != 0:
             raise RuntimeError("analysis failed in the RMSE comparison")
+    js = net.judge_stats.cpu().numpy()
     half = n_cycles // 2
     res = {k: float(np.mean(v[half:])) for k, v in rm.items()}
     return {
@@ -246,8 +252,12 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
         "learned_below_free_run": 1.0 - res["learned"] / res["free"],
         "plain_member_spread_first_last": spread,
         "feedback_rmse": res["plain_feedback"], "feedback_ratio": res["plain_feedback"] / res["plain"],
-        "cycles": n_cycles, "learned_every_cycle": True,
-        "fallback_tiles": int(net.fallback_count.item()), "correction_distance_to_plain": judge,
+        "cycles": n_cycles,
+        "judge": {"every": net.judge_every, "tol": net.judge_tol, "judged": int(js[1]),
+                  "plain_corrected_cycles": int(js[2]), "guarded_cycles": int(js[3]),
+                  "last_judged_distance": float(js[0])},
+        "guarded_tiles": int(net.fallback_count.item()),
+        "network_distance_to_plain_correction": judge,
         "rmse_first_last": {k: [v[0], v[-1]] for k, v in rm.items()},
     }
 
@@ -434,13 +444,12 @@ def cpu_baseline(cfg):
     }
 
 
-def load_net(cfg, path):
-    import paper_2012_10091_amd as m
+def load_net(cfg, path, judge_every):
     from paper_2012_10091_amd import learned
     path = path or learned.DEFAULT_WEIGHTS
     if not os.path.exists(path):
         return None, path
-    return learned.load(path, guard=10.0), path
+    return learned.load(path, guard=10.0, judge_every=judge_every), path
 
 
 def bench_batch(args):
@@ -451,7 +460,7 @@ def bench_batch(args):
     from paper_2012_10091_amd import learned
     from synthetic import configs, fields
     cfgs = configs.uneven_batch()
-    net = learned.load(learned.weights_for("ns2d_512_128_n32"), guard=10.0)
+    net = learned.load(learned.weights_for("ns2d_512_128_n32"), guard=10.0, judge_every=args.judge_every)
     f32 = torch.float32
     insts = []
     t0 = time.perf_counter()
@@ -481,7 +490,7 @@ def bench_batch(args):
         batch = m.Batch(n_lanes=lanes)
         stream = torch.cuda.Stream()
         a = [i["ctx"].cycle_args(i["fine"], i["prev"], i["members"], i["xs"], i["dc"], i["y"], i["cfg"].seed + 5,
-                                 m.MENKF_CYCLE_DEVICE, i["cfg"].n_obs, n_sweeps=0, alpha=0.5,
+                                 m.MENKF_CYCLE_DEVICE, i["cfg"].n_obs, n_sweeps=args.sweeps, alpha=0.5,
                                  mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net) for i in insts]
         torch.cuda.synchronize()
         with torch.cuda.stream(stream):
@@ -518,7 +527,8 @@ def bench_batch(args):
                    "probes_range": [min(c.n_probes for c in cfgs), max(c.n_probes for c in cfgs)],
                    "lanes": args.lanes, "lane_of": lanes, "instance_cycles_per_s": cps * len(insts),
                    "one_lane_batch_cycles_per_s": cps1, "autotuned": bool(args.autotune),
-                   "prolongation": "learned with per-tile fallback", "failed_instances": bad + bad1},
+                   "prolongation": f"learned, judged every {net.judge_every} cycles against Pi_F + {args.sweeps} "
+                                   f"sweeps (its fallback)", "failed_instances": bad + bad1},
     }
     print(json.dumps(out), flush=True)
 
@@ -1078,23 +1088,27 @@ def main():
     variants = {"plain": {"cycles_per_s": plain_cps, "ms_per_cycle": sec / args.steps * 1e3,
                           "prolongation": f"Pi_F + {args.sweeps} relaxed sweeps"}}
     value, ms = plain_cps, sec / args.steps * 1e3
-    net, wpath = load_net(cfg, args.weights)
+    net, wpath = load_net(cfg, args.weights, args.judge_every)
     headline = "plain"
     if net is not None and not args.small:
-        learned = Cycle(cfg, 0, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
+        learned = Cycle(cfg, args.sweeps, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
+        net.judge_stats.zero_()
         if tuned:
             learned.ctx.set_schedule(m.MENKF_FINE, tuned["fine"]["tile"], tuned["fine"]["member_chunk"])
             learned.ctx.set_schedule(m.MENKF_COARSE, tuned["coarse"]["tile"], tuned["coarse"]["member_chunk"])
         lsec, _ = time_cycles(learned, Y, args.warmup, args.steps)
         lstatus = learned.ctx.get_status()
         lcps = args.steps / lsec
+        tjs = net.judge_stats.cpu().numpy()
         log(f"bench: learned {lcps:.2f} cycles/s, status {lstatus}")
         net.fallback_count.zero_()
         cmp = rmse_comparison(cfg, net, args.rmse_cycles, args.sweeps, args.judge_every)
         log(f"bench: RMSE plain {cmp['plain_rmse']:.5f} learned {cmp['learned_rmse']:.5f} "
             f"(ratio {cmp['ratio']:.3f}, equal {cmp['equal_rmse']})")
         variants["learned"] = {"cycles_per_s": lcps, "ms_per_cycle": lsec / args.steps * 1e3,
-                               "prolongation": "network with per-tile guard (fallback Pi_F)",
+                               "prolongation": f"network; judged every {net.judge_every} cycles against Pi_F + "
+                                               f"{args.sweeps} sweeps (its fallback above distance {net.judge_tol})",
+                               "timed_cycles_judged": int(tjs[1]), "timed_cycles_on_plain": int(tjs[2]),
                                "weights": os.path.relpath(wpath, ROOT)}
         variants["rmse"] = cmp
         if cmp["equal_rmse"] and lstatus == 0:
@@ -1102,8 +1116,8 @@ def main():
         # the same cycle with the ensemble-space form of the gain (an exact
         # identity for R = s^2 I; not the headline, which keeps the N_y x N_y
         # FP64 Cholesky of the workload)
-        ens = Cycle(with_gain_mode(cfg, m.MENKF_GAIN_ENSEMBLE_SPACE), 0, mode=m.MENKF_PROLONG_LEARNED_FALLBACK,
-                    net=net)
+        ens = Cycle(with_gain_mode(cfg, m.MENKF_GAIN_ENSEMBLE_SPACE), args.sweeps,
+                    mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
         if tuned:
             ens.ctx.set_schedule(m.MENKF_FINE, tuned["fine"]["tile"], tuned["fine"]["member_chunk"])
             ens.ctx.set_schedule(m.MENKF_COARSE, tuned["coarse"]["tile"], tuned["coarse"]["member_chunk"])

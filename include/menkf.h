@@ -273,11 +273,20 @@ menkf_status menkf_update(menkf_ctx *ctx, void *members_dev, void *deltac_dev, m
  *   implementation notes).
  *   MENKF_PROLONG_LEARNED: x' = x^F_f + Pi_F(delta^C) + NN(Pi_F(delta^C), x^F_f)
  *   with the network net (2D, MENKF_F32 contexts), no sweeps.
- *   MENKF_PROLONG_LEARNED_FALLBACK: as LEARNED, but every 16x16 pixel tile
- *   whose network output is non-finite or whose norm exceeds
- *   guard * |Pi_F(delta^C)| on that tile uses the plain Pi_F(delta^C)
- *   instead (counted in net->fallback_count_dev if given); then n_sweeps
- *   sweeps.
+ *   MENKF_PROLONG_LEARNED_FALLBACK: the network's correction, with the plain
+ *   correction (Pi_F(delta^C) and n_sweeps sweeps, as MENKF_PROLONG_PLAIN)
+ *   as its judge and its fallback; the network's output is not swept.
+ *   Every net->judge_every-th call of the context (the first included;
+ *   0 = never) also forms the plain correction x_plain and the distance
+ *   |x_net - x_plain| / |x_plain - x^F_f| (whole fine state, FP64 sums):
+ *   above net->judge_tol the plain correction is used, in this call and in
+ *   every call up to the next judged one (which may return to the
+ *   network).  Independently, a 16x16 pixel tile whose network output is
+ *   non-finite or whose norm exceeds guard * |Pi_F(delta^C)| on that tile
+ *   (counted in net->fallback_count_dev if given) makes that call use the
+ *   plain correction for the whole state.  The decisions are taken on the
+ *   device (graph-capturable); their state lives in the workspace and is
+ *   reset by menkf_set_workspace.
  * A no-op on the device if the status word is set.
  *
  * The network (not part of the paper; its closing section names better
@@ -294,7 +303,12 @@ typedef struct {
     const float *params;   /* FP32 parameter vector (the biases are read from it) */
     float in_scale[8], in_offset[8], out_scale[4];
     float guard;           /* fallback amplitude guard (LEARNED_FALLBACK) */
-    int32_t *fallback_count_dev; /* optional: incremented per fallback tile */
+    int32_t *fallback_count_dev; /* optional: incremented per guarded tile */
+    int32_t judge_every;   /* LEARNED_FALLBACK: judge every judge_every-th call; 0 = never */
+    float judge_tol;       /* LEARNED_FALLBACK: largest accepted relative distance to the plain correction */
+    double *judge_dev;     /* optional, 4 doubles accumulated by LEARNED_FALLBACK calls: [0] distance of
+                            * the last judged call, [1] judged calls, [2] calls corrected by the plain
+                            * path, [3] calls with a guarded tile */
 } menkf_net;
 
 menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *deltac_dev, void *xf_dev,

@@ -42,6 +42,8 @@ class MenkfNet(ctypes.Structure):
         ("out_scale", ctypes.c_float * 4),
         ("guard", ctypes.c_float),
         ("fallback_count_dev", c_void_p),
+        ("judge_every", c_int32), ("judge_tol", ctypes.c_float),
+        ("judge_dev", c_void_p),
     ]
 
 

@@ -503,7 +503,8 @@ def unpack_params(flat):
 class Net:
     """Device parameters of the learned prolongation (menkf_net / menkf_net_pack)."""
 
-    def __init__(self, params, in_scale, in_offset, out_scale, guard=10.0, device="cuda"):
+    def __init__(self, params, in_scale, in_offset, out_scale, guard=10.0, device="cuda", judge_every=0,
+                 judge_tol=1.0):
         self.lib = _lib.load()
         self.params = torch.as_tensor(params, dtype=torch.float32).reshape(-1).to(device).contiguous()
         if self.params.numel() != _lib.NET_NPARAM:
@@ -514,6 +515,10 @@ class Net:
         self.out_scale = [float(v) for v in out_scale]
         self.guard = float(guard)
         self.fallback_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.judge_every = int(judge_every)
+        self.judge_tol = float(judge_tol)
+        # [last judged distance, judged calls, calls on the plain correction, calls with a guarded tile]
+        self.judge_stats = torch.zeros(4, dtype=torch.float64, device=device)
         self.repack()
 
     def repack(self, stream=None):
@@ -532,6 +537,9 @@ class Net:
             n.out_scale[i] = self.out_scale[i]
         n.guard = self.guard
         n.fallback_count_dev = self.fallback_count.data_ptr()
+        n.judge_every = self.judge_every
+        n.judge_tol = self.judge_tol
+        n.judge_dev = self.judge_stats.data_ptr()
         self._c = n
         return n
 

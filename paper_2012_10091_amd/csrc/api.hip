@@ -188,6 +188,7 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
         p->off_mlinv = take(64 * 64 * 8);
         p->off_gpart = take((size_t)p->gchunks * (nt * (nt + 1) / 2) * 4096 * 8);
     }
+    p->off_judge = take((size_t)2 * JUDGE_BLOCKS * 8);
     p->ws_bytes = o;
     for (int l = 0; l < 2; ++l) {
         ns_tile_shape(cfg->precision, 0, &p->sched[l].tile_x, &p->sched[l].tile_y);
@@ -242,6 +243,7 @@ menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws, size_t bytes) {
     if (e == hipSuccess && ncu > 0) ctx->n_cus = ncu;
     if (e == hipSuccess) e = launch_set_word((int32_t *)((char *)ws + ctx->plan.off_info), 0, nullptr);
     if (e == hipSuccess) e = launch_set_word64((uint64_t *)((char *)ws + ctx->plan.off_info + 64), 1, nullptr);
+    if (e == hipSuccess) e = launch_zero_words((int32_t *)((char *)ws + ctx->plan.off_info + JUDGE_WORDS), JW_N, nullptr);
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_set_workspace");
     return MENKF_OK;
 }
@@ -433,6 +435,36 @@ menkf_status menkf_update(menkf_ctx *ctx, void *members, void *dc, menkf_stream 
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_update");
 }
 
+// MENKF_PROLONG_LEARNED_FALLBACK: the network's correction into the
+// workspace copy W, the plain correction (Pi_F, n_sweeps sweeps) into the
+// two other fine buffers when the judge needs it, then the selected one
+// into xf.  Every kernel is launched on every call; the device words of
+// the judge make the unneeded ones return at once.
+static menkf_status learned_with_judge(menkf_ctx *ctx, const void *dc, void *xf, const void *xprev, int n_sweeps,
+                                       double alpha, const menkf_net *net, hipStream_t s) {
+    const Plan &p = ctx->plan;
+    if (!(net->guard > 0.0f)) return fail(ctx, MENKF_E_ARG, "LEARNED_FALLBACK needs guard > 0");
+    if (net->judge_every < 0) return fail(ctx, MENKF_E_ARG, "judge_every must be >= 0");
+    if (net->judge_every > 0 && !(net->judge_tol >= 0.0f))
+        return fail(ctx, MENKF_E_ARG, "judge_tol must be >= 0 when judging");
+    const int32_t *info = (const int32_t *)((char *)ctx->ws + p.off_info);
+    int32_t *jw = (int32_t *)((char *)ctx->ws + p.off_info + JUDGE_WORDS);
+    void *W = (char *)ctx->ws + p.off_f1;
+    void *P[2] = {(char *)ctx->ws + p.off_f2, (char *)ctx->ws + p.off_facc};
+    hipError_t e = launch_judge_pre(info, jw, net->judge_every, s);
+    if (e == hipSuccess) e = launch_net_prolong(p, dc, xf, W, net, 1, jw + JW_SKIP_NET, jw + JW_TILES, s);
+    if (e == hipSuccess) e = launch_judge_mid(info, jw, s);
+    if (e == hipSuccess) e = launch_prolong_add(p, dc, xf, P[0], jw + JW_SKIP_PLAIN, s);
+    int cur = 0;
+    for (int k = 0; k < n_sweeps && e == hipSuccess; ++k) {
+        e = launch_sweep(p, P[cur], xprev, P[1 - cur], alpha, jw + JW_SKIP_PLAIN, ctx->ws, s);
+        cur = 1 - cur;
+    }
+    if (e == hipSuccess) e = launch_judge_decide(p, W, P[cur], xf, info, jw, net->judge_tol, net->judge_dev, ctx->ws, s);
+    if (e == hipSuccess) e = launch_judge_select(p, W, P[cur], xf, info, jw, s);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_prolong_smooth (learned with judge)");
+}
+
 menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, const void *xprev, int32_t n_sweeps,
                                   double alpha, int32_t mode, const menkf_net *net, menkf_stream stream) {
     NEED_WS(ctx);
@@ -463,12 +495,12 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
             return fail(ctx, MENKF_E_ARG, "learned prolongation needs a menkf_net with packed weights and parameters");
         for (int i = 0; i < 4; ++i)
             if (!(net->out_scale[i] != 0.0f)) return fail(ctx, MENKF_E_ARG, "net out_scale must be non-zero");
-        if (mode == MENKF_PROLONG_LEARNED_FALLBACK && !(net->guard > 0.0f))
-            return fail(ctx, MENKF_E_ARG, "LEARNED_FALLBACK needs guard > 0");
+        if (mode == MENKF_PROLONG_LEARNED_FALLBACK)
+            return learned_with_judge(ctx, dc, xf, xprev, n_sweeps, alpha, net, s);
         // the network reads x^F_f with a halo: write the result to the workspace copy
-        e = launch_net_prolong(p, dc, xf, W, net, mode == MENKF_PROLONG_LEARNED_FALLBACK, ctx->ws, s);
+        e = launch_net_prolong(p, dc, xf, W, net, 0, info, nullptr, s);
         src = W;
-        if (mode == MENKF_PROLONG_LEARNED) n_sweeps = 0;
+        n_sweeps = 0;
     }
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth");
     for (int k = 0; k < n_sweeps; ++k) {

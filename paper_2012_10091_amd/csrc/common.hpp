@@ -179,7 +179,16 @@ struct Plan {
     // its Linv scratch, and the chunked partial Grams of Y
     int defer_ok, gchunks, gpc;
     size_t off_mg, off_mlinv, off_gpart;
+    // judge of the learned prolongation: partial sums of its distance reduction
+    size_t off_judge;
 };
+
+// Words of the learned prolongation's judge, in the workspace's status
+// block (int32 each, from byte JUDGE_WORDS of the block)
+constexpr int JUDGE_WORDS = 128;
+enum { JW_CALLS = 0, JW_STICK = 1, JW_TILES = 2, JW_SKIP_NET = 3, JW_SKIP_PLAIN = 4, JW_JUDGE = 5, JW_USE_PLAIN = 6,
+       JW_N = 8 };
+constexpr int JUDGE_BLOCKS = 512;
 
 constexpr int CHOL_NB = 64;
 
@@ -249,9 +258,19 @@ size_t diagnostics_noalloc_capacity();              // doubles the array holds
 hipError_t launch_set_word(int32_t *w, int32_t v, hipStream_t s);
 hipError_t launch_set_word64(uint64_t *w, uint64_t v, hipStream_t s);
 // learned prolongation
+// gate: the kernel does nothing when *gate != 0 (the status word, or the
+// judge's skip word); tile_count (optional) counts this call's guarded tiles
 hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, void *xout, const menkf_net *net,
-                              int fallback, void *ws, hipStream_t s);
+                              int fallback, const int32_t *gate, int32_t *tile_count, hipStream_t s);
 hipError_t launch_net_pack(const float *prm, void *wk, hipStream_t s);
+// the judge of LEARNED_FALLBACK (words jw = status block + JUDGE_WORDS)
+hipError_t launch_judge_pre(const int32_t *info, int32_t *jw, int judge_every, hipStream_t s);
+hipError_t launch_judge_mid(const int32_t *info, int32_t *jw, hipStream_t s);
+hipError_t launch_judge_decide(const Plan &p, const void *xnet, const void *xplain, const void *xf, const int32_t *info,
+                               int32_t *jw, float tol, double *judge_dev, void *ws, hipStream_t s);
+hipError_t launch_judge_select(const Plan &p, const void *xnet, const void *xplain, void *xf, const int32_t *info,
+                               const int32_t *jw, hipStream_t s);
+hipError_t launch_zero_words(int32_t *w, int n, hipStream_t s);
 hipError_t launch_net_train_step(const menkf_net_train *t, hipStream_t s);
 hipError_t launch_net_forward(const menkf_net_train *t, hipStream_t s);
 hipError_t launch_net_backward(const menkf_net_train *t, hipStream_t s);

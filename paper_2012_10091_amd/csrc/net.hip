@@ -112,6 +112,7 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
                                                        const float *__restrict__ prm, NetConst nc, int nx, int ny,
                                                        int r, int nxc, int nyc, int tiles_x, int total_tiles,
                                                        int fallback, int32_t *__restrict__ fb_count,
+                                                       int32_t *__restrict__ tile_count,
                                                        const int32_t *__restrict__ info) {
     // LDS in three regions, reused as the layers go (3 workgroups per CU):
     //   A: the input activations in0 and, after them, the coarse window of
@@ -249,7 +250,10 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
         const float nd = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
         const float nbad = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
         use_net = nbad == 0.0f && isfinite(no) && no <= nc.guard * nc.guard * nd;
-        if (!use_net && tid == 0 && fb_count) atomicAdd(fb_count, 1);
+        if (!use_net && tid == 0) {
+            if (fb_count) atomicAdd(fb_count, 1);
+            if (tile_count) atomicAdd(tile_count, 1);
+        }
     }
     if (gx < nx && gy < ny) {
         const long long g = (long long)gy * nx + gx;
@@ -259,8 +263,7 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
 }
 
 hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, void *xout, const menkf_net *net,
-                              int fallback, void *ws, hipStream_t s) {
-    const int32_t *info = (const int32_t *)((char *)ws + p.off_info);
+                              int fallback, const int32_t *gate, int32_t *tile_count, hipStream_t s) {
     NetConst nc;
     for (int i = 0; i < 8; ++i) {
         nc.in_scale[i] = net->in_scale[i];
@@ -272,7 +275,154 @@ hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, voi
     const int total = tiles_x * tiles_y;
     hipLaunchKernelGGL(net_prolong_fwd, dim3(total), dim3(256), 0, s, (const float *)dc, (const float *)xf,
                        (float *)xout, (const __bf16 *)net->wpacked, net->params, nc, p.nx, p.ny, p.cfg.ratio, p.nxc,
-                       p.nyc, tiles_x, total, fallback, net->fallback_count_dev, info);
+                       p.nyc, tiles_x, total, fallback, net->fallback_count_dev, tile_count, gate);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- judge
+// The plain correction (Pi_F and the relaxed sweeps) judges the network's
+// and replaces it when the network strays: a few single-thread kernels
+// keep the decision on the device, so a captured cycle replays it.
+//   pre:    count the call; judged call when calls % judge_every == 0;
+//           skip the network when the plain correction is kept (stick) and
+//           this call is not judged; clear the guarded-tile count
+//   mid:    the plain correction is formed when judged, kept, or a tile
+//           was guarded
+//   decide: on a judged call d = |x_net - x_plain| / |x_plain - x^F_f| in
+//           FP64 (fixed-order sums), stick = !(d <= tol); use the plain
+//           correction when stick or a tile was guarded
+//   select: x^F_a = plain or network correction
+__global__ void judge_pre_kernel(const int32_t *__restrict__ info, int32_t *__restrict__ jw, int every) {
+    const uint32_t c = (uint32_t)jw[JW_CALLS];
+    const int judge = every > 0 && (c % (uint32_t)every) == 0u;
+    jw[JW_CALLS] = (int32_t)(c + 1u);
+    jw[JW_JUDGE] = judge;
+    jw[JW_TILES] = 0;
+    jw[JW_SKIP_NET] = (*info != 0 || (jw[JW_STICK] && !judge)) ? 1 : 0;
+}
+
+__global__ void judge_mid_kernel(const int32_t *__restrict__ info, int32_t *__restrict__ jw) {
+    const int need = jw[JW_JUDGE] || jw[JW_STICK] || jw[JW_TILES] > 0;
+    jw[JW_SKIP_PLAIN] = (*info != 0 || !need) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void judge_partial(const float *__restrict__ xn, const float *__restrict__ xp,
+                                                     const float *__restrict__ xf, long long n,
+                                                     const int32_t *__restrict__ jw, double *__restrict__ part) {
+    if (jw[JW_SKIP_PLAIN] || !jw[JW_JUDGE]) return;
+    __shared__ double s0[256], s1[256];
+    double a = 0.0, b = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const double p = (double)xp[i];
+        const double d = (double)xn[i] - p, c = p - (double)xf[i];
+        a += d * d;
+        b += c * c;
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            s0[threadIdx.x] += s0[threadIdx.x + h];
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void judge_final(const double *__restrict__ part, int nblocks,
+                                                   const int32_t *__restrict__ info, int32_t *__restrict__ jw,
+                                                   float tol, double *__restrict__ stats) {
+    if (*info != 0) return;
+    const int judge = jw[JW_JUDGE];
+    __shared__ double s[2][256];
+    if (judge) {
+        double a = 0.0, b = 0.0;
+        for (int k = threadIdx.x; k < nblocks; k += 256) {
+            a += part[2 * k];
+            b += part[2 * k + 1];
+        }
+        s[0][threadIdx.x] = a;
+        s[1][threadIdx.x] = b;
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (judge && threadIdx.x < h) {
+            s[0][threadIdx.x] += s[0][threadIdx.x + h];
+            s[1][threadIdx.x] += s[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    if (judge) {
+        const double a = s[0][0], b = s[1][0];
+        const double d = b > 0.0 ? sqrt(a / b) : (a > 0.0 ? INFINITY : 0.0);
+        jw[JW_STICK] = (d <= (double)tol) ? 0 : 1;   // NaN fails the test
+        if (stats) {
+            stats[0] = d;
+            stats[1] += 1.0;
+        }
+    }
+    const int tiles = jw[JW_TILES] > 0;
+    const int use_plain = jw[JW_STICK] || tiles;
+    jw[JW_USE_PLAIN] = use_plain;
+    if (stats) {
+        stats[2] += (double)use_plain;
+        stats[3] += (double)tiles;
+    }
+}
+
+__global__ __launch_bounds__(256) void judge_select_kernel(const float *__restrict__ xn, const float *__restrict__ xp,
+                                                           float *__restrict__ xf, long long n,
+                                                           const int32_t *__restrict__ info,
+                                                           const int32_t *__restrict__ jw) {
+    if (*info != 0) return;
+    const float *src = jw[JW_USE_PLAIN] ? xp : xn;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) xf[i] = src[i];
+}
+
+__global__ void zero_words_kernel(int32_t *w, int n) {
+    if ((int)threadIdx.x < n) w[threadIdx.x] = 0;
+}
+
+hipError_t launch_judge_pre(const int32_t *info, int32_t *jw, int judge_every, hipStream_t s) {
+    hipLaunchKernelGGL(judge_pre_kernel, dim3(1), dim3(1), 0, s, info, jw, judge_every);
+    return hipGetLastError();
+}
+
+hipError_t launch_judge_mid(const int32_t *info, int32_t *jw, hipStream_t s) {
+    hipLaunchKernelGGL(judge_mid_kernel, dim3(1), dim3(1), 0, s, info, jw);
+    return hipGetLastError();
+}
+
+hipError_t launch_judge_decide(const Plan &p, const void *xnet, const void *xplain, const void *xf, const int32_t *info,
+                               int32_t *jw, float tol, double *judge_dev, void *ws, hipStream_t s) {
+    double *part = (double *)((char *)ws + p.off_judge);
+    const long long n = (long long)p.F * p.nf;
+    long long nb = (n + 255) / 256;
+    if (nb > JUDGE_BLOCKS) nb = JUDGE_BLOCKS;
+    hipLaunchKernelGGL(judge_partial, dim3((unsigned)nb), dim3(256), 0, s, (const float *)xnet, (const float *)xplain,
+                       (const float *)xf, n, (const int32_t *)jw, part);
+    hipLaunchKernelGGL(judge_final, dim3(1), dim3(256), 0, s, (const double *)part, (int)nb, info, jw, tol, judge_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_judge_select(const Plan &p, const void *xnet, const void *xplain, void *xf, const int32_t *info,
+                               const int32_t *jw, hipStream_t s) {
+    const long long n = (long long)p.F * p.nf;
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(judge_select_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const float *)xnet,
+                       (const float *)xplain, (float *)xf, n, info, jw);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(int32_t *w, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, w, n);
     return hipGetLastError();
 }
 

@@ -62,9 +62,14 @@ def save(net: B.Net, path: str, meta: dict):
              **{k: np.array(v) for k, v in meta.items()})
 
 
-def load(path: str, guard=10.0, device="cuda") -> B.Net:
+def load(path: str, guard=10.0, device="cuda", judge_every=0, judge_tol=None) -> B.Net:
+    """A committed network; judge_tol defaults to the tolerance stored with
+    the weights (1.0 when none is)."""
     z = np.load(path, allow_pickle=False)
-    return B.Net(z["params"], z["in_scale"], z["in_offset"], z["out_scale"], guard=guard, device=device)
+    if judge_tol is None:
+        judge_tol = float(z["judge_tol"]) if "judge_tol" in z.files else 1.0
+    return B.Net(z["params"], z["in_scale"], z["in_offset"], z["out_scale"], guard=guard, device=device,
+                 judge_every=judge_every, judge_tol=judge_tol)
 
 
 class Run:
@@ -108,43 +113,131 @@ class Run:
         return float(math.sqrt(d[0] / d[1]))
 
 
-def generate_pairs(cfg, n_runs, cycles_per_run, skip=2, n_sweeps=3, log=print):
-    """(dproj, xf, target) fields from plain MEnKF runs, stacked on the device."""
+def train_flops_per_crop(crop: int) -> float:
+    """Useful arithmetic of one training crop (forward, data and weight
+    gradients): the three valid convolutions on (C+4)^2, (C+2)^2 and C^2
+    output pixels, 2 flops per multiply-add, backward about twice the
+    forward (no data gradient for the input layer)."""
+    fwd = 2.0 * (9 * 8 * 32 * (crop + 4) ** 2 + 9 * 32 * 32 * (crop + 2) ** 2 + 9 * 32 * 4 * crop ** 2)
+    bwd_w = fwd
+    bwd_d = 2.0 * (9 * 32 * 32 * (crop + 2) ** 2 + 9 * 32 * 4 * crop ** 2)
+    return fwd + bwd_w + bwd_d
+
+
+def train_streamed(cfg, net: B.Net, n_pairs=20000, ring=1024, n_parallel=8, cycles_per_run=120,
+                   steps_per_pair=0.25, batch=16, crop=128, lr=1e-3, n_sweeps=3, seed=0, relative=True,
+                   log=print):
+    """Train on pairs that plain MEnKF runs generate while training goes on.
+
+    n_parallel independent runs (own seeds: truth, model and member initial
+    conditions, probes, noise) are advanced cycle by cycle; every analysis
+    gives one pair (inputs Pi_F(delta^C) and x^F_f, target the plain fine
+    correction x^F_a - x^F_f after Pi_F and n_sweeps sweeps), written into a
+    device ring buffer of `ring` pairs, so the n_pairs pairs are never
+    stored together.  A run is replaced by a fresh one after cycles_per_run
+    cycles, so the pairs cover whole assimilation runs.  Adam steps on
+    random periodic crops of the pairs in the ring are interleaved, about
+    steps_per_pair per new pair, with a cosine learning-rate decay.  With
+    relative, a pair is drawn with probability proportional to
+    1 / |target|^2, so the expected loss is the mean squared error relative
+    to each pair's own correction (the measure of the judge), and the small
+    corrections of late cycles weigh as much as the first analyses' large
+    ones.  Returns the loss history and the throughput record."""
     from synthetic import fields
-    dps, xfs, tgs = [], [], []
-    for run_i in range(n_runs):
-        rc = cfg.with_(seed=cfg.seed + 1000 * (run_i + 1))
-        run = Run(rc, fields.truth_ic(rc), fields.model_ic(rc), fields.member_ics(rc), fields.probes_for(rc),
-                  lambda c, rc=rc: fields.obs_noise(rc, c), n_sweeps=n_sweeps)
-        zero = torch.zeros_like(run.fine)
-        for c in range(cycles_per_run):
+    shape = (4, cfg.ny, cfg.nx)
+    f32 = torch.float32
+    ring = min(ring, n_pairs)
+    dp = torch.zeros((ring,) + shape, dtype=f32, device="cuda")
+    xr = torch.zeros_like(dp)
+    tg = torch.zeros_like(dp)
+    tnorm = torch.ones(ring, dtype=torch.float64, device="cuda")
+    made, filled, steps, next_seed = 0, 0, 0, 0
+    total_steps = max(1, int(round(n_pairs * steps_per_pair)))
+
+    def new_run():
+        nonlocal next_seed
+        next_seed += 1
+        rc = cfg.with_(seed=cfg.seed + 1000 * next_seed)
+        return Run(rc, fields.truth_ic(rc), fields.model_ic(rc), fields.member_ics(rc), fields.probes_for(rc),
+                   lambda c, rc=rc: fields.obs_noise(rc, c), n_sweeps=n_sweeps)
+
+    runs = [new_run() for _ in range(n_parallel)]
+    tr = B.Trainer(net, batch=batch, crop=crop, lr=lr)
+    g = np.random.default_rng(seed)
+    lr_min = lr * 0.01
+    hist = []
+    t_gen = t_train = 0.0
+    n_runs = n_parallel
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while made < n_pairs:
+        ta = time.perf_counter()
+        for i in range(len(runs)):
+            if made >= n_pairs:
+                break
+            run = runs[i]
             run.forecast_and_gain()
-            xf = run.fine.clone()
-            dproj = zero.clone()
-            run.ctx.prolong_smooth(run.dc, dproj, None, n_sweeps=0)
+            k = made % ring
+            xr[k].copy_(run.fine)
+            dp[k].zero_()
+            run.ctx.prolong_smooth(run.dc, dp[k], None, n_sweeps=0)
             run.correct(B.MENKF_PROLONG_PLAIN)
-            if c >= skip:
-                dps.append(dproj)
-                xfs.append(xf)
-                tgs.append(run.fine - xf)
-        if run.ctx.get_status() != 0:
-            raise RuntimeError("analysis failed while generating pairs")
-        log(f"pairs: run {run_i + 1}/{n_runs} done, rmse {run.velocity_rmse():.4f}")
-    return (torch.stack(dps).contiguous(), torch.stack(xfs).contiguous(), torch.stack(tgs).contiguous())
+            torch.sub(run.fine, xr[k], out=tg[k])
+            tnorm[k] = torch.linalg.vector_norm(tg[k].double())
+            made += 1
+            filled = min(filled + 1, ring)
+            if run.cycle >= cycles_per_run:
+                if run.ctx.get_status() != 0:
+                    raise RuntimeError("analysis failed while generating pairs")
+                runs[i] = new_run()
+                n_runs += 1
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        t_gen += tb - ta
+        if relative:
+            w = 1.0 / np.maximum(tnorm[:filled].cpu().numpy(), 1e-30) ** 2
+            w /= w.sum()
+        while steps < total_steps * made / n_pairs:
+            tr.lr = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * steps / total_steps))
+            pick = g.choice(filled, batch, p=w) if relative else g.integers(0, filled, batch)
+            crops = np.stack([pick, g.integers(0, cfg.ny, batch), g.integers(0, cfg.nx, batch)], axis=1)
+            loss = tr.step(dp, xr, tg, torch.as_tensor(crops.astype(np.int32), device="cuda"))
+            if steps % 250 == 0 or steps == total_steps - 1:
+                hist.append((steps, float(loss.item())))
+                log(f"train: pairs {made} step {steps} loss {hist[-1][1]:.4e}")
+            steps += 1
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - tb
+    wall = time.perf_counter() - t0
+    fl = train_flops_per_crop(crop) * batch * steps
+    rec = {"pairs": made, "runs": n_runs, "ring": ring, "adam_steps": steps, "batch": batch, "crop": crop,
+           "relative_sampling": int(relative),
+           "wall_s": wall, "generation_s": t_gen, "training_s": t_train,
+           "pairs_per_s": made / t_gen, "adam_steps_per_s": steps / t_train,
+           "training_crops_per_s": steps * batch / t_train, "training_tflops": fl / t_train / 1e12,
+           "workload": cfg.name}
+    log(f"train: {rec}")
+    return hist, rec
 
 
-def evaluate(cfg, net: B.Net, n_cycles=40, seed_offset=9000, n_sweeps=3, log=print):
+def evaluate(cfg, net: B.Net, n_cycles=100, seed_offset=9000, n_sweeps=3, judge_every=10, log=print):
     """Held-out runs (unseen seeds) of the plain and the learned MEnKF.
 
-    Returns the second-half mean velocity RMSE of both runs and, on the
-    plain run, how far the learned and the sweep-free (Pi_F only)
-    corrections are from the plain correction (relative L2, averaged)."""
+    The learned run uses LEARNED_FALLBACK with the judge (every judge_every
+    cycles the plain correction is formed and compared).  Returns the
+    second-half mean velocity RMSE of both runs, and on the plain run the
+    distance of the network's and of the sweep-free (Pi_F only) corrections
+    to the plain correction (relative L2, mean and the values at every
+    tenth cycle), the conservativity indicator Gamma (Sec. 6) of the three,
+    and the learned run's judge counts."""
     from synthetic import fields
     rc = cfg.with_(seed=cfg.seed + seed_offset)
     args = (rc, fields.truth_ic(rc), fields.model_ic(rc), fields.member_ics(rc), fields.probes_for(rc),
             lambda c: fields.obs_noise(rc, c))
     plain = Run(*args, n_sweeps=n_sweeps)
     learned = Run(*args, n_sweeps=n_sweeps)
+    net.judge_stats.zero_()
+    every, net.judge_every = net.judge_every, judge_every
     rm_p, rm_l, d_net, d_pif = [], [], [], []
     gam = {"plain": [], "learned": [], "pif": []}
     res_buf = torch.empty_like(plain.fine)
@@ -163,7 +256,8 @@ def evaluate(cfg, net: B.Net, n_cycles=40, seed_offset=9000, n_sweeps=3, log=pri
         nn = xf.clone()
         plain.ctx.prolong_smooth(plain.dc, nn, None, n_sweeps=0, mode=B.MENKF_PROLONG_LEARNED, net=net)
         plain.correct(B.MENKF_PROLONG_PLAIN)
-        learned.correct(B.MENKF_PROLONG_LEARNED, net=net)
+        learned.ctx.prolong_smooth(learned.dc, learned.fine, learned.prev, n_sweeps=n_sweeps, alpha=0.5,
+                                   mode=B.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
         ref = plain.fine - xf
         nrm = torch.linalg.vector_norm(ref)
         d_net.append(float(torch.linalg.vector_norm(nn - plain.fine) / nrm))
@@ -173,31 +267,19 @@ def evaluate(cfg, net: B.Net, n_cycles=40, seed_offset=9000, n_sweeps=3, log=pri
         gam["pif"].append(gamma_rms(pif, plain.prev))
         rm_p.append(plain.velocity_rmse())
         rm_l.append(learned.velocity_rmse())
+    net.judge_every = every
+    st = net.judge_stats.cpu().numpy()
     half = n_cycles // 2
     res = {"plain_rmse": float(np.mean(rm_p[half:])), "learned_rmse": float(np.mean(rm_l[half:])),
-           "net_vs_plain_correction": float(np.mean(d_net)), "pif_vs_plain_correction": float(np.mean(d_pif)),
+           "net_vs_plain_correction": float(np.mean(d_net)),
+           "net_vs_plain_correction_every_10": [round(v, 4) for v in d_net[9::10]],
+           "pif_vs_plain_correction": float(np.mean(d_pif)),
            "gamma_plain": float(np.mean(gam["plain"])), "gamma_learned": float(np.mean(gam["learned"])),
-           "gamma_pif": float(np.mean(gam["pif"])), "cycles": n_cycles}
+           "gamma_pif": float(np.mean(gam["pif"])), "cycles": n_cycles,
+           "judged": int(st[1]), "plain_corrected_cycles": int(st[2]), "guarded_cycles": int(st[3])}
     res["ratio"] = res["learned_rmse"] / res["plain_rmse"]
     log(f"evaluate: {res}")
     return res
-
-
-def train(net: B.Net, pairs, steps, batch=16, crop=128, lr=1e-3, seed=0, log=print):
-    dproj, xf, target = pairs
-    P, _, H, W = dproj.shape
-    tr = B.Trainer(net, batch=batch, crop=crop, lr=lr)
-    g = np.random.default_rng(seed)
-    hist = []
-    lr_min = lr * 0.01
-    for s in range(steps):
-        tr.lr = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * s / steps))   # cosine decay
-        crops = np.stack([g.integers(0, P, batch), g.integers(0, H, batch), g.integers(0, W, batch)], axis=1)
-        loss = tr.step(dproj, xf, target, torch.as_tensor(crops.astype(np.int32), device="cuda"))
-        if s % 100 == 0 or s == steps - 1:
-            hist.append((s, float(loss.item())))
-            log(f"train: step {s} loss {hist[-1][1]:.4e}")
-    return hist
 
 
 def main(argv=None):
@@ -205,31 +287,34 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="C4", choices=["C3", "C4"])
     ap.add_argument("--out", default=None)
-    ap.add_argument("--runs", type=int, default=4)
-    ap.add_argument("--cycles", type=int, default=34)
-    ap.add_argument("--eval-cycles", type=int, default=40)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--pairs", type=int, default=20000)
+    ap.add_argument("--ring", type=int, default=1024)
+    ap.add_argument("--parallel", type=int, default=8)
+    ap.add_argument("--cycles-per-run", type=int, default=120)
+    ap.add_argument("--steps-per-pair", type=float, default=0.25)
+    ap.add_argument("--eval-cycles", type=int, default=100)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--crop", type=int, default=128)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--judge-tol", type=float, default=1.0)
+    ap.add_argument("--uniform", action="store_true", help="draw pairs uniformly instead of by 1/|target|^2")
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     cfg = configs.CONFIGS[args.workload]
     out = args.out or weights_for(cfg.name)
-    t0 = time.perf_counter()
-    pairs = generate_pairs(cfg, args.runs, args.cycles, log=log)
-    log(f"pairs: {pairs[0].shape[0]} fields of {tuple(pairs[0].shape[1:])} in {time.perf_counter() - t0:.1f}s")
     s, o, os_ = default_scaling(cfg.gamma, cfg.mach)
-    net = B.Net(init_params(seed=cfg.seed), s, o, os_)
-    t1 = time.perf_counter()
-    hist = train(net, pairs, args.steps, args.batch, args.crop, args.lr, log=log)
-    torch.cuda.synchronize()
-    log(f"train: {args.steps} steps x {args.batch} crops of {args.crop}^2 in {time.perf_counter() - t1:.1f}s")
-    del pairs
+    net = B.Net(init_params(seed=cfg.seed), s, o, os_, judge_tol=args.judge_tol)
+    hist, rec = train_streamed(cfg, net, n_pairs=args.pairs, ring=args.ring, n_parallel=args.parallel,
+                               cycles_per_run=args.cycles_per_run, steps_per_pair=args.steps_per_pair,
+                               batch=args.batch, crop=args.crop, lr=args.lr, relative=not args.uniform, log=log)
+    torch.cuda.empty_cache()
     ev = evaluate(cfg, net, n_cycles=args.eval_cycles, log=log)
-    save(net, out, {"loss_history": np.array(hist), "pairs": args.runs * (args.cycles - 2),
-                    "crop_samples": args.steps * args.batch, "workload": cfg.name,
-                    **{f"eval_{k}": v for k, v in ev.items()}})
+    meta = {"loss_history": np.array(hist), "pairs": rec["pairs"], "runs": rec["runs"],
+            "cycles_per_run": args.cycles_per_run, "adam_steps": rec["adam_steps"],
+            "crop_samples": rec["adam_steps"] * args.batch, "workload": cfg.name, "judge_tol": args.judge_tol,
+            **{f"train_{k}": v for k, v in rec.items() if isinstance(v, (int, float))},
+            **{f"eval_{k}": v for k, v in ev.items()}}
+    save(net, out, meta)
     log(f"saved {out}")
 
 

@@ -98,6 +98,59 @@ def test_fallback_guard_restores_plain_path():
     np.testing.assert_array_equal(to_np(c), to_np(d))
 
 
+def test_judge_distance_decision_and_stickiness():
+    """LEARNED_FALLBACK with the judge: the device's distance
+    |x_net - x_plain| / |x_plain - x^F_f| against the oracle's network and
+    plain corrections (BF16 network tolerance), the network kept below the
+    tolerance (bitwise = LEARNED), the plain correction above it (bitwise =
+    PLAIN) and kept on the unjudged calls that follow, until a judged call
+    accepts the network again."""
+    import paper_2012_10091_amd as m
+    from oracle import smooth
+    from oracle.models import Model
+    cfg = configs.tiny_2d()
+    p = _params(cfg)
+    dc, xf = _inputs(cfg)
+    xprev = fields.truth_ic(cfg.with_(seed=cfg.seed + 3)).astype(np.float32).astype(np.float64)
+    ns = 2
+    dproj = grids.prolong(dc, cfg.ratio, 2)
+    x_net = xf + onet.learned_correction(p, dproj, xf)
+    x_pl = smooth.smooth(xf + dproj, xprev, Model(cfg, "fine"), ns, 0.5)
+    d_o = np.linalg.norm(x_net - x_pl) / np.linalg.norm(x_pl - xf)
+    dcd, xp = to_dev(dc, F32), to_dev(xprev, F32)
+    ctx, _, _ = make_ctx(cfg)
+    gnet = _gpu_net(p)
+    gnet.judge_every, gnet.judge_tol = 1, 1e30
+    say(f"judge: oracle distance {d_o:.4f}")
+    a = to_dev(xf, F32)
+    ctx.prolong_smooth(dcd, a, xp, n_sweeps=ns, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=gnet)
+    st = to_np(gnet.judge_stats)
+    assert abs(st[0] - d_o) < 5e-2 * d_o, (st[0], d_o)
+    assert list(st[1:]) == [1, 0, 0]
+    b = to_dev(xf, F32)
+    ctx.prolong_smooth(dcd, b, None, n_sweeps=0, mode=m.MENKF_PROLONG_LEARNED, net=gnet)
+    np.testing.assert_array_equal(to_np(a), to_np(b))
+    plain = to_dev(xf, F32)
+    ctx.prolong_smooth(dcd, plain, xp, n_sweeps=ns, mode=m.MENKF_PROLONG_PLAIN)
+    # a fresh context (judge state reset): judged every second call, tolerance below the distance
+    ctx2, _, _ = make_ctx(cfg)
+    g2 = _gpu_net(p)
+    g2.judge_every, g2.judge_tol = 2, 0.5 * float(st[0])
+    outs = []
+    for k in range(3):
+        if k == 2:
+            g2.judge_tol = 1e30                  # the third call (judged) accepts the network
+        c = to_dev(xf, F32)
+        ctx2.prolong_smooth(dcd, c, xp, n_sweeps=ns, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=g2)
+        outs.append(to_np(c))
+    np.testing.assert_array_equal(outs[0], to_np(plain))      # judged, rejected
+    np.testing.assert_array_equal(outs[1], to_np(plain))      # not judged, plain kept
+    np.testing.assert_array_equal(outs[2], to_np(b))          # judged, accepted
+    st2 = to_np(g2.judge_stats)
+    assert list(st2[1:]) == [2, 2, 0]
+    assert ctx2.get_status() == 0
+
+
 def _train_case(seed=3):
     cfg = configs.tiny_2d(nx=32, ny=32)
     r = np.random.default_rng(seed)
