@@ -70,6 +70,7 @@ enum { MENKF_F32 = 0, MENKF_F64 = 1 };                 /* precision */
 enum { MENKF_GAIN_EXACT_R = 0, MENKF_GAIN_SAMPLE_EE = 1, MENKF_GAIN_ENSEMBLE_SPACE = 2 };
 enum { MENKF_FINE = 0, MENKF_COARSE = 1 };             /* grid level */
 enum { MENKF_PROLONG_PLAIN = 0, MENKF_PROLONG_LEARNED = 1, MENKF_PROLONG_LEARNED_FALLBACK = 2 };
+enum { MENKF_TIME_SSPRK3 = 0, MENKF_TIME_FIRST_ORDER = 1 };   /* time scheme (inlet-forced Burgers) */
 
 /*
  * Configuration of one assimilation instance.
@@ -146,6 +147,17 @@ typedef struct {
     double theta_sigma[2];
     /* MENKF_EULER1D_INLET only: strength of the explicit filter, in [0, 1]. */
     double filter_sigma;
+    /* MENKF_BURGERS1D_INLET: MENKF_TIME_SSPRK3 (0, the default: three-stage
+     * SSP Runge-Kutta) or MENKF_TIME_FIRST_ORDER, the paper's first-order
+     * scheme (Sec. 4; implementation notes after Algo. 4): forward-Euler
+     * steps, and the last step of every forecast call (the analysis step)
+     * as a single Jacobi iteration of the implicit-Euler system
+     * x_k - dt L(x_k) = x_{k-1} started from x_{k-1}, the convective
+     * coefficient frozen there: x_k = x_{k-1} + dt / D L(x_{k-1}),
+     * D = 1 + 2 nu dt / h^2 (centred convection has a zero diagonal).  The
+     * inlet value is imposed at t_k and the outlet extrapolated after
+     * every step.  Other models take 0 only. */
+    int32_t time_scheme;
 } menkf_config;
 
 /* Create / destroy a context for the current HIP device.  The context owns

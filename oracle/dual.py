@@ -17,6 +17,17 @@ Readings (the paper leaves them open):
   workloads' explicit scheme); the inlet node takes the Dirichlet value of
   each Runge-Kutta stage at that stage's time (t + dt, t + dt/2, t + dt),
   the outlet node the linear extrapolation 2 u_{n-2} - u_{n-3}.
+* the paper's own first-order scheme (time_scheme "first_order"; Sec. 4
+  and the implementation notes after Algo. 4): explicit (forward-Euler)
+  steps between analyses, and at the analysis step, the last of a
+  forecast window, a single iteration of a matrix splitting of the
+  implicit-Euler system Psi x_k = x_{k-1}, Psi x = x - dt L_{x^0}(x) with
+  the convective coefficient frozen at the starting iterate x^0 = x_{k-1}.
+  Reading: the splitting is Jacobi, D = diag Psi = 1 + 2 nu dt / h^2 (the
+  centred convection has a zero diagonal), no relaxation (the paper names
+  a relaxation coefficient only for the final fine-grid iteration), so the
+  step is x_k = x_{k-1} + D^-1 dt L(x_{k-1}) at the interior nodes, with the
+  inlet value at t_k and the outlet extrapolated as in the other steps.
 * Pi_F on the open grid: the cubic Lagrange interpolant through the four
   coarse nodes b..b+3 with b = min(max(j - 1, 0), n_c - 4) for the fine
   node r j + m (one-sided near both ends, including the r - 1 fine nodes
@@ -87,6 +98,8 @@ def model_forecast(cfg, x, t0, nsteps, theta, level):
     if getattr(cfg, "eq", "burgers") == "euler":
         from . import euler1d
         return euler1d.forecast(x, t0, nsteps, cfg.dt, theta, h, cfg.gamma, cfg.mach, cfg.omega, cfg.filter_sigma)
+    if getattr(cfg, "time_scheme", "ssprk3") == "first_order":
+        return inlet_forecast_first_order(x, t0, nsteps, cfg.dt, theta, cfg.nu, h, cfg.u0, cfg.omega)
     return inlet_forecast(x, t0, nsteps, cfg.dt, theta, cfg.nu, h, cfg.u0, cfg.omega)
 
 
@@ -135,6 +148,31 @@ def inlet_forecast(u, t0, nsteps, dt, theta, nu, h, u0, omega):
     for s in range(nsteps):
         prev = u
         u = inlet_step(u, t0 + s * dt, dt, th, nu, h, u0, omega)
+    return u[..., None, :], prev[..., None, :]
+
+
+def jacobi_diagonal(dt, nu, h):
+    """Diagonal of Psi = I - dt L at an interior node: the centred second
+    difference contributes 2 nu dt / h^2, the centred convection nothing."""
+    return 1.0 + 2.0 * nu * dt / (h * h)
+
+
+def inlet_forecast_first_order(u, t0, nsteps, dt, theta, nu, h, u0, omega):
+    """The paper's first-order scheme over one forecast window: nsteps - 1
+    forward-Euler steps, then the analysis step as one Jacobi iteration of
+    the implicit-Euler system started from x_{k-1}.  Returns (final state,
+    state one step earlier), shapes as inlet_forecast."""
+    u = np.asarray(u, dtype=np.float64)[..., 0, :].copy()
+    th = np.asarray(theta, dtype=np.float64)
+    D = jacobi_diagonal(dt, nu, h)
+    prev = u.copy()
+    for s in range(nsteps):
+        prev = u
+        g = inlet_value(t0 + (s + 1) * dt, th, u0, omega)
+        if s < nsteps - 1:
+            u = _with_bc(u + dt * _rhs(u, nu, h), g)                 # explicit step
+        else:
+            u = _with_bc(u + (dt / D) * _rhs(u, nu, h), g)           # x^1 = x^0 + D^-1 (c - Psi x^0), x^0 = c
     return u[..., None, :], prev[..., None, :]
 
 

@@ -32,6 +32,7 @@ class MenkfConfig(ctypes.Structure):
         ("u0", c_double), ("omega", c_double),
         ("theta_sigma", c_double * 2),
         ("filter_sigma", c_double),
+        ("time_scheme", c_int32),
     ]
 
 

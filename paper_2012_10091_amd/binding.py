@@ -28,6 +28,8 @@ MENKF_COARSE = 1
 MENKF_PROLONG_PLAIN = 0
 MENKF_PROLONG_LEARNED = 1
 MENKF_PROLONG_LEARNED_FALLBACK = 2
+MENKF_TIME_SSPRK3 = 0
+MENKF_TIME_FIRST_ORDER = 1
 MENKF_CYCLE_DEVICE = (1 << 64) - 1
 
 STATUS = {0: "MENKF_OK", -1: "MENKF_E_ARG", -2: "MENKF_E_SHAPE", -3: "MENKF_E_NOT_SPD",
@@ -53,10 +55,10 @@ def _stream(stream=None):
 def make_config(model, nx, ny, ratio, n_members, n_probes, dt, precision=MENKF_F32,
                 gain_mode=MENKF_GAIN_EXACT_R, length=6.283185307179586, nu=0.0, gamma=1.4,
                 mach=0.3, reynolds=1000.0, prandtl=0.71, obs_sigma=0.01, anomaly_terms=0, u0=1.0, omega=0.0,
-                theta_sigma=(0.0, 0.0), filter_sigma=0.0) -> _lib.MenkfConfig:
+                theta_sigma=(0.0, 0.0), filter_sigma=0.0, time_scheme=0) -> _lib.MenkfConfig:
     return _lib.MenkfConfig(model, precision, gain_mode, nx, ny, ratio, n_members, n_probes,
                             length, dt, nu, gamma, mach, reynolds, prandtl, obs_sigma, anomaly_terms,
-                            u0, omega, (ctypes.c_double * 2)(*theta_sigma), filter_sigma)
+                            u0, omega, (ctypes.c_double * 2)(*theta_sigma), filter_sigma, time_scheme)
 
 
 def config_from(cfg) -> _lib.MenkfConfig:
@@ -75,7 +77,9 @@ def config_from(cfg) -> _lib.MenkfConfig:
         gamma=cfg.gamma, mach=cfg.mach, reynolds=cfg.reynolds, prandtl=cfg.prandtl,
         obs_sigma=cfg.obs_sigma, anomaly_terms=getattr(cfg, "anomaly_terms", 0),
         u0=getattr(cfg, "u0", 1.0), omega=getattr(cfg, "omega", 0.0),
-        theta_sigma=tuple(getattr(cfg, "theta_walk", (0.0, 0.0))), filter_sigma=getattr(cfg, "filter_sigma", 0.0))
+        theta_sigma=tuple(getattr(cfg, "theta_walk", (0.0, 0.0))), filter_sigma=getattr(cfg, "filter_sigma", 0.0),
+        time_scheme=MENKF_TIME_FIRST_ORDER if getattr(cfg, "time_scheme", "ssprk3") == "first_order"
+        else MENKF_TIME_SSPRK3)
 
 
 def ram_ratio(dim: int, ratio: int, n_members: int) -> float:

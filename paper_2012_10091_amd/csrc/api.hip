@@ -134,6 +134,11 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
         return fail(nullptr, MENKF_E_ARG,
                     "MENKF_GAIN_SAMPLE_EE: Y Y^T + E E^T has rank <= 2(N-1) = %d < n_probes = %d (singular)",
                     2 * cfg->n_members - 2, cfg->n_probes);
+    if (cfg->time_scheme != MENKF_TIME_SSPRK3 && cfg->time_scheme != MENKF_TIME_FIRST_ORDER)
+        return fail(nullptr, MENKF_E_ARG, "time_scheme must be MENKF_TIME_SSPRK3 or MENKF_TIME_FIRST_ORDER (got %d)",
+                    cfg->time_scheme);
+    if (cfg->time_scheme == MENKF_TIME_FIRST_ORDER && cfg->model != MENKF_BURGERS1D_INLET)
+        return fail(nullptr, MENKF_E_UNSUPPORTED, "MENKF_TIME_FIRST_ORDER is built for MENKF_BURGERS1D_INLET");
     if (cfg->anomaly_terms != 0 && cfg->anomaly_terms != 1 && cfg->anomaly_terms != 3)
         return fail(nullptr, MENKF_E_ARG, "anomaly_terms must be 0, 1 or 3 (got %d)", cfg->anomaly_terms);
     if (cfg->anomaly_terms == 0) p->cfg.anomaly_terms = 3;

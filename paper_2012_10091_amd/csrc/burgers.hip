@@ -181,10 +181,15 @@ __device__ __forceinline__ void inlet_stage(const T *__restrict__ U, const T *__
     }
 }
 
-template <typename T, int PPT>
+// SCHEME 0: three-stage SSP-RK3 steps.  SCHEME 1: the paper's first-order
+// scheme: forward-Euler steps, and the window's last step (the analysis
+// step) as one Jacobi iteration of the implicit-Euler system from x_{k-1},
+// x_k = x_{k-1} + (dt / D) L(x_{k-1}), D = 1 + 2 nu dt / h^2 (coefficients
+// cj, whose dt is dt / D).
+template <typename T, int PPT, int SCHEME>
 __global__ __launch_bounds__(1024) void burgers_inlet_window(T *__restrict__ state, T *__restrict__ prev, int n,
-                                                             int nsteps, BurgersCoef<T> c, InletCoef<T> ic,
-                                                             const double *__restrict__ theta,
+                                                             int nsteps, BurgersCoef<T> c, BurgersCoef<T> cj,
+                                                             InletCoef<T> ic, const double *__restrict__ theta,
                                                              const double *__restrict__ t0p) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *G = reinterpret_cast<T *>(smem_raw);   // [INLET_GCH][2]: g(t + dt), g(t + dt/2)
@@ -220,12 +225,17 @@ __global__ __launch_bounds__(1024) void burgers_inlet_window(T *__restrict__ sta
                 }
             }
             const T g1 = G[2 * j], g2 = G[2 * j + 1];
-            inlet_stage<1, PPT>(U, U, A, n, g1, c);
-            __syncthreads();
-            inlet_stage<2, PPT>(U, A, B, n, g2, c);
-            __syncthreads();
-            inlet_stage<3, PPT>(U, B, A, n, g1, c);   // the new state, into A
-            __syncthreads();
+            if (SCHEME == 1) {
+                inlet_stage<1, PPT>(U, U, A, n, g1, step == nsteps - 1 ? cj : c);   // the new state, into A
+                __syncthreads();
+            } else {
+                inlet_stage<1, PPT>(U, U, A, n, g1, c);
+                __syncthreads();
+                inlet_stage<2, PPT>(U, A, B, n, g2, c);
+                __syncthreads();
+                inlet_stage<3, PPT>(U, B, A, n, g1, c);   // the new state, into A
+                __syncthreads();
+            }
             T *t = U;
             U = A;
             A = t;
@@ -324,13 +334,14 @@ static hipError_t burgers_forecast_t(const Plan &p, int level, T *state, int nb,
 size_t inlet_window_lds(int n, size_t tsize) { return (2 * (size_t)INLET_GCH + 3 * (size_t)n) * tsize; }
 
 template <typename T, int PPT>
-static hipError_t launch_inlet(T *state, T *prev, int n, int nb, int nsteps, BurgersCoef<T> c, InletCoef<T> ic,
-                               const double *theta, const double *t0, int bs, hipStream_t s) {
+static hipError_t launch_inlet(T *state, T *prev, int n, int nb, int nsteps, BurgersCoef<T> c, BurgersCoef<T> cj,
+                               InletCoef<T> ic, int scheme, const double *theta, const double *t0, int bs,
+                               hipStream_t s) {
     const size_t lds = inlet_window_lds(n, sizeof(T));
-    auto kern = burgers_inlet_window<T, PPT>;
+    auto kern = scheme == MENKF_TIME_FIRST_ORDER ? burgers_inlet_window<T, PPT, 1> : burgers_inlet_window<T, PPT, 0>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, s, state, prev, n, nsteps, c, ic, theta, t0);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(bs), lds, s, state, prev, n, nsteps, c, cj, ic, theta, t0);
     return hipGetLastError();
 }
 
@@ -339,14 +350,20 @@ static hipError_t inlet_forecast_t(const Plan &p, int level, T *state, int nb, i
                                    const double *theta, const double *t0, hipStream_t s) {
     const int n = level == MENKF_FINE ? p.nx : p.nxc;
     const BurgersCoef<T> c = make_coef<T>(p, level);
+    // the Jacobi iteration of the analysis step: dt scaled by 1/D, D the
+    // diagonal 1 + 2 nu dt / h^2 of the implicit-Euler matrix on this level
+    BurgersCoef<T> cj = c;
+    const double h = p.cfg.length / n;
+    cj.dt = (T)(p.cfg.dt / (1.0 + 2.0 * p.cfg.nu * p.cfg.dt / (h * h)));
+    const int sch = p.cfg.time_scheme;
     const InletCoef<T> ic{p.cfg.u0, p.cfg.omega, p.cfg.dt};
     int bs = 64;
     while (bs < 1024 && bs < n) bs *= 2;
     const int ppt = (n + bs - 1) / bs;
-    if (ppt <= 1) return launch_inlet<T, 1>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
-    if (ppt <= 2) return launch_inlet<T, 2>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
-    if (ppt <= 4) return launch_inlet<T, 4>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
-    if (ppt <= 8) return launch_inlet<T, 8>(state, prev, n, nb, nsteps, c, ic, theta, t0, bs, s);
+    if (ppt <= 1) return launch_inlet<T, 1>(state, prev, n, nb, nsteps, c, cj, ic, sch, theta, t0, bs, s);
+    if (ppt <= 2) return launch_inlet<T, 2>(state, prev, n, nb, nsteps, c, cj, ic, sch, theta, t0, bs, s);
+    if (ppt <= 4) return launch_inlet<T, 4>(state, prev, n, nb, nsteps, c, cj, ic, sch, theta, t0, bs, s);
+    if (ppt <= 8) return launch_inlet<T, 8>(state, prev, n, nb, nsteps, c, cj, ic, sch, theta, t0, bs, s);
     return hipErrorInvalidValue;   // rows this long are rejected when the context is created
 }
 

@@ -53,6 +53,8 @@ class Config:
     # 1D equations: "burgers" or "euler" (inviscid 1D Euler, acoustic case)
     eq: str = "burgers"
     filter_sigma: float = 1.0      # strength of the explicit filter (Euler case)
+    # inlet-forced Burgers: "ssprk3" or "first_order" (the paper's scheme)
+    time_scheme: str = "ssprk3"
     theta_b: float = 10.0          # truth amplitude theta0 (1 + sin(omega t / b)) (Euler case)
 
     @property

@@ -127,3 +127,97 @@ def test_correction_keeps_the_inlet_and_sweeps_solve_the_implicit_system():
     assert np.abs(r[0, 1:-1]).max() < 1e-13
     assert y[0, 0] == x[0, 0]
     assert y[0, -1] == 2.0 * y[0, -2] - y[0, -3]
+
+
+# ------------------------------------------------------------------ the paper's first-order scheme
+def _psi_matrix(u0, dt, nu, h):
+    """Psi = I - dt L_{u0} of the implicit-Euler step at the interior nodes,
+    with the convective coefficient frozen at u0, written out densely:
+    (Psi x)_i = x_i - dt (-u0_i (x_{i+1} - x_{i-1}) / 2h + nu (x_{i+1} - 2 x_i + x_{i-1}) / h^2)."""
+    n = u0.shape[-1]
+    P = np.eye(n)
+    for i in range(1, n - 1):
+        P[i, i - 1] += -dt * (u0[i] / (2 * h) + nu / h ** 2)
+        P[i, i] += dt * 2 * nu / h ** 2
+        P[i, i + 1] += -dt * (-u0[i] / (2 * h) + nu / h ** 2)
+    return P
+
+
+def test_first_order_analysis_step_is_one_jacobi_iteration():
+    """The last step of a first-order window is x^1 = x^0 + diag(Psi)^-1 (c - Psi x^0)
+    at the interior nodes, with c = x^0 = x_{k-1}, the inlet value at t_k and
+    the outlet extrapolated; the steps before it are forward Euler."""
+    n, dt, nu, h, u0, om = 14, 2e-3, 0.02, 0.1, 1.0, 2 * np.pi
+    th = np.array([0.3, 0.4])
+    x0 = 1.0 + 0.2 * np.sin(np.arange(n) * 0.7)
+    x0[0] = dual.inlet_value(0.0, th, u0, om)
+    out, prev = dual.inlet_forecast_first_order(x0[None], 0.0, 1, dt, th, nu, h, u0, om)
+    P = _psi_matrix(x0, dt, nu, h)
+    jac = x0 + (x0 - P @ x0) / np.diag(P)
+    np.testing.assert_allclose(out[0, 1:-1], jac[1:-1], rtol=0, atol=1e-14)
+    assert out[0, 0] == dual.inlet_value(dt, th, u0, om)
+    assert out[0, -1] == 2 * out[0, -2] - out[0, -3]
+    np.testing.assert_array_equal(prev[0], x0)
+    # two steps: a forward-Euler step (L from the explicit definition) then the Jacobi step
+    out2, prev2 = dual.inlet_forecast_first_order(x0[None], 0.0, 2, dt, th, nu, h, u0, om)
+    fe = x0 - (P - np.eye(n)) @ x0                                 # x0 + dt L x0 = x0 - (Psi - I) x0
+    fe[0] = dual.inlet_value(dt, th, u0, om)
+    fe[-1] = 2 * fe[-2] - fe[-3]
+    np.testing.assert_allclose(prev2[0], fe, rtol=0, atol=1e-14)
+    P2 = _psi_matrix(fe, dt, nu, h)
+    jac2 = fe + (fe - P2 @ fe) / np.diag(P2)
+    np.testing.assert_allclose(out2[0, 1:-1], jac2[1:-1], rtol=0, atol=1e-14)
+
+
+def test_jacobi_iterated_solves_the_implicit_step():
+    """Repeating the splitting (coefficients re-frozen at each iterate)
+    converges to the solution of the nonlinear implicit-Euler step, which a
+    dense Newton solve of x - dt L(x) = c finds independently: the single
+    iteration the scheme takes is the first of a convergent sequence."""
+    n, dt, nu, h = 16, 5e-3, 0.05, 0.1
+    c = 1.0 + 0.3 * np.cos(np.arange(n) * 0.5)
+    x = c.copy()
+    for _ in range(200):
+        P = _psi_matrix(x, dt, nu, h)
+        x[1:-1] = (x + (c - P @ x) / np.diag(P))[1:-1]
+    z = c.copy()
+    for _ in range(30):                        # Newton on the interior nodes, boundary values fixed at c
+        F = z - c
+        F[1:-1] = z[1:-1] - dt * (-z[1:-1] * (z[2:] - z[:-2]) / (2 * h) + nu * (z[2:] - 2 * z[1:-1] + z[:-2]) / h ** 2) - c[1:-1]
+        J = np.eye(n)
+        for i in range(1, n - 1):
+            J[i, i - 1] = -dt * (z[i] / (2 * h) + nu / h ** 2)
+            J[i, i] = 1 + dt * ((z[i + 1] - z[i - 1]) / (2 * h) + 2 * nu / h ** 2)
+            J[i, i + 1] = -dt * (-z[i] / (2 * h) + nu / h ** 2)
+        z = z - np.linalg.solve(J, F)
+    np.testing.assert_allclose(x, z, rtol=0, atol=1e-12)
+
+
+def test_first_order_scheme_converges_at_first_order_in_time():
+    """The explicit steps of the first-order scheme: halving dt halves the
+    error at a fixed time against a much finer step (one Jacobi step at
+    the end of each window of 10 steps)."""
+    L, n, nu, u0, om = 10.0, 200, 0.02, 1.0, 2 * np.pi
+    th = np.array([0.2, 0.0])
+    T = 0.4
+
+    def run(dt):
+        u = np.full((1, 1, n), u0)
+        t = 0.0
+        steps = int(round(T / dt))
+        for w in range(steps // 10):
+            u, _ = dual.inlet_forecast_first_order(u, t, 10, dt, th, nu, L / n, u0, om)
+            t += 10 * dt
+        return u[0, 0]
+    ref = run(2.5e-5)
+    e = [np.abs(run(dt) - ref).max() for dt in (1e-3, 5e-4, 2.5e-4)]
+    orders = [np.log2(e[i] / e[i + 1]) for i in range(2)]
+    assert all(0.85 < o < 1.25 for o in orders), (e, orders)
+
+
+def test_first_order_uniform_flow_is_steady():
+    cfg = configs.inlet_burgers(nx=200, time_scheme="first_order")
+    u = fields.inlet_uniform(cfg)
+    out, prev = dual.inlet_forecast_first_order(u, 0.0, 30, cfg.dt, np.array([0.0, 0.7]), cfg.nu,
+                                                cfg.length / cfg.nx, cfg.u0, cfg.omega)
+    np.testing.assert_array_equal(out, u)
