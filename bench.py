@@ -292,9 +292,11 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
     # stage 2: 2R 2W, stage 3: 2R 1W, stage 4: 3R 1W) -> 3.25 passes per launch
     contract = 3.25 * state_bytes
     minimum = 2.0 * state_bytes / 4.0      # one read + one write of the state per step
+    shape = (f"ns_march<float,{cfg.nxc},*> (row march, 16 rows per workgroup" if sc["tile"][0] == 0
+             else f"ns_stage<float,{sc['tile'][0]},{sc['tile'][1]},*> (tile")
     return {
-        "kernel": f"ns_stage<float,{sc['tile'][0]},{sc['tile'][1]},*> (ensemble RK4 stage, "
-                  f"{cfg.n_members} x 4 x {cfg.nyc}x{cfg.nxc}, member chunk {sc['member_chunk'] or cfg.n_members})",
+        "kernel": f"{shape}; ensemble RK4 stage, {cfg.n_members} x 4 x {cfg.nyc}x{cfg.nxc}, member chunk "
+                  f"{sc['member_chunk'] or cfg.n_members})",
         "avg_launch_us": avg_s * 1e6,
         "contract_bytes": contract,
         "traffic": measured_traffic(sc),

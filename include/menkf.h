@@ -201,7 +201,12 @@ menkf_status menkf_forecast(menkf_ctx *ctx, int32_t level, void *state_dev, int3
  *   tile_x, tile_y  grid points per 256-thread workgroup of the 2D stencil,
  *                   one of 32x16, 64x8, 32x8, 16x16, 64x4 (FP32) or
  *                   32x8, 16x8, 16x16, 64x4 (FP64); 0, 0 = the first of
- *                   the list.  Ignored by the 1D model.
+ *                   the list (32x16 / 32x8).  FP32 also takes 0x16, the
+ *                   row march: a workgroup of nx threads advances 16 whole
+ *                   periodic rows of one state (nx = 64, 128, 192 or 256,
+ *                   ny a multiple of 16; other grids run the 32x16 tile
+ *                   instead); it is the coarse level's initial schedule
+ *                   when it applies.  Ignored by the 1D model.
  *   member_chunk    states advanced together through a whole forecast
  *                   window, chunk after chunk, so that a chunk's state and
  *                   Runge-Kutta temporaries stay in the last-level cache;

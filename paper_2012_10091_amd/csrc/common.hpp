@@ -216,6 +216,8 @@ hipError_t launch_dual_prep(const Plan &p, const void *members, void *trial, con
 int ns_tile_count(int precision);
 void ns_tile_shape(int precision, int i, int *tx, int *ty);
 int ns_tile_index(int precision, int tx, int ty);   // -1 if not in the table
+struct Plan;
+bool ns_march_applies(const Plan &p, int level);     // the 0 x 16 row-march schedule runs on this level
 hipError_t launch_ns_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
                               void *prev, void *ws, hipStream_t s);
 // grids

@@ -14,14 +14,30 @@
 //   D2 f = (-f[-2] + 16 f[-1] - 30 f[0] + 16 f[1] - f[2]) / 12h^2,
 //   txx = mu(4/3 u_x - 2/3 v_y), tyy = mu(4/3 v_y - 2/3 u_x), txy = mu(u_y + v_x).
 //
-// Kernel structure (one launch per RK stage, all members of a level in one
-// grid): a workgroup owns a TX x TY tile of one member and stages, in LDS,
-//   phase 1: u, v on the tile + halo 4; m, n, p, T on the tile + halo 2
-//   phase 2: u_y, v_x and the energy fluxes tau.u - (E+p)(u, v) on the tile
-//            + halo 2 (by linearity one difference operator per direction
-//            covers the convective and the viscous-work flux of E)
-//   phase 3: F(q) at the tile points, then the stage epilogue
-// The epilogue fuses the classical RK4 combination
+// The arithmetic of one grid point is written once, in three point
+// functions with every fused multiply-add explicit (FP contraction is off
+// in this file), and shared by both kernel shapes, so that any schedule
+// gives bitwise the same forecast:
+//   ns_prim   from (rho, m, n, E): u, v, p, T, the nodal fluxes m u + p,
+//             n u, m v, n v + p and E + p
+//   ns_p2     from u, v at the 4 neighbours in x and in y: u_y, v_x and
+//             the energy fluxes tau.u - (E+p)(u, v) (by linearity one
+//             difference operator per direction covers the convective and
+//             the viscous-work flux of E)
+//   ns_p3     from the neighbours' fluxes, primitives and phase-2 values:
+//             F(q); the difference coefficients (1/12h, mu/12h^2, ...) are
+//             folded into the combining multiply-adds.
+// Kernel shapes (one launch per RK stage, all members of a level in one grid):
+//   ns_stage  a workgroup owns a TX x TY tile of one member; phase 1 on the
+//             tile + halo 4 (u, v) / halo 2 (m, n, p, T), phase 2 on the
+//             tile + halo 2, phase 3 on the tile, each staged in LDS;
+//   ns_march  a workgroup owns 16 whole periodic rows of one member (rows
+//             of 64 to 256 points, one thread per column) and marches down
+//             them: phase 1 of row a, phase 2 of row a - 2 and phase 3 of
+//             row a - 4 in one step, the y-neighbours in registers, the
+//             x-neighbours in LDS rings of 5 and 3 rows, one barrier per
+//             step; no x halo, a y halo of 8 rows per 16.
+// The stage epilogue fuses the classical RK4 combination
 //   q' = q + dt/6 (k1 + 2 k2 + 2 k3 + k4)
 // with the partial sum carried where it costs no extra pass: dt/6 k1 and
 // dt/3 k3 are recovered as (s1 - q)/3 and (s3 - q)/3 from the stage states
@@ -34,14 +50,20 @@
 //   resid  : r = x_prev + dt F(x) - x                      (implicit-Euler residual)
 #include "common.hpp"
 
+#pragma clang fp contract(off)
+
 namespace menkf {
 
 template <typename T>
 struct NSCoef {
-    T i12hx, i12hy, i12hx2, i12hy2;
-    T gm1, tfac, mu, kappa;
-    T epfac;  // gamma / (gamma - 1): E + p = epfac p + (m u + n v) / 2
-    T dt, w;  // w = alpha / D for the sweep
+    T gm1, mhgm1, tfac, epfac, half;   // gamma-1, -(gamma-1)/2, gamma Ma^2, gamma/(gamma-1), 1/2
+    T ix, iy, nix, niy;                // 1/12h and -1/12h per direction
+    T mu, mu2, mm23;                   // mu, 2 mu, -2/3 mu
+    T vxx43, vyy, vy13;                // mu 4/3 /12hx^2, mu /12hy^2, mu/3 /12hy  (rho u equation)
+    T vxx, vyy43, vx13;                // mu /12hx^2, mu 4/3 /12hy^2, mu/3 /12hx  (rho v equation)
+    T kxx, kyy;                        // kappa /12h^2 per direction
+    T dt, hdt, dt3, dt6, third;        // dt, dt/2, dt/3, dt/6, 1/3
+    T w;                               // alpha / D for the sweep
 };
 
 enum { ST1 = 1, ST2 = 2, ST3 = 3, ST4 = 4, SWEEP = 5, RESID = 6 };
@@ -49,6 +71,8 @@ enum { ST1 = 1, ST2 = 2, ST3 = 3, ST4 = 4, SWEEP = 5, RESID = 6 };
 // 1/rho: the hardware reciprocal in FP32 (within 1 ulp), exact division in FP64.
 __device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Per-point records of the LDS tiles: the values a stencil reads at one
 // neighbour sit together, so each neighbour costs one wide LDS read at an
@@ -65,7 +89,164 @@ template <typename T>
 struct alignas(2 * sizeof(T)) NSgd {
     T g, d;   // energy flux g and the cross derivative d differenced along the same direction
 };
+template <typename T>
+struct alignas(4 * sizeof(T)) NSrx {
+    T m, f1, f2, tt;   // what phase 3 differences along x: m, m u + p, n u, T
+};
 
+// ----------------------------------------------------------------- point math
+template <typename T>
+struct NSPrim {
+    T u, v, p, tt, f1, f2, mv, nvp, ep;
+};
+
+template <typename T>
+__device__ __forceinline__ T ns_rho_u2(T m, T n, T u, T v) {
+    return fmad(m, u, n * v);   // rho |u|^2 = m u + n v
+}
+
+template <typename T>
+__device__ __forceinline__ T ns_ep(T p, T s, const NSCoef<T> &c) {
+    return fmad(c.epfac, p, c.half * s);   // E + p = gamma/(gamma-1) p + rho |u|^2 / 2
+}
+
+template <typename T>
+__device__ __forceinline__ NSPrim<T> ns_prim(T rho, T m, T n, T E, const NSCoef<T> &c) {
+    NSPrim<T> r;
+    const T ir = recip(rho);
+    r.u = m * ir;
+    r.v = n * ir;
+    const T s = ns_rho_u2(m, n, r.u, r.v);
+    r.p = fmad(c.mhgm1, s, c.gm1 * E);
+    r.tt = (c.tfac * r.p) * ir;
+    r.f1 = fmad(m, r.u, r.p);
+    r.f2 = n * r.u;
+    r.mv = m * r.v;
+    r.nvp = fmad(n, r.v, r.p);
+    r.ep = ns_ep(r.p, s, c);
+    return r;
+}
+
+// 12 h D1 f and 12 h^2 D2 f from the neighbours in the order -2, -1, +1, +2
+template <typename T>
+__device__ __forceinline__ T s1(const T f[4]) {
+    return fmad(T(8), f[2] - f[1], f[0] - f[3]);
+}
+template <typename T>
+__device__ __forceinline__ T s2(const T f[4], T f0) {
+    return fmad(T(16), f[1] + f[2], fmad(T(-30), f0, -(f[0] + f[3])));
+}
+
+template <typename T>
+struct NSP2 {
+    T gx, gy, uy, vx;
+};
+
+// Phase 2 at one point: u, v of the x- and y-neighbours, u, v and E + p here.
+template <typename T>
+__device__ __forceinline__ NSP2<T> ns_p2(const T xu[4], const T xv[4], const T yu[4], const T yv[4], T u, T v,
+                                         T ep, const NSCoef<T> &c) {
+    const T ux = s1(xu) * c.ix, vx = s1(xv) * c.ix;
+    const T uy = s1(yu) * c.iy, vy = s1(yv) * c.iy;
+    const T dv = c.mm23 * (ux + vy);
+    const T txx = fmad(c.mu2, ux, dv);
+    const T tyy = fmad(c.mu2, vy, dv);
+    const T txy = c.mu * (uy + vx);
+    NSP2<T> r;
+    r.gx = fmad(txx - ep, u, txy * v);   // txx u + txy v - (E+p) u
+    r.gy = fmad(tyy - ep, v, txy * u);   // txy u + tyy v - (E+p) v
+    r.uy = uy;
+    r.vx = vx;
+    return r;
+}
+
+// Phase 3 at one point: F(q) from the neighbours along x (m, m u + p, n u,
+// g_x, u_y, T, u, v) and along y (n, m v, n v + p, g_y, v_x, T, u, v) and
+// u, v, T here.
+template <typename T>
+__device__ __forceinline__ void ns_p3(const T xm[4], const T xf1[4], const T xf2[4], const T xg[4], const T xuy[4],
+                                      const T xT[4], const T xu[4], const T xv[4], const T yn[4], const T ymv[4],
+                                      const T ynvp[4], const T yg[4], const T yvx[4], const T yT[4], const T yu[4],
+                                      const T yv[4], T u0, T v0, T T0, const NSCoef<T> &c, T k[4]) {
+    k[0] = fmad(c.nix, s1(xm), c.niy * s1(yn));
+    k[1] = fmad(c.nix, s1(xf1), fmad(c.niy, s1(ymv), fmad(c.vxx43, s2(xu, u0), fmad(c.vyy, s2(yu, u0), c.vy13 * s1(yvx)))));
+    k[2] = fmad(c.nix, s1(xf2), fmad(c.niy, s1(ynvp), fmad(c.vxx, s2(xv, v0), fmad(c.vyy43, s2(yv, v0), c.vx13 * s1(xuy)))));
+    k[3] = fmad(c.ix, s1(xg), fmad(c.iy, s1(yg), fmad(c.kxx, s2(xT, T0), c.kyy * s2(yT, T0))));
+}
+
+// The stage epilogue of one field at one point: a0, a1, a2 as the kernel
+// prefetched them (ST1: q; ST2: s1, q; ST3: q; ST4: acc, q, s3; SWEEP and
+// RESID: x, x_prev).
+template <typename T, int MODE>
+__device__ __forceinline__ void ns_epilogue(T k, T a0, T a1, T a2, const NSCoef<T> &c, T &o1, T &o2) {
+    if (MODE == ST1) {
+        o1 = fmad(c.hdt, k, a0);                                    // s1
+    } else if (MODE == ST2) {
+        o1 = fmad(c.dt3, k, fmad(c.third, a0 - a1, a1));           // acc
+        o2 = fmad(c.hdt, k, a1);                                    // s2
+    } else if (MODE == ST3) {
+        o1 = fmad(c.dt, k, a0);                                     // s3
+    } else if (MODE == ST4) {
+        o1 = fmad(c.dt6, k, fmad(c.third, a2 - a1, a0));           // q'
+    } else if (MODE == SWEEP) {
+        o1 = fmad(c.w, fmad(c.dt, k, a1) - a0, a0);
+    } else {
+        o1 = fmad(c.dt, k, a1) - a0;
+    }
+}
+
+template <int MODE>
+struct NSPre {
+    static constexpr int N = (MODE == ST1 || MODE == ST3) ? 1 : (MODE == ST4 ? 3 : 2);
+};
+
+// Loads the epilogue operands of one point (byte offset vo in the member's
+// buffers) and stores its outputs.
+template <typename T, int MODE>
+__device__ __forceinline__ void ns_pre_load(T pre[][4], buf_t b_in, buf_t b_q0, buf_t b_acc, int vo, int fstride) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (MODE == ST1) {
+            pre[0][f] = buf_load<T>(b_in, vo, f * fstride);        // q
+        } else if (MODE == ST3) {
+            pre[0][f] = buf_load<T>(b_q0, vo, f * fstride);        // q
+        } else if (MODE == ST4) {
+            pre[0][f] = buf_load<T>(b_acc, vo, f * fstride);       // acc
+            pre[1][f] = buf_load<T>(b_q0, vo, f * fstride);        // q
+            pre[2][f] = buf_load<T>(b_in, vo, f * fstride);        // s3
+        } else {
+            pre[0][f] = buf_load<T>(b_in, vo, f * fstride);        // s1 (ST2) / x
+            pre[1][f] = buf_load<T>(b_q0, vo, f * fstride);        // q (ST2) / x_prev
+        }
+    }
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void ns_store(const T k[4], const T pre[][4], const NSCoef<T> &c, buf_t b_acc,
+                                         buf_t b_next, buf_t b_out, buf_t b_prev, bool has_prev, int vo,
+                                         int fstride) {
+    constexpr int NP = NSPre<MODE>::N;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int so = f * fstride;
+        const T a0 = pre[0][f], a1 = pre[NP > 1 ? 1 : 0][f], a2 = pre[NP - 1][f];
+        T o1 = T(0), o2 = T(0);
+        ns_epilogue<T, MODE>(k[f], a0, a1, a2, c, o1, o2);
+        if (MODE == ST1) {
+            buf_store(o1, b_next, vo, so);
+            if (has_prev) buf_store(a0, b_prev, vo, so);
+        } else if (MODE == ST2) {
+            buf_store(o1, b_acc, vo, so);
+            buf_store(o2, b_next, vo, so);
+        } else if (MODE == ST3) {
+            buf_store(o1, b_next, vo, so);
+        } else {
+            buf_store(o1, b_out, vo, so);
+        }
+    }
+}
+
+// ----------------------------------------------------------------- tile kernel
 template <typename T, int TX, int TY, int MODE>
 __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, const T *q0,
                                                 T *__restrict__ acc, T *__restrict__ snext,
@@ -107,34 +288,15 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
     // updates q in place: q0 and qout are the same array, each point read
     // and then written by the same thread)
     constexpr int IT3 = (TX * TY + 255) / 256;
-    constexpr int NPRE = (MODE == ST1 || MODE == ST3) ? 1 : (MODE == ST4 ? 3 : 2);
+    constexpr int NPRE = NSPre<MODE>::N;
     T pre[IT3][NPRE][4];
 #pragma unroll
     for (int k = 0; k < IT3; ++k) {
         const int i = threadIdx.x + k * 256;
         const int ty = i / TX, tx = i - ty * TX;
         const int gx = tx0 + tx, gy = ty0 + ty;
-        if (i < TX * TY && gx < nx && gy < ny) {
-            const int vo = (gy * nx + gx) * (int)sizeof(T);
-#pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                if (MODE == ST1) {
-                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);      // q
-                } else if (MODE == ST3) {
-                    pre[k][0][f] = buf_load<T>(b_q0, vo, f * fstride);      // q
-                } else if (MODE == ST4) {
-                    pre[k][0][f] = buf_load<T>(b_acc, vo, f * fstride);     // acc
-                    pre[k][1][f] = buf_load<T>(b_q0, vo, f * fstride);      // q
-                    pre[k][NPRE - 1][f] = buf_load<T>(b_in, vo, f * fstride);   // s3
-                } else if (MODE == ST2) {
-                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);      // s1
-                    pre[k][NPRE - 1][f] = buf_load<T>(b_q0, vo, f * fstride);   // q
-                } else {
-                    pre[k][0][f] = buf_load<T>(b_in, vo, f * fstride);
-                    pre[k][NPRE - 1][f] = buf_load<T>(b_q0, vo, f * fstride);
-                }
-            }
-        }
+        if (i < TX * TY && gx < nx && gy < ny)
+            ns_pre_load<T, MODE>(pre[k], b_in, b_q0, b_acc, (gy * nx + gx) * (int)sizeof(T), fstride);
     }
 
     // periodic wrap of the box coordinates, once per tile
@@ -167,14 +329,11 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         // the tail rewrites the last box point with the value it already has
         const int i = min((int)threadIdx.x + k * 256, NB - 1);
         const int by = i / BX, bx = i - by * BX;
-        const T rho = r_rho[k], m = r_m[k], n = r_n[k], E = r_E[k];
-        const T ir = recip(rho);
-        const T u = m * ir, v = n * ir;
-        suv[i] = NSuv<T>{u, v};
+        const NSPrim<T> pr = ns_prim(r_rho[k], r_m[k], r_n[k], r_E[k], c);
+        suv[i] = NSuv<T>{pr.u, pr.v};
         const bool inner = bx >= 2 && bx < BX - 2 && by >= 2 && by < BY - 2;
         const int ci = inner ? (by - 2) * CX + (bx - 2) : NC;
-        const T p = c.gm1 * (E - T(0.5) * (m * u + n * v));
-        smp[ci] = NSmnpt<T>{m, n, p, c.tfac * p * ir};
+        smp[ci] = NSmnpt<T>{r_m[k], r_n[k], pr.p, pr.tt};
     }
     __syncthreads();
 
@@ -192,25 +351,20 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         const NSuv<T> w0 = pu[2 * BX + 2];
         const NSuv<T> xl2 = pu[2 * BX], xl1 = pu[2 * BX + 1], xr1 = pu[2 * BX + 3], xr2 = pu[2 * BX + 4];
         const NSuv<T> yl2 = pu[2], yl1 = pu[BX + 2], yr1 = pu[3 * BX + 2], yr2 = pu[4 * BX + 2];
-        const T ux = (xl2.u - T(8) * xl1.u + T(8) * xr1.u - xr2.u) * c.i12hx;
-        const T vx = (xl2.v - T(8) * xl1.v + T(8) * xr1.v - xr2.v) * c.i12hx;
-        const T uy = (yl2.u - T(8) * yl1.u + T(8) * yr1.u - yr2.u) * c.i12hy;
-        const T vy = (yl2.v - T(8) * yl1.v + T(8) * yr1.v - yr2.v) * c.i12hy;
-        const T div = ux + vy;
-        const T txx = c.mu * (T(2) * ux - T(2.0 / 3.0) * div);
-        const T tyy = c.mu * (T(2) * vy - T(2.0 / 3.0) * div);
-        const T txy = c.mu * (uy + vx);
-        const T u = w0.u, v = w0.v;
+        const T xu[4] = {xl2.u, xl1.u, xr1.u, xr2.u}, xv[4] = {xl2.v, xl1.v, xr1.v, xr2.v};
+        const T yu[4] = {yl2.u, yl1.u, yr1.u, yr2.u}, yv[4] = {yl2.v, yl1.v, yr1.v, yr2.v};
         const NSmnpt<T> a0 = smp[i];
-        const T ep = c.epfac * a0.p + T(0.5) * (a0.m * u + a0.n * v);   // E + p from the state
-        // the energy equation's convective and viscous-work fluxes share one
-        // difference operator per direction
-        sgx[i] = NSgd<T>{(txx * u + txy * v) - ep * u, uy};
-        sgy[i] = NSgd<T>{(txy * u + tyy * v) - ep * v, vx};
+        const T ep = ns_ep(a0.p, ns_rho_u2(a0.m, a0.n, w0.u, w0.v), c);
+        const NSP2<T> r = ns_p2(xu, xv, yu, yv, w0.u, w0.v, ep, c);
+        sgx[i] = NSgd<T>{r.gx, r.uy};
+        sgy[i] = NSgd<T>{r.gy, r.vx};
     }
     __syncthreads();
 
     // phase 3
+    const buf_t b_next = buf_rsrc(snext ? snext + mbase : sin_, mbytes);
+    const buf_t b_out = buf_rsrc(qout ? qout + mbase : sin_, mbytes);
+    const buf_t b_prev = buf_rsrc(prev ? prev + mbase : sin_, mbytes);
 #pragma unroll
     for (int k3 = 0; k3 < IT3; ++k3) {
         const int i = threadIdx.x + k3 * 256;
@@ -227,8 +381,8 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         constexpr int OC = 2 * CX + 2, OB = 2 * BX + 2;
         // neighbour values along x (offset k) and along y, in the order
         // -2, -1, +1, +2 of the stencils
-        T xm[4], xfm[4], xfn[4], xg[4], xuy[4], xT[4], xu[4], xv[4];
-        T yn[4], yfm[4], yfn[4], yg[4], yvx[4], yT[4], yu[4], yv[4];
+        T xm[4], xf1[4], xf2[4], xg[4], xuy[4], xT[4], xu[4], xv[4];
+        T yn[4], ymv[4], ynvp[4], yg[4], yvx[4], yT[4], yu[4], yv[4];
         constexpr int offs[4] = {-2, -1, 1, 2};
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -237,8 +391,8 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
             const NSmnpt<T> ax = pc[OC + o];
             const NSgd<T> gx_ = pgx[OC + o];
             xm[k] = ax.m;
-            xfm[k] = ax.m * wx.u + ax.p;
-            xfn[k] = ax.n * wx.u;
+            xf1[k] = fmad(ax.m, wx.u, ax.p);    // the values ns_prim forms
+            xf2[k] = ax.n * wx.u;
             xg[k] = gx_.g;
             xuy[k] = gx_.d;
             xT[k] = ax.tt;
@@ -248,8 +402,8 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
             const NSmnpt<T> ay = pc[OC + o * CX];
             const NSgd<T> gy_ = pgy[OC + o * CX];
             yn[k] = ay.n;
-            yfm[k] = ay.m * wy.v;
-            yfn[k] = ay.n * wy.v + ay.p;
+            ymv[k] = ay.m * wy.v;
+            ynvp[k] = fmad(ay.n, wy.v, ay.p);
             yg[k] = gy_.g;
             yvx[k] = gy_.d;
             yT[k] = ay.tt;
@@ -258,43 +412,134 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
         }
         const NSuv<T> w0 = pb[OB];
         const T T0 = pc[OC].tt;
-#define DF(F, h) ((F[0] - T(8) * F[1] + T(8) * F[2] - F[3]) * h)
-#define D2(F, f0, h) ((-F[0] + T(16) * F[1] - T(30) * (f0) + T(16) * F[2] - F[3]) * h)
-        const T k_rho = -(DF(xm, c.i12hx) + DF(yn, c.i12hy));
-        const T k_m = -(DF(xfm, c.i12hx) + DF(yfm, c.i12hy)) +
-                      c.mu * (T(4.0 / 3.0) * D2(xu, w0.u, c.i12hx2) + D2(yu, w0.u, c.i12hy2) +
-                              T(1.0 / 3.0) * DF(yvx, c.i12hy));
-        const T k_n = -(DF(xfn, c.i12hx) + DF(yfn, c.i12hy)) +
-                      c.mu * (D2(xv, w0.v, c.i12hx2) + T(4.0 / 3.0) * D2(yv, w0.v, c.i12hy2) +
-                              T(1.0 / 3.0) * DF(xuy, c.i12hx));
-        const T k_E = DF(xg, c.i12hx) + DF(yg, c.i12hy) + c.kappa * (D2(xT, T0, c.i12hx2) + D2(yT, T0, c.i12hy2));
-#undef DF
-#undef D2
-        const T kk[4] = {k_rho, k_m, k_n, k_E};
-        const int vo = (gy * nx + gx) * (int)sizeof(T);
-        const buf_t b_next = buf_rsrc(snext ? snext + mbase : sin_, mbytes);
-        const buf_t b_out = buf_rsrc(qout ? qout + mbase : sin_, mbytes);
-        const buf_t b_prev = buf_rsrc(prev ? prev + mbase : sin_, mbytes);
+        T kk[4];
+        ns_p3(xm, xf1, xf2, xg, xuy, xT, xu, xv, yn, ymv, ynvp, yg, yvx, yT, yu, yv, w0.u, w0.v, T0, c, kk);
+        ns_store<T, MODE>(kk, pre[k3], c, b_acc, b_next, b_out, b_prev, prev != nullptr,
+                          (gy * nx + gx) * (int)sizeof(T), fstride);
+    }
+}
+
+// ----------------------------------------------------------------- row-march kernel
+constexpr int MARCH_ROWS = 16;
+
+// W threads = W columns (a whole periodic row) of one member; the
+// workgroup's R = MARCH_ROWS output rows y0 .. y0 + R - 1.  Step t (fully
+// unrolled, t = 0 .. R + 7) runs phase 1 on row a = y0 - 4 + t, phase 2 on
+// row a - 2 (t >= 4) and phase 3 on row a - 4 (t >= 8):
+//   LDS: RX, RU of row a in slot t % 5 (x-neighbours of phases 2 and 3),
+//        phase 2's (g_x, u_y) in slot t % 3 (x-neighbours of phase 3);
+//   registers: each thread's column of u, v, n, m v, n v + p, T (the last
+//        7 rows), E + p (3 rows) and g_y, v_x (5 rows), the y-neighbours.
+// A slot is rewritten 5 (3) steps after it was written, one step after its
+// last reader, and a step's reads are of slots written at least two steps
+// before, so one barrier at the end of every step orders all of them.
+template <typename T, int W, int MODE>
+__global__ __launch_bounds__(W, 4) void ns_march(const T *__restrict__ sin_, const T *q0, T *__restrict__ acc,
+                                              T *__restrict__ snext, T *qout, T *__restrict__ prev, int ny,
+                                              int segs, int total_blocks, NSCoef<T> c) {
+    constexpr int R = MARCH_ROWS, NIT = R + 8;
+    __shared__ NSrx<T> rx[5][W];
+    __shared__ NSuv<T> ru[5][W];
+    __shared__ NSgd<T> rb[3][W];
+    const int lb = xcd_remap(blockIdx.x, total_blocks);
+    const int member = lb / segs;
+    const int y0 = (lb - member * segs) * R;
+    const int x = threadIdx.x;
+    const int xn[4] = {x >= 2 ? x - 2 : x - 2 + W, x >= 1 ? x - 1 : x - 1 + W, x + 1 < W ? x + 1 : x + 1 - W,
+                       x + 2 < W ? x + 2 : x + 2 - W};
+    const int nxy = W * ny;
+    const long long mbase = (long long)member * 4 * nxy;
+    const uint32_t mbytes = 4u * (uint32_t)nxy * sizeof(T);
+    const int fstride = nxy * (int)sizeof(T);
+    const buf_t b_in = buf_rsrc(sin_ + mbase, mbytes);
+    const buf_t b_q0 = buf_rsrc(q0 ? q0 + mbase : sin_, mbytes);
+    const buf_t b_acc = buf_rsrc(acc ? acc + mbase : sin_, mbytes);
+    const buf_t b_next = buf_rsrc(snext ? snext + mbase : sin_, mbytes);
+    const buf_t b_out = buf_rsrc(qout ? qout + mbase : sin_, mbytes);
+    const buf_t b_prev = buf_rsrc(prev ? prev + mbase : sin_, mbytes);
+    // byte offset of (row a mod ny, column x); a in [-4, ny + 3]
+    auto voff = [&](int a) {
+        a = a < 0 ? a + ny : (a >= ny ? a - ny : a);
+        return (a * W + x) * (int)sizeof(T);
+    };
+    constexpr int NPRE = NSPre<MODE>::N;
+    T wu[7], wv[7], wn[7], wmv[7], wnvp[7], wt[7], wep[3], wgy[5], wvx[5];
+    T ld[4], pre[2][NPRE][4];   // epilogue operands, by step parity (the next row's arrive while this row's are used)
+    {
+        const int vo = voff(y0 - 4);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            const int so = f * fstride;
-            const T a0 = pre[k3][0][f], a1 = pre[k3][NPRE > 1 ? 1 : 0][f], a2 = pre[k3][NPRE - 1][f];
-            if (MODE == ST1) {   // a0 = q
-                buf_store(a0 + c.dt * T(0.5) * kk[f], b_next, vo, so);
-                if (prev) buf_store(a0, b_prev, vo, so);
-            } else if (MODE == ST2) {   // a0 = s1, a1 = q
-                buf_store(a1 + (a0 - a1) * T(1.0 / 3.0) + c.dt * T(1.0 / 3.0) * kk[f], b_acc, vo, so);
-                buf_store(a1 + c.dt * T(0.5) * kk[f], b_next, vo, so);
-            } else if (MODE == ST3) {   // a0 = q
-                buf_store(a0 + c.dt * kk[f], b_next, vo, so);
-            } else if (MODE == ST4) {   // a0 = acc, a1 = q, a2 = s3
-                buf_store(a0 + (a2 - a1) * T(1.0 / 3.0) + c.dt * T(1.0 / 6.0) * kk[f], b_out, vo, so);
-            } else if (MODE == SWEEP) {
-                buf_store(a0 + c.w * (a1 + c.dt * kk[f] - a0), b_out, vo, so);
-            } else {
-                buf_store(a1 + c.dt * kk[f] - a0, b_out, vo, so);
-            }
+        for (int f = 0; f < 4; ++f) ld[f] = buf_load<T>(b_in, vo, f * fstride);
+    }
+#pragma unroll
+    for (int t = 0; t < NIT; ++t) {
+        // phase 1 on row a = y0 - 4 + t; the next row's loads go out first
+        const T rho = ld[0], m = ld[1], n = ld[2], E = ld[3];
+        if (t + 1 < NIT) {
+            const int vo = voff(y0 - 3 + t);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) ld[f] = buf_load<T>(b_in, vo, f * fstride);
         }
+        if (t >= 7 && t + 1 < NIT)   // epilogue operands of the row phase 3 handles next step
+            ns_pre_load<T, MODE>(pre[(t + 1) & 1], b_in, b_q0, b_acc, voff(y0 + t - 7), fstride);
+        const NSPrim<T> pr = ns_prim(rho, m, n, E, c);
+        rx[t % 5][x] = NSrx<T>{m, pr.f1, pr.f2, pr.tt};
+        ru[t % 5][x] = NSuv<T>{pr.u, pr.v};
+        wu[t % 7] = pr.u;
+        wv[t % 7] = pr.v;
+        wn[t % 7] = n;
+        wmv[t % 7] = pr.mv;
+        wnvp[t % 7] = pr.nvp;
+        wt[t % 7] = pr.tt;
+        wep[t % 3] = pr.ep;
+        if (t >= 4) {
+            // phase 2 on row a - 2 (phase 1 of step t - 2)
+            const NSuv<T> *r2 = ru[(t - 2) % 5];
+            const NSuv<T> q[4] = {r2[xn[0]], r2[xn[1]], r2[xn[2]], r2[xn[3]]};
+            const T xu[4] = {q[0].u, q[1].u, q[2].u, q[3].u}, xv[4] = {q[0].v, q[1].v, q[2].v, q[3].v};
+            const T yu[4] = {wu[(t - 4) % 7], wu[(t - 3) % 7], wu[(t - 1) % 7], wu[t % 7]};
+            const T yv[4] = {wv[(t - 4) % 7], wv[(t - 3) % 7], wv[(t - 1) % 7], wv[t % 7]};
+            const NSP2<T> r = ns_p2(xu, xv, yu, yv, wu[(t - 2) % 7], wv[(t - 2) % 7], wep[(t - 2) % 3], c);
+            rb[t % 3][x] = NSgd<T>{r.gx, r.uy};
+            wgy[t % 5] = r.gy;
+            wvx[t % 5] = r.vx;
+        }
+        if (t >= 8) {
+            // phase 3 on row y = a - 4 (phase 1 of step t - 4, phase 2 of step t - 2)
+            const NSrx<T> *r3 = rx[(t - 4) % 5];
+            const NSuv<T> *u3 = ru[(t - 4) % 5];
+            const NSgd<T> *b3 = rb[(t - 2) % 3];
+            T xm[4], xf1[4], xf2[4], xg[4], xuy[4], xT[4], xu[4], xv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const NSrx<T> a3 = r3[xn[k]];
+                const NSuv<T> w3 = u3[xn[k]];
+                const NSgd<T> g3 = b3[xn[k]];
+                xm[k] = a3.m;
+                xf1[k] = a3.f1;
+                xf2[k] = a3.f2;
+                xT[k] = a3.tt;
+                xu[k] = w3.u;
+                xv[k] = w3.v;
+                xg[k] = g3.g;
+                xuy[k] = g3.d;
+            }
+            // rows y - 2, y - 1, y + 1, y + 2: phase 1 of steps t - 6, t - 5, t - 3, t - 2
+            // and phase 2 of steps t - 4, t - 3, t - 1, t
+            const T yn[4] = {wn[(t - 6) % 7], wn[(t - 5) % 7], wn[(t - 3) % 7], wn[(t - 2) % 7]};
+            const T ymv[4] = {wmv[(t - 6) % 7], wmv[(t - 5) % 7], wmv[(t - 3) % 7], wmv[(t - 2) % 7]};
+            const T ynvp[4] = {wnvp[(t - 6) % 7], wnvp[(t - 5) % 7], wnvp[(t - 3) % 7], wnvp[(t - 2) % 7]};
+            const T yT[4] = {wt[(t - 6) % 7], wt[(t - 5) % 7], wt[(t - 3) % 7], wt[(t - 2) % 7]};
+            const T yu[4] = {wu[(t - 6) % 7], wu[(t - 5) % 7], wu[(t - 3) % 7], wu[(t - 2) % 7]};
+            const T yv[4] = {wv[(t - 6) % 7], wv[(t - 5) % 7], wv[(t - 3) % 7], wv[(t - 2) % 7]};
+            const T yg[4] = {wgy[(t - 4) % 5], wgy[(t - 3) % 5], wgy[(t - 1) % 5], wgy[t % 5]};
+            const T yvx[4] = {wvx[(t - 4) % 5], wvx[(t - 3) % 5], wvx[(t - 1) % 5], wvx[t % 5]};
+            T kk[4];
+            ns_p3(xm, xf1, xf2, xg, xuy, xT, xu, xv, yn, ymv, ynvp, yg, yvx, yT, yu, yv, wu[(t - 4) % 7],
+                  wv[(t - 4) % 7], wt[(t - 4) % 7], c, kk);
+            ns_store<T, MODE>(kk, pre[t & 1], c, b_acc, b_next, b_out, b_prev, prev != nullptr, voff(y0 + t - 8),
+                              fstride);
+        }
+        __syncthreads();
     }
 }
 
@@ -306,21 +551,78 @@ static NSCoef<T> ns_coef(const Plan &p, int level, double alpha) {
     const double g = p.cfg.gamma, ma = p.cfg.mach;
     const double mu = 1.0 / p.cfg.reynolds;
     const double cp = 1.0 / ((g - 1.0) * ma * ma);
+    const double kappa = mu * cp / p.cfg.prandtl;
+    const double ix = 1.0 / (12.0 * hx), iy = 1.0 / (12.0 * hy);
+    const double ixx = 1.0 / (12.0 * hx * hx), iyy = 1.0 / (12.0 * hy * hy);
     NSCoef<T> c;
-    c.i12hx = (T)(1.0 / (12.0 * hx));
-    c.i12hy = (T)(1.0 / (12.0 * hy));
-    c.i12hx2 = (T)(1.0 / (12.0 * hx * hx));
-    c.i12hy2 = (T)(1.0 / (12.0 * hy * hy));
     c.gm1 = (T)(g - 1.0);
-    c.epfac = (T)(g / (g - 1.0));
+    c.mhgm1 = (T)(-0.5 * (g - 1.0));
     c.tfac = (T)(g * ma * ma);
+    c.epfac = (T)(g / (g - 1.0));
+    c.half = (T)0.5;
+    c.ix = (T)ix;
+    c.iy = (T)iy;
+    c.nix = (T)(-ix);
+    c.niy = (T)(-iy);
     c.mu = (T)mu;
-    c.kappa = (T)(mu * cp / p.cfg.prandtl);
+    c.mu2 = (T)(2.0 * mu);
+    c.mm23 = (T)(-2.0 / 3.0 * mu);
+    c.vxx43 = (T)(mu * 4.0 / 3.0 * ixx);
+    c.vyy = (T)(mu * iyy);
+    c.vy13 = (T)(mu / 3.0 * iy);
+    c.vxx = (T)(mu * ixx);
+    c.vyy43 = (T)(mu * 4.0 / 3.0 * iyy);
+    c.vx13 = (T)(mu / 3.0 * ix);
+    c.kxx = (T)(kappa * ixx);
+    c.kyy = (T)(kappa * iyy);
     c.dt = (T)p.cfg.dt;
+    c.hdt = (T)(0.5 * p.cfg.dt);
+    c.dt3 = (T)(p.cfg.dt / 3.0);
+    c.dt6 = (T)(p.cfg.dt / 6.0);
+    c.third = (T)(1.0 / 3.0);
     const double D = 1.0 + p.cfg.dt * mu * (30.0 / 12.0) * (1.0 / (hx * hx) + 1.0 / (hy * hy));
     c.w = (T)(alpha / D);
     return c;
 }
+
+// Row-march schedule: rows of W = nx points (64, 128, 192 or 256, one
+// thread each) and ny a multiple of the 16 rows of a workgroup (FP32).
+static bool march_shape_ok(int nx, int ny) {
+    return (nx == 64 || nx == 128 || nx == 192 || nx == 256) && ny % MARCH_ROWS == 0 && ny >= MARCH_ROWS;
+}
+
+template <typename T, int W>
+struct MarchLauncher {
+    template <int MODE>
+    static hipError_t stage(const T *s, const T *q0, T *acc, T *snext, T *qout, T *prev, int ny, int nb,
+                            const NSCoef<T> &c, hipStream_t st) {
+        const int segs = ny / MARCH_ROWS;
+        const int total = segs * nb;
+        hipLaunchKernelGGL((ns_march<T, W, MODE>), dim3(total), dim3(W), 0, st, s, q0, acc, snext, qout, prev, ny,
+                           segs, total, c);
+        return hipGetLastError();
+    }
+    static hipError_t forecast(T *state, T *s1, T *s2, T *acc, T *prev, int ny, int nb, int nsteps, int chunk,
+                               const NSCoef<T> &c, hipStream_t st) {
+        hipError_t e = hipSuccess;
+        const long long msz = 4LL * W * ny;
+        if (chunk < 1 || chunk > nb) chunk = nb;
+        for (int m0 = 0; m0 < nb && e == hipSuccess; m0 += chunk) {
+            const int cb = nb - m0 < chunk ? nb - m0 : chunk;
+            T *q = state + m0 * msz;
+            T *a = acc + m0 * msz, *t1 = s1 + m0 * msz, *t2 = s2 + m0 * msz;
+            T *pchunk = prev ? prev + m0 * msz : nullptr;
+            for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
+                T *pv = step == nsteps - 1 ? pchunk : nullptr;
+                e = stage<ST1>(q, nullptr, nullptr, t1, nullptr, pv, ny, cb, c, st);
+                if (e == hipSuccess) e = stage<ST2>(t1, q, a, t2, nullptr, nullptr, ny, cb, c, st);
+                if (e == hipSuccess) e = stage<ST3>(t2, q, nullptr, t1, nullptr, nullptr, ny, cb, c, st);
+                if (e == hipSuccess) e = stage<ST4>(t1, q, a, nullptr, q, nullptr, ny, cb, c, st);
+            }
+        }
+        return e;
+    }
+};
 
 template <typename T, int TX, int TY>
 struct NSLauncher {
@@ -363,7 +665,10 @@ struct NSLauncher {
 // workgroup: (2 (TX+8)(TY+8) + 8 (TX+4)(TY+4) + 4) elements, e.g. 30.7 KB
 // for 32 x 16 in FP32 (five workgroups per compute unit).  The first entry
 // of each list is the default.
-static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}};
+// The last FP32 entry, 0 x 16, is the row-march schedule (whole rows of
+// 64 to 256 points, 16 rows per workgroup); on other grids it runs the
+// default tile.
+static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}, {0, MARCH_ROWS}};
 static const int kTilesF64[][2] = {{32, 8}, {16, 8}, {16, 16}, {64, 4}};
 
 int ns_tile_count(int precision) {
@@ -375,6 +680,11 @@ void ns_tile_shape(int precision, int i, int *tx, int *ty) {
     const int(*tab)[2] = precision == MENKF_F64 ? kTilesF64 : kTilesF32;
     *tx = tab[i][0];
     *ty = tab[i][1];
+}
+
+bool ns_march_applies(const Plan &p, int level) {
+    return p.dim == 2 && p.cfg.precision == MENKF_F32 &&
+           march_shape_ok(level == MENKF_FINE ? p.nx : p.nxc, level == MENKF_FINE ? p.ny : p.nyc);
 }
 
 int ns_tile_index(int precision, int tx, int ty) {
@@ -404,6 +714,7 @@ static hipError_t with_tile(int ti, const Fn &f) {
         case 2: return f.template run<32, 8>();
         case 3: return f.template run<16, 16>();
         case 4: return f.template run<64, 4>();
+        case 5: return f.run_march();
         default: return f.template run<32, 16>();
         }
     }
@@ -420,6 +731,17 @@ struct NSForecastFn {
     hipError_t run() const {
         return NSLauncher<T, TX, TY>::forecast(state, s1, s2, acc, prev, nx, ny, nb, nsteps, chunk, c, s);
     }
+    hipError_t run_march() const {
+        if (sizeof(T) == 4 && march_shape_ok(nx, ny)) {
+            switch (nx) {
+            case 64: return MarchLauncher<T, 64>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            case 128: return MarchLauncher<T, 128>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            case 192: return MarchLauncher<T, 192>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            default: return MarchLauncher<T, 256>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            }
+        }
+        return run<32, 16>();
+    }
 };
 
 template <typename TT, int MODE>
@@ -435,6 +757,7 @@ struct NSSingleFn {
     hipError_t run() const {
         return NSLauncher<T, TX, TY>::template stage<MODE>(x, xp, nullptr, nullptr, out, nullptr, nx, ny, 1, c, info, s);
     }
+    hipError_t run_march() const { return run<32, 16>(); }   // sweeps and residuals use the tile kernel
 };
 
 static int sched_tile(const Plan &p, int level) {

@@ -143,6 +143,12 @@ def test_forecast_c3_shapes_f32():
     g = to_np(mem_d)
     for i in range(cfg.n_members):
         assert rel_l2(g[i], o_m[i]) < 1e-5, i
+    # the row-march schedule of the coarse level: the same forecast, bitwise
+    ctx.set_schedule(1, (0, 16), 0)
+    mem2 = to_dev(mem, F32)
+    say("  coarse level again with the row-march schedule")
+    ctx.forecast(1, mem2, cfg.n_obs)
+    np.testing.assert_array_equal(to_np(mem2), g)
 
 
 def test_forecast_conserves_totals_f64():

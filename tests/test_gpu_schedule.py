@@ -13,7 +13,7 @@ from tests.gpu_helpers import make_ctx, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TILES = {"f32": [(32, 16), (64, 8), (32, 8), (16, 16), (64, 4)],
+TILES = {"f32": [(32, 16), (64, 8), (32, 8), (16, 16), (64, 4), (0, 16)],
          "f64": [(32, 8), (16, 8), (16, 16), (64, 4)]}
 
 
@@ -83,3 +83,29 @@ def test_autotune_picks_a_listed_schedule_and_keeps_results():
     got = _forecast(ctx, cfg, torch.float32, 2)
     for a, b in zip(got, ref):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("side", [(256, 256), (512, 256), (768, 768)], ids=["coarse64x64", "coarse128x64",
+                                                                            "coarse192x192"])
+def test_row_march_is_bitwise_equal_to_the_tile_kernel(side):
+    """Grids whose coarse rows the row-march schedule (0 x 16) takes whole:
+    forecasts of every member and x_{k-1}, with and without member chunks,
+    bitwise equal to the default tile's."""
+    nx, ny = side
+    cfg = configs.tiny_2d(nx=nx, ny=ny, n_members=5, precision="f32", dt=5e-4 * 256 / nx)
+    ctx, _, _ = make_ctx(cfg)
+    mem0 = to_dev(fields.member_ics(cfg), torch.float32)
+    outs = []
+    for tile, chunk in (((32, 16), 0), ((0, 16), 0), ((0, 16), 2)):
+        say(f"row march {nx}x{ny}: coarse tile {tile} chunk {chunk}")
+        ctx.set_schedule(1, tile, chunk)
+        m = mem0.clone()
+        ctx.forecast(1, m, 3)
+        p = mem0[:1].clone()
+        pv = torch.empty_like(p)
+        ctx.forecast(1, p, 2, prev=pv)
+        torch.cuda.synchronize()
+        outs.append((m.cpu(), p.cpu(), pv.cpu()))
+    for got in outs[1:]:
+        for a, b in zip(got, outs[0]):
+            assert torch.equal(a, b)
