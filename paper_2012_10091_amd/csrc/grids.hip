@@ -104,6 +104,57 @@ __global__ __launch_bounds__(256) void prolong_add_rows(const T *__restrict__ dc
     xout[g] = xin[g] + acc;
 }
 
+// 2D form with the coarse rows staged: one workgroup per (fine row y,
+// field); the four coarse rows jy - 1 .. jy + 2 under the row are read once
+// into LDS (coalesced), then every fine point of the row interpolates from
+// them.  Same weights and summation order (x first per coarse row, then
+// y) as prolong_at, so the result is bitwise that of prolong_add_rows.
+template <typename T>
+__global__ __launch_bounds__(256) void prolong_add_staged(const T *__restrict__ dc, const T *__restrict__ xin,
+                                                          T *__restrict__ xout, int nx, int ny, int r, int nxc,
+                                                          int nyc, const int32_t *__restrict__ info) {
+    extern __shared__ __align__(16) unsigned char smem_pa[];
+    T(*wxs)[4] = reinterpret_cast<T(*)[4]>(smem_pa);          // [64][4]
+    T *crow = reinterpret_cast<T *>(smem_pa + 64 * 4 * sizeof(T));   // [4][nxc]
+    if (*info != 0) return;
+    const int y = blockIdx.x, f = blockIdx.y;
+    const int jy = y / r, my = y - jy * r;
+    const T *d = dc + (long long)f * nxc * nyc;
+    if ((int)threadIdx.x < r) lagrange4<T>(T(threadIdx.x) / T(r), wxs[threadIdx.x]);
+    for (int e = threadIdx.x; e < 4 * nxc; e += 256) {
+        const int a = e / nxc, j = e - a * nxc;
+        int ry = jy - 1 + a;
+        ry += ry < 0 ? nyc : 0;
+        ry -= ry >= nyc ? nyc : 0;
+        crow[e] = d[(long long)ry * nxc + j];
+    }
+    T wy[4];
+    lagrange4<T>(T(my) / T(r), wy);
+    __syncthreads();
+    const long long g0 = ((long long)f * ny + y) * nx;
+    for (int x = threadIdx.x; x < nx; x += 256) {
+        const int jx = x / r, mx = x - jx * r;
+        int cx[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            int v = jx - 1 + b;
+            v += v < 0 ? nxc : 0;
+            v -= v >= nxc ? nxc : 0;
+            cx[b] = v;
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const T *row = crow + a * nxc;
+            T sa = T(0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) sa += wxs[mx][b] * row[cx[b]];
+            acc += wy[a] * sa;
+        }
+        xout[g0 + x] = xin[g0 + x] + acc;
+    }
+}
+
 // Members recentred on the injected fine state: one thread per coarse
 // (field, point); the member mean is accumulated in FP64.
 template <typename T>
@@ -154,6 +205,17 @@ hipError_t launch_prolong_add(const Plan &p, const void *dc, const void *xin, vo
         else
             hipLaunchKernelGGL(prolong_add_open<float>, dim3(blocks), dim3(256), 0, s, (const float *)dc,
                                (const float *)xin, (float *)xout, p.nx, p.cfg.ratio, p.nxc, p.F, info);
+        return hipGetLastError();
+    }
+    if (p.dim == 2 && p.cfg.ratio <= 64 && (size_t)(64 + p.nxc) * 4 * p.tsize <= 32768) {
+        const dim3 grid(p.ny, p.F);
+        const size_t lds = (size_t)(64 + p.nxc) * 4 * p.tsize;
+        if (p.cfg.precision == MENKF_F64)
+            hipLaunchKernelGGL(prolong_add_staged<double>, grid, dim3(256), lds, s, (const double *)dc,
+                               (const double *)xin, (double *)xout, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, info);
+        else
+            hipLaunchKernelGGL(prolong_add_staged<float>, grid, dim3(256), lds, s, (const float *)dc,
+                               (const float *)xin, (float *)xout, p.nx, p.ny, p.cfg.ratio, p.nxc, p.nyc, info);
         return hipGetLastError();
     }
     if (p.dim == 2 && p.ny <= 65535 && p.cfg.ratio <= 64) {
