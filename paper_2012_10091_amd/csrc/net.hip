@@ -58,9 +58,15 @@ __device__ __forceinline__ bf16x8 zero_bf16x8() {
     return z;
 }
 
-// One conv layer from LDS activations act_in ([RIN*RIN][IC], BF16) to
-// act_out ([ROUT*ROUT][32], BF16, bias + ReLU).  Waves take 32-pixel groups
-// round-robin.
+// 32-channel pixel records in LDS: the four 16-byte chunks of 8 channels
+// of pixel p sit at chunk position q ^ ((p >> 2) & 3), so that the 16 lanes
+// of an MFMA operand read that fetch the same chunk of 16 consecutive
+// pixels (records 64 bytes apart) cover 16 distinct 4-bank groups.
+__device__ __forceinline__ int chunk_pos(int pix, int q) { return (q ^ ((pix >> 2) & 3)) * 8; }
+
+// One conv layer from LDS activations act_in ([RIN*RIN][IC], BF16; 32
+// channels in swizzled chunks) to act_out ([ROUT*ROUT][32], BF16 swizzled,
+// bias + ReLU).  Waves take 32-pixel groups round-robin.
 template <int IC, int RIN, int ROUT>
 __device__ __forceinline__ void conv_layer(const __bf16 *act_in, __bf16 *act_out, const __bf16 *__restrict__ wk,
                                            const float *__restrict__ bias, int wave, int lane) {
@@ -89,7 +95,8 @@ __device__ __forceinline__ void conv_layer(const __bf16 *act_in, __bf16 *act_out
             if (kb < K) {
                 const int tap = kb / IC, ic0 = kb - tap * IC;
                 const int pix = (py + tap / 3) * RIN + (px + tap % 3);
-                b = *reinterpret_cast<const bf16x8 *>(act_in + pix * IC + ic0);
+                const int off = IC == 32 ? chunk_pos(pix, ic0 >> 3) : ic0;
+                b = *reinterpret_cast<const bf16x8 *>(act_in + pix * IC + off);
             } else {
                 b = zero_bf16x8();
             }
@@ -98,8 +105,7 @@ __device__ __forceinline__ void conv_layer(const __bf16 *act_in, __bf16 *act_out
         if (valid) {
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int oc0 = 8 * g + 4 * (lane >> 5);
-                __bf16 *dst = act_out + n * 32 + oc0;
+                __bf16 *dst = act_out + n * 32 + chunk_pos(n, g) + 4 * (lane >> 5);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) dst[i] = (__bf16)fmaxf(acc[4 * g + i] + bv[4 * g + i], 0.0f);
             }
@@ -205,7 +211,7 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
                 const int kb = ks * 16 + (lane >> 5) * 8;
                 const int tap = kb / 32, ic0 = kb - tap * 32;
                 const int pix = (py + tap / 3) * R2 + (px + tap % 3);
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(act2 + pix * 32 + ic0);
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(act2 + pix * 32 + chunk_pos(pix, ic0 >> 3));
                 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
             }
             if (lane < 32) {
