@@ -421,6 +421,10 @@ __global__ __launch_bounds__(256) void ns_stage(const T *__restrict__ sin_, cons
 
 // ----------------------------------------------------------------- row-march kernel
 constexpr int MARCH_ROWS = 16;
+#ifndef MARCH_AHEAD_STEPS
+#define MARCH_AHEAD_STEPS 1
+#endif
+constexpr int MARCH_AHEAD = MARCH_AHEAD_STEPS;   // steps between a row's load and its phase 1
 
 // W threads = W columns (a whole periodic row) of one member; the
 // workgroup's R = MARCH_ROWS output rows y0 .. y0 + R - 1.  Step t (fully
@@ -464,20 +468,24 @@ __global__ __launch_bounds__(W, 4) void ns_march(const T *__restrict__ sin_, con
     };
     constexpr int NPRE = NSPre<MODE>::N;
     T wu[7], wv[7], wn[7], wmv[7], wnvp[7], wt[7], wep[3], wgy[5], wvx[5];
-    T ld[4], pre[2][NPRE][4];   // epilogue operands, by step parity (the next row's arrive while this row's are used)
-    {
-        const int vo = voff(y0 - 4);
+    // phase 1's input rows, loaded MARCH_AHEAD steps before they are used
+    // (slot t % MARCH_AHEAD), and the epilogue operands, by step parity
+    T ld[MARCH_AHEAD][4], pre[2][NPRE][4];
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ld[f] = buf_load<T>(b_in, vo, f * fstride);
+    for (int k = 0; k < MARCH_AHEAD; ++k) {
+        const int vo = voff(y0 - 4 + k);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) ld[k][f] = buf_load<T>(b_in, vo, f * fstride);
     }
 #pragma unroll
     for (int t = 0; t < NIT; ++t) {
-        // phase 1 on row a = y0 - 4 + t; the next row's loads go out first
-        const T rho = ld[0], m = ld[1], n = ld[2], E = ld[3];
-        if (t + 1 < NIT) {
-            const int vo = voff(y0 - 3 + t);
+        // phase 1 on row a = y0 - 4 + t; the loads of row a + MARCH_AHEAD go out first
+        const T rho = ld[t % MARCH_AHEAD][0], m = ld[t % MARCH_AHEAD][1], n = ld[t % MARCH_AHEAD][2],
+                E = ld[t % MARCH_AHEAD][3];
+        if (t + MARCH_AHEAD < NIT) {
+            const int vo = voff(y0 - 4 + t + MARCH_AHEAD);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) ld[f] = buf_load<T>(b_in, vo, f * fstride);
+            for (int f = 0; f < 4; ++f) ld[t % MARCH_AHEAD][f] = buf_load<T>(b_in, vo, f * fstride);
         }
         if (t >= 7 && t + 1 < NIT)   // epilogue operands of the row phase 3 handles next step
             ns_pre_load<T, MODE>(pre[(t + 1) & 1], b_in, b_q0, b_acc, voff(y0 + t - 7), fstride);
