@@ -266,8 +266,12 @@ def rmse_comparison(cfg, net, n_cycles, n_sweeps, judge_every):
 
 
 def stage_kernel_roofline(cfg, cyc, reps=2):
-    """Average duration of the ensemble RK4 stage kernel, timed with HIP events
-    on the stream it is launched on, and its bytes per launch."""
+    """Average duration of the ensemble RK4 stage kernel launches, timed with
+    HIP events on the stream they are launched on, and their bytes per
+    launch: the algorithmic minimum (one read and one write of the state per
+    time step, shared by the launches of the step) and the kernel's own
+    contract (13 state passes per step over four single-stage launches, 7
+    over the two launches of the paired row march)."""
     import torch
     import paper_2012_10091_amd as m
     stream = torch.cuda.Stream()
@@ -284,20 +288,28 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
     sc = cyc.ctx.get_schedule(m.MENKF_COARSE)
     chunk = sc["member_chunk"] or cfg.n_members
     n_chunks = -(-cfg.n_members // chunk)
-    launches = reps * cfg.n_obs * 4 * n_chunks
+    paired = tuple(sc["tile"]) == (0, 32)
+    per_step = 2 if paired else 4
+    launches = reps * cfg.n_obs * per_step * n_chunks
     avg_s = ev0.elapsed_time(ev1) / 1e3 / launches
     pts = cfg.n_members * cfg.nxc * cfg.nyc / n_chunks      # points per launch (equal chunks)
     state_bytes = pts * 4 * 4
-    # kernel contract: 13 state passes per RK4 step over 4 launches (stage 1: 1R 1W,
-    # stage 2: 2R 2W, stage 3: 2R 1W, stage 4: 3R 1W) -> 3.25 passes per launch
-    contract = 3.25 * state_bytes
-    minimum = 2.0 * state_bytes / 4.0      # one read + one write of the state per step
-    shape = (f"ns_march<float,{cfg.nxc},*> (row march, 16 rows per workgroup" if sc["tile"][0] == 0
-             else f"ns_stage<float,{sc['tile'][0]},{sc['tile'][1]},*> (tile")
+    # kernel contract per step: single-stage launches 13 passes (stage 1: 1R 1W,
+    # 2: 2R 2W, 3: 2R 1W, 4: 3R 1W); paired launches 7 (stages 1+2: 1R 2W,
+    # stages 3+4: 3R 1W)
+    contract = (7.0 if paired else 13.0) / per_step * state_bytes
+    minimum = 2.0 * state_bytes / per_step      # one read + one write of the state per step
+    if paired:
+        shape = f"ns_march_pair<float,{cfg.nxc},0|1> (row march, two RK stages per launch, 32 rows per workgroup"
+    elif sc["tile"][0] == 0:
+        shape = f"ns_march<float,{cfg.nxc},*> (row march, one RK stage per launch, 16 rows per workgroup"
+    else:
+        shape = f"ns_stage<float,{sc['tile'][0]},{sc['tile'][1]},*> (tile, one RK stage per launch"
     return {
-        "kernel": f"{shape}; ensemble RK4 stage, {cfg.n_members} x 4 x {cfg.nyc}x{cfg.nxc}, member chunk "
+        "kernel": f"{shape}; ensemble RK4, {cfg.n_members} x 4 x {cfg.nyc}x{cfg.nxc}, member chunk "
                   f"{sc['member_chunk'] or cfg.n_members})",
         "avg_launch_us": avg_s * 1e6,
+        "launches_per_step": per_step,
         "contract_bytes": contract,
         "traffic": measured_traffic(sc),
         "min_bytes": minimum,
@@ -373,7 +385,7 @@ def gain_fp64_utilisation(cfg, cyc, reps=5):
             "frac_of_fp64_peak": flops / avg / 1e12 / FP64_PEAK_TFLOPS_MATRIX}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ns_stage_64x4x256sq_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ns_march_pair_64x4x256sq_traffic.md")
 
 
 def measured_traffic(schedule):
@@ -1182,7 +1194,8 @@ def main():
             "avg_launch_us": rl["avg_launch_us"],
             "algorithmic_bytes_per_launch": rl["min_bytes"],
             "algorithmic_bytes": "one read and one write of the state per time step (2 F 4 B per point), "
-                                 "a quarter of it per RK4 stage launch",
+                                 "shared equally by the launches of a step",
+            "launches_per_step": rl["launches_per_step"],
             "contract_bytes_per_launch": rl["contract_bytes"],
             "contract_gbs": rl["achieved_contract"],
             "contract_frac": rl["achieved_contract"] / HBM_PEAK_GBS,

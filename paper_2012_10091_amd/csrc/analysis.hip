@@ -1287,6 +1287,17 @@ __global__ __launch_bounds__(64) void mfma_test_bf16(const __bf16 *a, const __bf
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     for (int e = 0; e < 16; ++e) out[(8 * (e >> 2) + 4 * (l >> 5) + (e & 3)) * 32 + (l & 31)] = acc[e];
 }
+__global__ __launch_bounds__(64) void mfma_test_bf16_16(const __bf16 *a, const __bf16 *b, float *out) {
+    const int l = threadIdx.x;
+    bf16x8 av, bv;
+    for (int e = 0; e < 8; ++e) {
+        av[e] = a[(l & 15) * 32 + (l >> 4) * 8 + e];
+        bv[e] = b[((l >> 4) * 8 + e) * 16 + (l & 15)];
+    }
+    f32x4 acc = {};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    for (int e = 0; e < 4; ++e) out[(4 * (l >> 4) + e) * 16 + (l & 15)] = acc[e];
+}
 __global__ __launch_bounds__(64) void mfma_test_f64(const double *a, const double *b, double *out) {
     const int l = threadIdx.x;
     f64x4 acc = {};
@@ -1302,6 +1313,9 @@ extern "C" int menkf_test_mfma(int which, const void *a, const void *b, void *ou
     else if (which == 1)
         hipLaunchKernelGGL(menkf::mfma_test_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, (const double *)a,
                            (const double *)b, (double *)out);
+    else if (which == 2)
+        hipLaunchKernelGGL(menkf::mfma_test_bf16_16, dim3(1), dim3(64), 0, (hipStream_t)stream, (const __bf16 *)a,
+                           (const __bf16 *)b, (float *)out);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();

@@ -199,11 +199,15 @@ static menkf_status build_plan(const menkf_config *cfg, Plan *p) {
         ns_tile_shape(cfg->precision, 0, &p->sched[l].tile_x, &p->sched[l].tile_y);
         p->sched[l].member_chunk = 0;
     }
-    // the coarse ensemble's whole rows fit one workgroup: march them by default
-    if (ns_march_applies(*p, MENKF_COARSE)) {
-        p->sched[1].tile_x = 0;
-        p->sched[1].tile_y = 16;
-    }
+    // the coarse ensemble's whole rows fit one workgroup: march them by
+    // default, two RK stages per launch where the rows divide into 32-row
+    // segments, one stage per launch where they divide into 16-row ones
+    for (int rows : {PAIR_ROWS, 16})
+        if (ns_march_applies(*p, MENKF_COARSE, rows)) {
+            p->sched[1].tile_x = 0;
+            p->sched[1].tile_y = rows;
+            break;
+        }
     return MENKF_OK;
 }
 
@@ -355,7 +359,7 @@ menkf_status menkf_autotune(menkf_ctx *ctx, int32_t level, void *scratch, int32_
         for (int c : chunks) {
             menkf_schedule sc{};
             ns_tile_shape(p.cfg.precision, t, &sc.tile_x, &sc.tile_y);
-            if (sc.tile_x == 0 && !ns_march_applies(p, level)) continue;   // would run the default tile
+            if (sc.tile_x == 0 && !ns_march_applies(p, level, sc.tile_y)) continue;   // would run the default tile
             sc.member_chunk = c;
             if (sc.tile_x == keep.tile_x && sc.tile_y == keep.tile_y && sc.member_chunk == keep.member_chunk) continue;
             cand.push_back(sc);

@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <type_traits>
+
 #include "../../include/menkf.h"
 
 namespace menkf {
@@ -24,6 +26,16 @@ __device__ __forceinline__ int xcd_remap(int i, int total) {
     const int per = total >> 3;
     const int rem = total & 7;
     return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+// f(std::integral_constant<int, I>) for I = B .. E-1 in order: the body is
+// instantiated once per I, so array indices derived from I are constants.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 __device__ __forceinline__ int wrap(int v, int n) {
@@ -217,7 +229,12 @@ int ns_tile_count(int precision);
 void ns_tile_shape(int precision, int i, int *tx, int *ty);
 int ns_tile_index(int precision, int tx, int ty);   // -1 if not in the table
 struct Plan;
-bool ns_march_applies(const Plan &p, int level);     // the 0 x 16 row-march schedule runs on this level
+// rows per workgroup of the paired row march (two RK stages per launch)
+#ifndef PAIR_ROWS_BUILD
+#define PAIR_ROWS_BUILD 32
+#endif
+constexpr int PAIR_ROWS = PAIR_ROWS_BUILD;
+bool ns_march_applies(const Plan &p, int level, int rows);   // the 0 x rows row-march schedule runs on this level
 hipError_t launch_ns_forecast(const Plan &p, int level, void *state, int nb, int nsteps,
                               void *prev, void *ws, hipStream_t s);
 // grids

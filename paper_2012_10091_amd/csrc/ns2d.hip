@@ -551,6 +551,215 @@ __global__ __launch_bounds__(W, 4) void ns_march(const T *__restrict__ sin_, con
     }
 }
 
+// ----------------------------------------------------------------- paired row-march kernel
+// Two RK stages per launch (stages 1 and 2, then 3 and 4), so that a step
+// moves 7 state passes instead of 13:
+//   pair 0: in q            -> acc, s2      (s1 stays on chip)       1R 2W
+//   pair 1: in s2, q, acc   -> q' (into a second array)              3R 1W
+// A workgroup of W threads owns PAIR_ROWS whole periodic rows of one
+// member.  The first stage of the pair (A) marches exactly as ns_march
+// does; each row it finishes is at once the input row of the second
+// stage (B), which marches 4 rows behind.  Step t (t = 0 .. R + 15):
+//   A: phase 1 on row y0 - 8 + t, phase 2 on y0 - 10 + t, phase 3 (an
+//      A output row) on y0 - 12 + t;
+//   B: phase 1 on that A output row, phase 2 on y0 - 14 + t, phase 3 (an
+//      output row of the launch) on y0 - 16 + t.
+// Each stage keeps its own LDS rings (5, 5 and 3 rows) and register
+// windows, with the same ring discipline as ns_march: one barrier per step.
+// The point arithmetic and the RK combinations are those of ns_stage, so
+// every schedule gives bitwise the same forecast.  Pair 1 cannot update q
+// in place (its y halo reads q rows that the neighbouring workgroup
+// writes): it writes q' to another array and the launcher alternates the
+// two between steps.
+
+template <typename T, int W>
+struct MarchRing {
+    NSrx<T> rx[5][W];
+    NSuv<T> ru[5][W];
+    NSgd<T> rb[3][W];
+};
+
+template <typename T>
+struct MarchWin {
+    T wu[7], wv[7], wn[7], wmv[7], wnvp[7], wt[7], wep[3], wgy[5], wvx[5];
+};
+
+// Step s of one stage's march (compile-time after unrolling): phase 1 on
+// the row whose state (rho, m, n, E) is given, phase 2 on the row of step
+// s - 2 (s >= 4) and phase 3 on the row of step s - 4 (s >= 8), whose F(q)
+// is returned in k.
+template <int s, typename T, int W>
+__device__ __forceinline__ void march_stage_step(MarchRing<T, W> &L, MarchWin<T> &w, const int x,
+                                                 const int xn[4], T rho, T m, T n, T E, const NSCoef<T> &c,
+                                                 T k[4]) {
+    const NSPrim<T> pr = ns_prim(rho, m, n, E, c);
+    L.rx[s % 5][x] = NSrx<T>{m, pr.f1, pr.f2, pr.tt};
+    L.ru[s % 5][x] = NSuv<T>{pr.u, pr.v};
+    w.wu[s % 7] = pr.u;
+    w.wv[s % 7] = pr.v;
+    w.wn[s % 7] = n;
+    w.wmv[s % 7] = pr.mv;
+    w.wnvp[s % 7] = pr.nvp;
+    w.wt[s % 7] = pr.tt;
+    w.wep[s % 3] = pr.ep;
+    if constexpr (s >= 4) {
+        const NSuv<T> *r2 = L.ru[(s - 2) % 5];
+        const NSuv<T> q[4] = {r2[xn[0]], r2[xn[1]], r2[xn[2]], r2[xn[3]]};
+        const T xu[4] = {q[0].u, q[1].u, q[2].u, q[3].u}, xv[4] = {q[0].v, q[1].v, q[2].v, q[3].v};
+        const T yu[4] = {w.wu[(s - 4) % 7], w.wu[(s - 3) % 7], w.wu[(s - 1) % 7], w.wu[s % 7]};
+        const T yv[4] = {w.wv[(s - 4) % 7], w.wv[(s - 3) % 7], w.wv[(s - 1) % 7], w.wv[s % 7]};
+        const NSP2<T> r = ns_p2(xu, xv, yu, yv, w.wu[(s - 2) % 7], w.wv[(s - 2) % 7], w.wep[(s - 2) % 3], c);
+        L.rb[s % 3][x] = NSgd<T>{r.gx, r.uy};
+        w.wgy[s % 5] = r.gy;
+        w.wvx[s % 5] = r.vx;
+    }
+    if constexpr (s >= 8) {
+        const NSrx<T> *r3 = L.rx[(s - 4) % 5];
+        const NSuv<T> *u3 = L.ru[(s - 4) % 5];
+        const NSgd<T> *b3 = L.rb[(s - 2) % 3];
+        T xm[4], xf1[4], xf2[4], xg[4], xuy[4], xT[4], xu[4], xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const NSrx<T> a3 = r3[xn[j]];
+            const NSuv<T> w3 = u3[xn[j]];
+            const NSgd<T> g3 = b3[xn[j]];
+            xm[j] = a3.m;
+            xf1[j] = a3.f1;
+            xf2[j] = a3.f2;
+            xT[j] = a3.tt;
+            xu[j] = w3.u;
+            xv[j] = w3.v;
+            xg[j] = g3.g;
+            xuy[j] = g3.d;
+        }
+        const T yn[4] = {w.wn[(s - 6) % 7], w.wn[(s - 5) % 7], w.wn[(s - 3) % 7], w.wn[(s - 2) % 7]};
+        const T ymv[4] = {w.wmv[(s - 6) % 7], w.wmv[(s - 5) % 7], w.wmv[(s - 3) % 7], w.wmv[(s - 2) % 7]};
+        const T ynvp[4] = {w.wnvp[(s - 6) % 7], w.wnvp[(s - 5) % 7], w.wnvp[(s - 3) % 7], w.wnvp[(s - 2) % 7]};
+        const T yT[4] = {w.wt[(s - 6) % 7], w.wt[(s - 5) % 7], w.wt[(s - 3) % 7], w.wt[(s - 2) % 7]};
+        const T yu[4] = {w.wu[(s - 6) % 7], w.wu[(s - 5) % 7], w.wu[(s - 3) % 7], w.wu[(s - 2) % 7]};
+        const T yv[4] = {w.wv[(s - 6) % 7], w.wv[(s - 5) % 7], w.wv[(s - 3) % 7], w.wv[(s - 2) % 7]};
+        const T yg[4] = {w.wgy[(s - 4) % 5], w.wgy[(s - 3) % 5], w.wgy[(s - 1) % 5], w.wgy[s % 5]};
+        const T yvx[4] = {w.wvx[(s - 4) % 5], w.wvx[(s - 3) % 5], w.wvx[(s - 1) % 5], w.wvx[s % 5]};
+        ns_p3(xm, xf1, xf2, xg, xuy, xT, xu, xv, yn, ymv, ynvp, yg, yvx, yT, yu, yv, w.wu[(s - 4) % 7],
+              w.wv[(s - 4) % 7], w.wt[(s - 4) % 7], c, k);
+    }
+}
+
+// PAIR 0: sin_ = q; writes acc, s2out and (if prev) x_{k-1} = q at the
+// owned rows.  PAIR 1: sin_ = s2, q0 = q, acc read; writes qout (!= q0).
+template <typename T, int W, int PAIR>
+__global__ __launch_bounds__(W, 2) void ns_march_pair(const T *__restrict__ sin_, const T *__restrict__ q0,
+                                                   T *__restrict__ acc, T *__restrict__ s2out,
+                                                   T *__restrict__ qout, T *__restrict__ prev, int ny, int segs,
+                                                   int total_blocks, NSCoef<T> c) {
+    constexpr int R = PAIR_ROWS, NIT = R + 16;
+    __shared__ MarchRing<T, W> LA, LB;
+    const int lb = xcd_remap(blockIdx.x, total_blocks);
+    const int member = lb / segs;
+    const int y0 = (lb - member * segs) * R;
+    const int x = threadIdx.x;
+    const int xn[4] = {x >= 2 ? x - 2 : x - 2 + W, x >= 1 ? x - 1 : x - 1 + W, x + 1 < W ? x + 1 : x + 1 - W,
+                       x + 2 < W ? x + 2 : x + 2 - W};
+    const int nxy = W * ny;
+    const long long mbase = (long long)member * 4 * nxy;
+    const uint32_t mbytes = 4u * (uint32_t)nxy * sizeof(T);
+    const int fstride = nxy * (int)sizeof(T);
+    const buf_t b_in = buf_rsrc(sin_ + mbase, mbytes);
+    const buf_t b_q = buf_rsrc((PAIR == 0 ? sin_ : q0) + mbase, mbytes);
+    const buf_t b_acc = buf_rsrc(acc + mbase, mbytes);
+    const buf_t b_s2 = buf_rsrc((PAIR == 0 ? s2out : acc) + mbase, mbytes);
+    const buf_t b_out = buf_rsrc((PAIR == 1 ? qout : acc) + mbase, mbytes);
+    const buf_t b_prev = buf_rsrc(prev ? prev + mbase : sin_, mbytes);
+    // byte offset of (row a mod ny, column x); a in [-16, ny + 15]
+    auto voff = [&](int a) {
+        a = a < 0 ? a + ny : (a >= ny ? a - ny : a);
+        return (a * W + x) * (int)sizeof(T);
+    };
+    MarchWin<T> wa, wb;
+    // Rings indexed by step: A's input rows (6 slots: loaded one step
+    // ahead, and in pair 0 also the q of A's combination four steps after
+    // its load); the q rows of A's combination (pair 1; 6 slots: loaded
+    // one step ahead, read again by B's combination four steps later);
+    // A's outputs (5 slots, B's combination four steps later); the
+    // operand of B's combination loaded one step ahead (q in pair 0, acc
+    // in pair 1).  A slot is reloaded only after its last read.
+    T ld[6][4], qa[6][4], sa[5][4], pb[2][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) ld[0][f] = buf_load<T>(b_in, voff(y0 - 8), f * fstride);
+    static_for<0, NIT>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        const int a = y0 - 8 + t;
+        // loads that go out before this step's arithmetic: A's next input
+        // row; (pair 1) the q row of A's combination next step; the
+        // operands of B's combination next step
+        if constexpr (t + 1 < NIT) {
+            const int vo = voff(a + 1);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) ld[(t + 1) % 6][f] = buf_load<T>(b_in, vo, f * fstride);
+        }
+        if constexpr (PAIR == 1 && t >= 7 && t + 1 < NIT) {
+            const int vo = voff(y0 - 11 + t);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) qa[(t + 1) % 6][f] = buf_load<T>(b_q, vo, f * fstride);
+        }
+        if constexpr (t >= 15 && t + 1 < NIT) {
+            const int vo = voff(y0 - 15 + t);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) pb[(t + 1) & 1][f] = buf_load<T>(PAIR == 0 ? b_q : b_acc, vo, f * fstride);
+        }
+        if constexpr (PAIR == 0 && t >= 8 && t < R + 8) {
+            if (prev != nullptr) {
+                const int vo = voff(a);
+#pragma unroll
+                for (int f = 0; f < 4; ++f) buf_store(ld[t % 6][f], b_prev, vo, f * fstride);
+            }
+        }
+        T kA[4], kB[4];
+        march_stage_step<t>(LA, wa, x, xn, ld[t % 6][0], ld[t % 6][1], ld[t % 6][2], ld[t % 6][3], c, kA);
+        if constexpr (t >= 8) {
+            // A's output row y0 - 12 + t (its input was loaded for step t - 4)
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                T o1 = T(0), o2 = T(0);
+                if constexpr (PAIR == 0)
+                    ns_epilogue<T, ST1>(kA[f], ld[(t - 4) % 6][f], T(0), T(0), c, o1, o2);
+                else
+                    ns_epilogue<T, ST3>(kA[f], qa[t % 6][f], T(0), T(0), c, o1, o2);
+                sa[t % 5][f] = o1;
+            }
+            march_stage_step<t - 8>(LB, wb, x, xn, sa[t % 5][0], sa[t % 5][1], sa[t % 5][2], sa[t % 5][3], c, kB);
+        }
+        if constexpr (t >= 16) {
+            // B's output row y0 - 16 + t
+            const int vo = voff(y0 - 16 + t);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int so = f * fstride;
+                T o1 = T(0), o2 = T(0);
+                if constexpr (PAIR == 0) {
+                    // stage 2: a0 = s1, a1 = q
+                    ns_epilogue<T, ST2>(kB[f], sa[(t - 4) % 5][f], pb[t & 1][f], T(0), c, o1, o2);
+                    buf_store(o1, b_acc, vo, so);
+                    buf_store(o2, b_s2, vo, so);
+                } else {
+                    // stage 4: a0 = acc, a1 = q, a2 = s3
+                    ns_epilogue<T, ST4>(kB[f], pb[t & 1][f], qa[(t - 4) % 6][f], sa[(t - 4) % 5][f], c, o1, o2);
+                    buf_store(o1, b_out, vo, so);
+                }
+            }
+        }
+        __syncthreads();
+    });
+}
+
+// Plain copy of n elements (the odd step of the paired schedule ends in
+// the second array).
+template <typename T>
+__global__ __launch_bounds__(256) void copy_state(const T *__restrict__ src, T *__restrict__ dst, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 template <typename T>
 static NSCoef<T> ns_coef(const Plan &p, int level, double alpha) {
     const int nx = level == MENKF_FINE ? p.nx : p.nxc;
@@ -632,6 +841,54 @@ struct MarchLauncher {
     }
 };
 
+// Paired row-march schedule: rows of W = nx points (64 to 256) and ny a
+// multiple of the 32 rows of a workgroup (FP32).
+static bool pair_shape_ok(int nx, int ny) {
+    return (nx == 64 || nx == 128 || nx == 192 || nx == 256) && ny % PAIR_ROWS == 0 && ny >= PAIR_ROWS;
+}
+
+template <typename T, int W>
+struct PairLauncher {
+    template <int PAIR>
+    static hipError_t pair(const T *s, const T *q0, T *acc, T *s2out, T *qout, T *prev, int ny, int nb,
+                           const NSCoef<T> &c, hipStream_t st) {
+        const int segs = ny / PAIR_ROWS;
+        const int total = segs * nb;
+        hipLaunchKernelGGL((ns_march_pair<T, W, PAIR>), dim3(total), dim3(W), 0, st, s, q0, acc, s2out, qout, prev,
+                           ny, segs, total, c);
+        return hipGetLastError();
+    }
+    // q alternates between the state and the s1 array (not needed by this
+    // schedule) step by step; an odd step count ends with one copy back.
+    static hipError_t forecast(T *state, T *s1, T *s2, T *acc, T *prev, int ny, int nb, int nsteps, int chunk,
+                               const NSCoef<T> &c, hipStream_t st) {
+        hipError_t e = hipSuccess;
+        const long long msz = 4LL * W * ny;
+        if (chunk < 1 || chunk > nb) chunk = nb;
+        for (int m0 = 0; m0 < nb && e == hipSuccess; m0 += chunk) {
+            const int cb = nb - m0 < chunk ? nb - m0 : chunk;
+            T *const home = state + m0 * msz;
+            T *q = home, *alt = s1 + m0 * msz;
+            T *a = acc + m0 * msz, *t2 = s2 + m0 * msz;
+            T *pchunk = prev ? prev + m0 * msz : nullptr;
+            for (int step = 0; step < nsteps && e == hipSuccess; ++step) {
+                T *pv = step == nsteps - 1 ? pchunk : nullptr;
+                e = pair<0>(q, nullptr, a, t2, nullptr, pv, ny, cb, c, st);
+                if (e == hipSuccess) e = pair<1>(t2, q, a, nullptr, alt, nullptr, ny, cb, c, st);
+                T *tmp = q;
+                q = alt;
+                alt = tmp;
+            }
+            if (e == hipSuccess && q != home) {
+                const long long n = (long long)cb * msz;
+                hipLaunchKernelGGL((copy_state<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, q, home, n);
+                e = hipGetLastError();
+            }
+        }
+        return e;
+    }
+};
+
 template <typename T, int TX, int TY>
 struct NSLauncher {
     template <int MODE>
@@ -673,10 +930,11 @@ struct NSLauncher {
 // workgroup: (2 (TX+8)(TY+8) + 8 (TX+4)(TY+4) + 4) elements, e.g. 30.7 KB
 // for 32 x 16 in FP32 (five workgroups per compute unit).  The first entry
 // of each list is the default.
-// The last FP32 entry, 0 x 16, is the row-march schedule (whole rows of
-// 64 to 256 points, 16 rows per workgroup); on other grids it runs the
-// default tile.
-static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}, {0, MARCH_ROWS}};
+// The last FP32 entries are the row-march schedules (whole rows of 64 to
+// 256 points): 0 x 16, one RK stage per launch and 16 rows per workgroup;
+// 0 x 32, two stages per launch and 32 rows per workgroup.  On other grids
+// they run the default tile.
+static const int kTilesF32[][2] = {{32, 16}, {64, 8}, {32, 8}, {16, 16}, {64, 4}, {0, MARCH_ROWS}, {0, PAIR_ROWS}};
 static const int kTilesF64[][2] = {{32, 8}, {16, 8}, {16, 16}, {64, 4}};
 
 int ns_tile_count(int precision) {
@@ -690,9 +948,10 @@ void ns_tile_shape(int precision, int i, int *tx, int *ty) {
     *ty = tab[i][1];
 }
 
-bool ns_march_applies(const Plan &p, int level) {
-    return p.dim == 2 && p.cfg.precision == MENKF_F32 &&
-           march_shape_ok(level == MENKF_FINE ? p.nx : p.nxc, level == MENKF_FINE ? p.ny : p.nyc);
+bool ns_march_applies(const Plan &p, int level, int rows) {
+    const int nx = level == MENKF_FINE ? p.nx : p.nxc, ny = level == MENKF_FINE ? p.ny : p.nyc;
+    if (p.dim != 2 || p.cfg.precision != MENKF_F32) return false;
+    return rows == PAIR_ROWS ? pair_shape_ok(nx, ny) : rows == MARCH_ROWS && march_shape_ok(nx, ny);
 }
 
 int ns_tile_index(int precision, int tx, int ty) {
@@ -723,6 +982,7 @@ static hipError_t with_tile(int ti, const Fn &f) {
         case 3: return f.template run<16, 16>();
         case 4: return f.template run<64, 4>();
         case 5: return f.run_march();
+        case 6: return f.run_march_pair();
         default: return f.template run<32, 16>();
         }
     }
@@ -750,6 +1010,17 @@ struct NSForecastFn {
         }
         return run<32, 16>();
     }
+    hipError_t run_march_pair() const {
+        if (sizeof(T) == 4 && pair_shape_ok(nx, ny)) {
+            switch (nx) {
+            case 64: return PairLauncher<T, 64>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            case 128: return PairLauncher<T, 128>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            case 192: return PairLauncher<T, 192>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            default: return PairLauncher<T, 256>::forecast(state, s1, s2, acc, prev, ny, nb, nsteps, chunk, c, s);
+            }
+        }
+        return run<32, 16>();
+    }
 };
 
 template <typename TT, int MODE>
@@ -766,6 +1037,7 @@ struct NSSingleFn {
         return NSLauncher<T, TX, TY>::template stage<MODE>(x, xp, nullptr, nullptr, out, nullptr, nx, ny, 1, c, info, s);
     }
     hipError_t run_march() const { return run<32, 16>(); }   // sweeps and residuals use the tile kernel
+    hipError_t run_march_pair() const { return run<32, 16>(); }
 };
 
 static int sched_tile(const Plan &p, int level) {

@@ -70,6 +70,14 @@ def test_mfma_lane_layouts():
     assert lib.menkf_test_mfma(1, ctypes.c_void_p(ad.data_ptr()), ctypes.c_void_p(bd.data_ptr()),
                                ctypes.c_void_p(o64.data_ptr()), s) == 0
     np.testing.assert_allclose(o64.cpu().numpy(), (a64 @ b64).numpy(), rtol=1e-14, atol=1e-14)
+    a16 = torch.randint(-4, 5, (16, 32), generator=g).to(torch.bfloat16)
+    b16 = torch.randint(-4, 5, (32, 16), generator=g).to(torch.bfloat16)
+    o16 = torch.zeros((16, 16), dtype=torch.float32, device="cuda")
+    ad, bd = a16.cuda().contiguous(), b16.cuda().contiguous()
+    say("mfma layout bf16 16x16x32")
+    assert lib.menkf_test_mfma(2, ctypes.c_void_p(ad.data_ptr()), ctypes.c_void_p(bd.data_ptr()),
+                               ctypes.c_void_p(o16.data_ptr()), s) == 0
+    np.testing.assert_array_equal(o16.cpu().numpy(), (a16.float() @ b16.float()).numpy())
 
 
 # ------------------------------------------------------------------ forecasts
@@ -143,12 +151,14 @@ def test_forecast_c3_shapes_f32():
     g = to_np(mem_d)
     for i in range(cfg.n_members):
         assert rel_l2(g[i], o_m[i]) < 1e-5, i
-    # the row-march schedule of the coarse level: the same forecast, bitwise
-    ctx.set_schedule(1, (0, 16), 0)
-    mem2 = to_dev(mem, F32)
-    say("  coarse level again with the row-march schedule")
-    ctx.forecast(1, mem2, cfg.n_obs)
-    np.testing.assert_array_equal(to_np(mem2), g)
+    # the row-march schedules of the coarse level (one and two RK stages
+    # per launch): the same forecast, bitwise
+    for tile in ((0, 16), (0, 32)):
+        ctx.set_schedule(1, tile, 0)
+        mem2 = to_dev(mem, F32)
+        say(f"  coarse level again with the row-march schedule {tile}")
+        ctx.forecast(1, mem2, cfg.n_obs)
+        np.testing.assert_array_equal(to_np(mem2), g)
 
 
 def test_forecast_conserves_totals_f64():

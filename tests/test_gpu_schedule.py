@@ -13,7 +13,7 @@ from tests.gpu_helpers import make_ctx, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TILES = {"f32": [(32, 16), (64, 8), (32, 8), (16, 16), (64, 4), (0, 16)],
+TILES = {"f32": [(32, 16), (64, 8), (32, 8), (16, 16), (64, 4), (0, 16), (0, 32)],
          "f64": [(32, 8), (16, 8), (16, 16), (64, 4)]}
 
 
@@ -88,7 +88,9 @@ def test_autotune_picks_a_listed_schedule_and_keeps_results():
 @pytest.mark.parametrize("side", [(256, 256), (512, 256), (768, 768)], ids=["coarse64x64", "coarse128x64",
                                                                             "coarse192x192"])
 def test_row_march_is_bitwise_equal_to_the_tile_kernel(side):
-    """Grids whose coarse rows the row-march schedule (0 x 16) takes whole:
+    """Grids whose coarse rows the row-march schedules take whole (0 x 16:
+    one RK stage per launch; 0 x 32: two stages per launch, the state
+    alternating with a second array, so odd step counts end with a copy):
     forecasts of every member and x_{k-1}, with and without member chunks,
     bitwise equal to the default tile's."""
     nx, ny = side
@@ -96,7 +98,7 @@ def test_row_march_is_bitwise_equal_to_the_tile_kernel(side):
     ctx, _, _ = make_ctx(cfg)
     mem0 = to_dev(fields.member_ics(cfg), torch.float32)
     outs = []
-    for tile, chunk in (((32, 16), 0), ((0, 16), 0), ((0, 16), 2)):
+    for tile, chunk in (((32, 16), 0), ((0, 16), 0), ((0, 16), 2), ((0, 32), 0), ((0, 32), 2)):
         say(f"row march {nx}x{ny}: coarse tile {tile} chunk {chunk}")
         ctx.set_schedule(1, tile, chunk)
         m = mem0.clone()
