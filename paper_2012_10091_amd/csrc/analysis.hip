@@ -908,6 +908,119 @@ __global__ __launch_bounds__(256) void update_bf16(float *__restrict__ X, float 
     }
 }
 
+// The same update with every wave on its own 32 points and no LDS: lane l
+// loads point l % 32 of the NPAD / 2 members k = 16 ks + 8 (l / 32) + e
+// (ks < NPAD / 16, e < 8), exactly the members of its MFMA B fragments.
+// The FP64 mean and delta^C are each lane's sum over its members plus the
+// partner lane's (l ^ 32); of the 16 states a lane writes per output tile,
+// half are its own loads and half its partner's (one lane swap each).
+// Used for NPAD <= 128 (the fragments then fit the registers).
+template <int NPAD, int TERMS>
+__global__ __launch_bounds__(256, NPAD <= 96 ? 4 : 2) void update_wave(float *__restrict__ X, float *__restrict__ dc,
+                                                   const __bf16 *__restrict__ zt, const double *__restrict__ zstar,
+                                                   int N, long long npts, float scale,
+                                                   const int32_t *__restrict__ info) {
+    constexpr int KS = NPAD / 16;
+    if (*info != 0) return;
+    const int l = threadIdx.x & 63, h = l >> 5;
+    const long long pbase = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    const long long pt = pbase + (l & 31);
+    const bool pin = pt < npts;
+    const unsigned off0 = (unsigned)(pin ? pt : 0);
+    const unsigned off8 = off0 + (unsigned)(8 * h) * (unsigned)npts;
+    // loads: member row 16 ks + e is a uniform base, the lane part an
+    // offset (the lane's member is 16 ks + e + 8 h); a member past N reads
+    // member 16 ks + e (upper half of the wave) or member 0 (both halves)
+    // instead, and the value is discarded below
+    float v[KS][8];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k0 = ks * 16 + e;
+            const float *row = X + (long long)(k0 < N ? k0 : 0) * npts;
+            v[ks][e] = row[k0 + 8 < N ? off8 : off0];
+        }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (!(ks * 16 + e + 8 * h < N && pin)) v[ks][e] = 0.0f;
+    // FP64 mean and delta^C = sum_k (x^(k) - mean) scale z*_k
+    double sm = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sm += (double)v[ks][e];
+    sm += __shfl_xor(sm, 32);
+    const double m = sm / (double)N;
+    const double sc = (double)scale;
+    double d = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = ks * 16 + e + 8 * h;
+            if (k < N) d += ((double)v[ks][e] - m) * sc * zstar[k];
+        }
+    d += __shfl_xor(d, 32);
+    if (h == 0 && pin) dc[pt] = (float)d;
+    // B fragments: anomalies (x - mean) scale, as BF16 (and the BF16 residue)
+    const float mp = (float)m;
+    bf16x8 bfrag[KS];
+    bf16x8 bfrag_lo[TERMS == 3 ? KS : 1];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float a = ks * 16 + e + 8 * h < N ? (v[ks][e] - mp) * scale : 0.0f;
+            const __bf16 hi = (__bf16)a;
+            bfrag[ks][e] = hi;
+            if constexpr (TERMS == 3) bfrag_lo[ks][e] = (__bf16)(a - (float)hi);
+        }
+    constexpr int KG = KS % 4 == 0 ? 4 : 2;
+#pragma unroll
+    for (int mt = 0; mt < NPAD / 32; ++mt) {
+        f32x16 acc = {};
+        const __bf16 *za = zt + (long long)(mt * 32 + (l & 31)) * NPAD + h * 8;
+#pragma unroll
+        for (int k0 = 0; k0 < KS; k0 += KG) {
+            bf16x8 a[KG], alo[TERMS == 3 ? KG : 1];
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                a[g] = *reinterpret_cast<const bf16x8 *>(za + (k0 + g) * 16);
+                if constexpr (TERMS == 3) alo[g] = *reinterpret_cast<const bf16x8 *>(za + NPAD * NPAD + (k0 + g) * 16);
+            }
+#pragma unroll
+            for (int g = 0; g < KG; ++g) {
+                const int ks = k0 + g;
+                if constexpr (TERMS == 3) {
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[g], bfrag[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[g], bfrag_lo[ks], acc, 0, 0, 0);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[g], bfrag[ks], acc, 0, 0, 0);
+            }
+        }
+        // element 4 g + i of the tile: member j = 32 mt + 8 g + 4 h + i, i.e.
+        // block ks = 2 mt + g / 2 at offset 8 (g & 1) + 4 h + i, which the
+        // lane half g & 1 loaded as its v[ks][4 h + i]: the lane's own value
+        // when g & 1 == h, otherwise the partner's (every lane sends its
+        // v[ks][4 (1 - h) + i], the index its partner needs)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int ks = 2 * mt + (g >> 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float mine = h ? v[ks][4 + i] : v[ks][i];
+                const float other = __shfl_xor(h ? v[ks][i] : v[ks][4 + i], 32);
+                const float x = ((g & 1) == h) ? mine : other;
+                const int j = mt * 32 + 8 * g + 4 * h + i;
+                if (j < N && pin) X[(long long)j * npts + pt] = x + acc[4 * g + i];
+            }
+        }
+    }
+}
+
 // FP64 update for MENKF_F64 contexts, in two passes so that both are
 // parallel over points and members alike (the in-place update of member j
 // must not overwrite x^(j) while other workgroups still read it for the
@@ -1220,6 +1333,14 @@ hipError_t launch_get_gain(const Plan &p, double *z, void *ws, hipStream_t s) {
 template <int NPAD>
 static void launch_update_np(const Plan &p, dim3 grid, hipStream_t s, float *X, float *dc, const __bf16 *zt,
                              const double *zs, long long npts, float scale, const int32_t *info) {
+    if constexpr (NPAD <= 128) {
+        // 128 points per workgroup, as the staged kernel's grid
+        if (p.cfg.anomaly_terms == 1)
+            hipLaunchKernelGGL((update_wave<NPAD, 1>), grid, dim3(256), 0, s, X, dc, zt, zs, p.N, npts, scale, info);
+        else
+            hipLaunchKernelGGL((update_wave<NPAD, 3>), grid, dim3(256), 0, s, X, dc, zt, zs, p.N, npts, scale, info);
+        return;
+    }
     if (p.cfg.anomaly_terms == 1)
         hipLaunchKernelGGL((update_bf16<NPAD, 1>), grid, dim3(256), 0, s, X, dc, zt, zs, p.N, npts, scale, info);
     else

@@ -11,10 +11,12 @@
 // Inference: one workgroup per 16x16 output tile.  The loader computes
 // Pi_F(delta^C) on the fly (the same device function as the plain
 // prolongation) on the tile plus a halo of 3; the three layers run as
-// implicit GEMMs on v_mfma_f32_32x32x16_bf16 with output channels as the M
-// dimension, 32 pixels as N, and K = (tap, input channel) with channels
-// fastest, so each lane's 8 K-values are 8 consecutive channels of one tap
-// of one pixel: a single 16-byte LDS read from the channel-last activations.
+// implicit GEMMs on BF16 MFMA with output channels as the M dimension,
+// pixels as N, and K = (tap, input channel) with channels fastest, so each
+// lane's 8 K-values are 8 consecutive channels of one tap of one pixel: a
+// single 16-byte LDS read from the activations, stored as planes of 8-channel
+// chunks.  Layers 1 and 2 use v_mfma_f32_32x32x16_bf16 (32 output channels),
+// layer 3 v_mfma_f32_16x16x32_bf16 (4 output channels in a 16-row tile).
 #include "common.hpp"
 
 namespace menkf {
@@ -58,62 +60,99 @@ __device__ __forceinline__ bf16x8 zero_bf16x8() {
     return z;
 }
 
-// 32-channel pixel records in LDS: the four 16-byte chunks of 8 channels
-// of pixel p sit at chunk position q ^ ((p >> 2) & 3), so that the 16 lanes
-// of an MFMA operand read that fetch the same chunk of 16 consecutive
-// pixels (records 64 bytes apart) cover 16 distinct 4-bank groups.
-__device__ __forceinline__ int chunk_pos(int pix, int q) { return (q ^ ((pix >> 2) & 3)) * 8; }
+// Activations in LDS as channel-chunk planes: the 8 channels of chunk q of
+// pixel p (16 bytes, BF16) at byte q * PLANE + 16 p, PLANE = 16 * pixels of
+// the layer.  The 32 lanes of an MFMA operand read fetch the same chunk of
+// consecutive pixels, i.e. one contiguous 512-byte run (no bank
+// conflicts), and every tap of a pixel group is at a compile-time offset
+// from one per-lane base address.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-// One conv layer from LDS activations act_in ([RIN*RIN][IC], BF16; 32
-// channels in swizzled chunks) to act_out ([ROUT*ROUT][32], BF16 swizzled,
-// bias + ReLU).  Waves take 32-pixel groups round-robin.
+template <int RIN>
+__device__ __forceinline__ constexpr int tap_off(int tap) {   // pixel offset of a 3x3 tap
+    return (tap / 3) * RIN + tap % 3;
+}
+
+// One conv layer from act_in (IC channels: IC / 8 planes of RIN * RIN
+// pixels) to act_out (32 channels: 4 planes of ROUT * ROUT pixels), bias +
+// ReLU.  Output channels are the M dimension of v_mfma_f32_32x32x16_bf16,
+// 32 pixels the N dimension, K = (tap, input channel) with channels
+// fastest.  Each wave takes two 32-pixel groups at a time (nt and nt + 4),
+// so two independent accumulator chains interleave on the matrix unit.
 template <int IC, int RIN, int ROUT>
-__device__ __forceinline__ void conv_layer(const __bf16 *act_in, __bf16 *act_out, const __bf16 *__restrict__ wk,
-                                           const float *__restrict__ bias, int wave, int lane) {
+__device__ __forceinline__ void conv_layer(const unsigned char *act_in, unsigned char *act_out,
+                                           const __bf16 *__restrict__ wk, const float *__restrict__ bias, int wave,
+                                           int lane) {
     constexpr int K = 9 * IC;
     constexpr int KCH = (K + 15) / 16;
     constexpr int NPIX = ROUT * ROUT;
+    constexpr int PIN = RIN * RIN * 16, POUT = NPIX * 16;
+    constexpr int NG = (NPIX + 31) / 32;
+    const int half = lane >> 5;
     bf16x8 a[KCH];
 #pragma unroll
     for (int ks = 0; ks < KCH; ++ks) {
-        const int kb = ks * 16 + (lane >> 5) * 8;
+        const int kb = ks * 16 + half * 8;
         a[ks] = kb < K ? *reinterpret_cast<const bf16x8 *>(wk + (lane & 31) * K + kb) : zero_bf16x8();
     }
     float bv[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) bv[e] = bias[8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)];
-    for (int nt = wave; nt * 32 < NPIX; nt += 4) {
-        const int n = nt * 32 + (lane & 31);
-        const bool valid = n < NPIX;
-        const int nn = valid ? n : 0;
-        const int py = nn / ROUT, px = nn - py * ROUT;
-        f32x16 acc = {};
+    for (int e = 0; e < 16; ++e) bv[e] = bias[8 * (e >> 2) + 4 * half + (e & 3)];
+    for (int nt = wave; nt < NG; nt += 8) {
+        const bool two = nt + 4 < NG;   // uniform per wave
+        int n[2];
+        const unsigned char *src[2];
+        bool valid[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            n[h] = (nt + 4 * h) * 32 + (lane & 31);
+            valid[h] = n[h] < NPIX;
+            const int nn = valid[h] ? n[h] : 0;
+            const int py = nn / ROUT, px = nn - py * ROUT;
+            // IC = 32: lane half h5 reads chunk 2 (ks & 1) + h5 of tap ks / 2;
+            // IC = 8: one plane, lane half h5 reads tap 2 ks + h5
+            src[h] = act_in + 16 * (py * RIN + px) + (IC == 32 ? half * PIN : half * 16 * tap_off<RIN>(1));
+        }
+        f32x16 acc[2] = {{}, {}};
 #pragma unroll
         for (int ks = 0; ks < KCH; ++ks) {
-            const int kb = ks * 16 + (lane >> 5) * 8;
-            bf16x8 b;
-            if (kb < K) {
-                const int tap = kb / IC, ic0 = kb - tap * IC;
-                const int pix = (py + tap / 3) * RIN + (px + tap % 3);
-                const int off = IC == 32 ? chunk_pos(pix, ic0 >> 3) : ic0;
-                b = *reinterpret_cast<const bf16x8 *>(act_in + pix * IC + off);
-            } else {
-                b = zero_bf16x8();
+            bf16x8 b[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if constexpr (IC == 32) {
+                    b[h] = *reinterpret_cast<const bf16x8 *>(src[h] + (ks & 1) * 2 * PIN + 16 * tap_off<RIN>(ks >> 1));
+                } else {
+                    // taps 2 ks (first half) and 2 ks + 1 (second half, whose base
+                    // carries tap_off(1)); the padding tap 9 (zero weights) reads
+                    // tap 1's finite values
+                    const int t1 = 2 * ks + 1 < 9 ? 2 * ks + 1 : 1;
+                    const int o = half ? 16 * (tap_off<RIN>(t1) - tap_off<RIN>(1)) : 16 * tap_off<RIN>(2 * ks);
+                    b[h] = *reinterpret_cast<const bf16x8 *>(src[h] + o);
+                }
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b[0], acc[0], 0, 0, 0);
+            if (two) acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b[1], acc[1], 0, 0, 0);
         }
-        if (valid) {
+        // element e of lane l: channel 8 (e >> 2) + 4 (l >> 5) + (e & 3), pixel
+        // l & 31 of the group: 4 consecutive channels of chunk e >> 2, one
+        // 8-byte store per chunk
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                __bf16 *dst = act_out + n * 32 + chunk_pos(n, g) + 4 * (lane >> 5);
+        for (int h = 0; h < 2; ++h) {
+            if (valid[h] && (h == 0 || two)) {
+                unsigned char *dst = act_out + 16 * n[h] + 8 * half;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) dst[i] = (__bf16)fmaxf(acc[4 * g + i] + bv[4 * g + i], 0.0f);
+                for (int g = 0; g < 4; ++g) {
+                    bf16x4 v;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = (__bf16)fmaxf(acc[h][4 * g + i] + bv[4 * g + i], 0.0f);
+                    *reinterpret_cast<bf16x4 *>(dst + g * POUT) = v;
+                }
             }
         }
     }
 }
 
-__global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__ dc, const float *__restrict__ xf,
+__global__ __launch_bounds__(256, 3) void net_prolong_fwd(const float *__restrict__ dc, const float *__restrict__ xf,
                                                        float *__restrict__ xout, const __bf16 *__restrict__ wk,
                                                        const float *__restrict__ prm, NetConst nc, int nx, int ny,
                                                        int r, int nxc, int nyc, int tiles_x, int total_tiles,
@@ -135,8 +174,8 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
     __shared__ __align__(16) unsigned char lds_net[REG_A + REG_B + 4 * NP3 * 4];
     __bf16 *in0 = reinterpret_cast<__bf16 *>(lds_net);
     float (*cwin)[CWMAX][CWMAX] = reinterpret_cast<float (*)[CWMAX][CWMAX]>(lds_net + IN0_B);
-    __bf16 *act2 = reinterpret_cast<__bf16 *>(lds_net);
-    __bf16 *act1 = reinterpret_cast<__bf16 *>(lds_net + REG_A);
+    unsigned char *act2 = lds_net;
+    unsigned char *act1 = lds_net + REG_A;
     float (*outb)[NP3] = reinterpret_cast<float (*)[NP3]>(lds_net + REG_A);
     float (*red)[4] = reinterpret_cast<float (*)[4]>(lds_net + REG_A + OUTB_B);
     float (*dps)[NP3] = reinterpret_cast<float (*)[NP3]>(lds_net + REG_A + REG_B);
@@ -144,7 +183,11 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
     // origin cx0, cy0; at most CWMAX points per side for r >= 1) and the
     // Lagrange weights of the r sub-positions
     __shared__ float wts[64][4];
-    __shared__ int s_fx[R0], s_fy[R0];   // periodic fine column / row offset
+    // per fine column (row) of the tile + halo: window column (row) of its
+    // first stencil point and its sub-position; periodic coarse column (row)
+    // of every window column (row)
+    __shared__ int s_bx[R0], s_px[R0], s_by[R0], s_py[R0];
+    __shared__ int s_wc[CWMAX], s_wr[CWMAX];
     if (*info != 0) return;
     const int lb = xcd_remap(blockIdx.x, total_tiles);
     const int y0 = (lb / tiles_x) * NT, x0 = (lb % tiles_x) * NT;
@@ -156,67 +199,141 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
     const int cx0 = fdiv(x0 - 3, r) - 1, cy0 = fdiv(y0 - 3, r) - 1;
     const int cwx = fdiv(x0 + NT + 2, r) + 3 - cx0, cwy = fdiv(y0 + NT + 2, r) + 3 - cy0;   // <= 25
     if (tid < r) lagrange4<float>(float(tid) / float(r), wts[tid]);
-    if (tid < R0) s_fx[tid] = wrap(x0 - 3 + tid, nx);
-    else if (tid >= 64 && tid < 64 + R0) s_fy[tid - 64] = wrap(y0 - 3 + tid - 64, ny) * nx;
-    for (int e = tid; e < 4 * cwx * cwy; e += 256) {
-        const int f = e / (cwx * cwy), rem = e - f * cwx * cwy, wy = rem / cwx, wx = rem - wy * cwx;
-        cwin[f][wy][wx] = dc[f * ncp + (long long)wrap(cy0 + wy, nyc) * nxc + wrap(cx0 + wx, nxc)];
+    if (tid < R0) {
+        const int X = x0 - 3 + tid, jx = fdiv(X, r);
+        s_bx[tid] = jx - 1 - cx0;
+        s_px[tid] = X - jx * r;
+    } else if (tid >= 64 && tid < 64 + R0) {
+        const int Y = y0 - 3 + tid - 64, jy = fdiv(Y, r);
+        s_by[tid - 64] = jy - 1 - cy0;
+        s_py[tid - 64] = Y - jy * r;
+    } else if (tid >= 128 && tid < 128 + CWMAX) {
+        s_wc[tid - 128] = wrap(cx0 + tid - 128, nxc);
+    } else if (tid >= 192 && tid < 192 + CWMAX) {
+        s_wr[tid - 192] = wrap(cy0 + tid - 192, nyc) * nxc;
+    }
+    // the tile's global reads go out together, before any is used: x^F_f at
+    // the thread's (at most two) pixels of the tile + halo and at its output
+    // pixel, and the coarse window (32 threads per window row, 8 rows per
+    // pass; rows wy = r8 + 8 i, at most CWMAX / 8 + 1 of them)
+    // periodic index of a tile + halo coordinate, in [-3, n + 17]: one
+    // conditional period on grids of at least 24 points, the full wrap below
+    const bool big = nx >= 24 && ny >= 24;
+    auto wrapc = [big](int v, int n) { return big ? (v < 0 ? v + n : (v >= n ? v - n : v)) : wrap(v, n); };
+    float xin[2][4], xo[4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int p = min(tid + 256 * k, NP0 - 1);
+        const int py = p / R0, px = p - py * R0;
+        const long long g = (long long)wrapc(y0 - 3 + py, ny) * nx + wrapc(x0 - 3 + px, nx);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) xin[k][f] = xf[f * nf + g];
+    }
+    {
+        const int py = tid / NT, px = tid - py * NT;
+        const long long g = (long long)min(y0 + py, ny - 1) * nx + min(x0 + px, nx - 1);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) xo[f] = xf[f * nf + g];
     }
     __syncthreads();
+    const int c32 = tid & 31, r8 = tid >> 5;
+    constexpr int WR = (CWMAX + 7) / 8;
+    float wv[4][WR];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int i = 0; i < WR; ++i) {
+            const int wy = min(r8 + 8 * i, cwy - 1), wx = min(c32, cwx - 1);
+            wv[f][i] = dc[f * ncp + s_wr[wy] + s_wc[wx]];
+        }
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int i = 0; i < WR; ++i)
+            if (r8 + 8 * i < cwy && c32 < cwx) cwin[f][r8 + 8 * i][c32] = wv[f][i];
+    __syncthreads();
 
-    for (int p = tid; p < NP0; p += 256) {
+    // Pi_F(delta^C) on the tile + halo, separably: the coarse window's rows
+    // interpolated in x at the R0 fine columns (sx, in region B: dead before
+    // layer 1 writes act1), then in y at every pixel; the products and sums
+    // are those of the 4 x 4 form, in the same order
+    float (*sx)[CWMAX][R0] = reinterpret_cast<float (*)[CWMAX][R0]>(lds_net + REG_A);
+    static_assert(4 * CWMAX * R0 * 4 <= REG_B, "x-interpolated rows fit region B");
+    static_assert(R0 <= 32 && CWMAX <= 32, "one window row per 32 threads");
+    if (c32 < R0) {
+        const float *wx = wts[s_px[c32]];
+        const int bx = s_bx[c32];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            for (int wyr = r8; wyr < cwy; wyr += 8) {
+                float sa = 0.0f;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) sa += wx[b] * cwin[f][wyr][bx + b];
+                sx[f][wyr][c32] = sa;
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int p = tid + 256 * k;
+        if (p >= NP0) break;
         const int py = p / R0, px = p - py * R0;
-        const long long g = (long long)s_fy[py] + s_fx[px];
-        // sub-positions and window columns of the 4-point stencils
-        const int X = x0 - 3 + px, Y = y0 - 3 + py;
-        const int jx = fdiv(X, r), jy = fdiv(Y, r);
-        const float *wx = wts[X - jx * r], *wy = wts[Y - jy * r];
-        const int bx = jx - 1 - cx0, by = jy - 1 - cy0;
-        __bf16 v[8];
+        const float *wy = wts[s_py[py]];
+        const int by = s_by[py];
+        bf16x8 v;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             float d = 0.0f;
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                float sa = 0.0f;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) sa += wx[b] * cwin[f][by + a][bx + b];
-                d += wy[a] * sa;
-            }
-            const float xv = xf[f * nf + g];
+            for (int a = 0; a < 4; ++a) d += wy[a] * sx[f][by + a][px];
+            const float xv = xin[k][f];
             v[f] = (__bf16)((d - nc.in_offset[f]) * nc.in_scale[f]);
             v[4 + f] = (__bf16)((xv - nc.in_offset[4 + f]) * nc.in_scale[4 + f]);
             if (py >= 3 && py < 3 + NT && px >= 3 && px < 3 + NT) dps[f][(py - 3) * NT + (px - 3)] = d;
         }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) in0[p * 8 + c] = v[c];
+        *reinterpret_cast<bf16x8 *>(in0 + p * 8) = v;
     }
     __syncthreads();
-    conv_layer<8, R0, R1>(in0, act1, wk + K_W1, prm + P_B1, wave, lane);
+    conv_layer<8, R0, R1>(lds_net, act1, wk + K_W1, prm + P_B1, wave, lane);
     __syncthreads();
     conv_layer<32, R1, R2>(act1, act2, wk + K_W2, prm + P_B2, wave, lane);
     __syncthreads();
     {
-        constexpr int K = 288, KCH = 18;
-        bf16x8 a[KCH];
+        // layer 3 (4 output channels) on v_mfma_f32_16x16x32_bf16: M = 16
+        // output channels (rows 4..15 of the packed weights are zero), N = 16
+        // pixels, K = 32 = the channels of one tap.  Lane l holds A row l % 16
+        // and B column l % 16, K values 8 (l / 16) .. 8 (l / 16) + 7; result
+        // element i of lane l is channel 4 (l / 16) + i, so lanes 0..15 hold
+        // the 4 output channels of their pixel.  Each wave takes two
+        // 16-pixel groups at a time.
+        bf16x8 a[9];
 #pragma unroll
-        for (int ks = 0; ks < KCH; ++ks)
-            a[ks] = *reinterpret_cast<const bf16x8 *>(wk + K_W3 + (lane & 31) * K + ks * 16 + (lane >> 5) * 8);
-        for (int nt = wave; nt < NP3 / 32; nt += 4) {
-            const int n = nt * 32 + (lane & 31);
-            const int py = n / NT, px = n - py * NT;
-            f32x16 acc = {};
+        for (int tap = 0; tap < 9; ++tap)
+            a[tap] = *reinterpret_cast<const bf16x8 *>(wk + K_W3 + (lane & 15) * 288 + tap * 32 + (lane >> 4) * 8);
+        constexpr int P2 = NP2 * 16;
+        for (int nt = wave; nt < NP3 / 16; nt += 8) {
+            int n[2];
+            const unsigned char *src[2];
 #pragma unroll
-            for (int ks = 0; ks < KCH; ++ks) {
-                const int kb = ks * 16 + (lane >> 5) * 8;
-                const int tap = kb / 32, ic0 = kb - tap * 32;
-                const int pix = (py + tap / 3) * R2 + (px + tap % 3);
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(act2 + pix * 32 + chunk_pos(pix, ic0 >> 3));
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
+            for (int h = 0; h < 2; ++h) {
+                n[h] = (nt + 4 * h) * 16 + (lane & 15);
+                const int py = n[h] / NT, px = n[h] - py * NT;
+                src[h] = act2 + (lane >> 4) * P2 + 16 * (py * R2 + px);
             }
-            if (lane < 32) {
+            f32x4 acc[2] = {{}, {}};
 #pragma unroll
-                for (int f = 0; f < 4; ++f) outb[f][n] = (acc[f] + prm[P_B3 + f]) / nc.out_scale[f];
+            for (int tap = 0; tap < 9; ++tap) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(src[h] + 16 * tap_off<R2>(tap));
+                    acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[tap], b, acc[h], 0, 0, 0);
+                }
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) outb[f][n[h]] = (acc[h][f] + prm[P_B3 + f]) / nc.out_scale[f];
             }
         }
     }
@@ -264,7 +381,7 @@ __global__ __launch_bounds__(256) void net_prolong_fwd(const float *__restrict__
     if (gx < nx && gy < ny) {
         const long long g = (long long)gy * nx + gx;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) xout[f * nf + g] = xf[f * nf + g] + d[f] + (use_net ? o[f] : 0.0f);
+        for (int f = 0; f < 4; ++f) xout[f * nf + g] = xo[f] + d[f] + (use_net ? o[f] : 0.0f);
     }
 }
 
