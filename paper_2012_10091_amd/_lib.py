@@ -158,6 +158,7 @@ SIGNATURES = {
 TEST_HOOKS = {
     "menkf_test_philox": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p]),
     "menkf_test_mfma": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "menkf_test_chol_diag": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 
 _LIB = None

@@ -348,11 +348,259 @@ __device__ __forceinline__ void chol_diag_block(const double *src, long long lds
     }
 }
 
+// ---- hierarchical form of the same factorisation (64x64 block, 256 threads)
+// The block is split into 4 x 4 sub-blocks of 16 x 16.  For s = 0..3:
+//   F: one wave factors the diagonal sub-block, D_ss = L_ss L_ss^T, and
+//      inverts L_ss: a 16-pivot sweep held in registers, no barrier
+//      inside (the pivot column reaches the lanes by a row broadcast within
+//      each 16-lane row, the pivot row by a lane permute);
+//   P: L_is = D_is L_ss^-T for the sub-blocks below (16x16x16 on FP64 MFMA);
+//   U: D_ij -= L_is L_js^T for s < j <= i (FP64 MFMA).
+// Then the blocks of L^-1 below the diagonal, by distance from it:
+//   (L^-1)_ij = -L_ii^-1 sum_{k=j}^{i-1} L_ik (L^-1)_kj,  (L^-1)_jj = L_jj^-1.
+// The pivots are those of the unblocked sweep (the diagonal of the
+// successive Schur complements); a pivot that is not positive is recorded
+// and the first one reported through the status word, outputs untouched.
+// The 16-pivot sweep: lane l holds column c = l % 16, rows r = 4 (l / 16) + e
+// (e < 4) of the sub-block (w, the block being reduced, and x, the rows of
+// the inverse, both unscaled as in chol_diag_block); at the end
+// L[r][c] = w / sqrt(p_c) and L^-1[r][c] = x / sqrt(p_r).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// value of lane J of the caller's 16-lane row (DPP row broadcast)
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x150 + J, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x150 + J, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// 16x16 factor and inverse of the sub-block at Ws (row stride LDP, lower
+// triangle read), by one wave: L_ss over the lower triangle of Ws (zeros
+// above), L_ss^-1 into Ts (16 x 16, zeros above), the pivots into piv[16].
+// Returns 1 + the first non-positive pivot (0 if none); uniform.
+__device__ __forceinline__ int chol16_wave(double *Ws, double *Ts, double *piv) {
+    const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
+    double w[4], x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = 4 * q + e;
+        w[e] = r >= c ? Ws[r * LDP + c] : Ws[c * LDP + r];
+        x[e] = r == c ? 1.0 : 0.0;
+    }
+    // the sweep is one basic block (no branch): the scheduler can issue a
+    // step's lane exchanges as soon as the previous step has produced them
+    int bad = 0;
+    static_for<0, 16>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int jq = j >> 2, je = j & 3;
+        const double p = readlane_d(w[je], 16 * jq + j);   // W[j][j]
+        bad = (bad == 0 && !(p > 0.0)) ? j + 1 : bad;
+        const double inv = pivot_recip(p);   // garbage after a bad pivot: the outputs are not written then
+        const int src = 16 * jq + c;   // lane holding (row j, column c)
+        const double rowj = __shfl(w[je], src);
+        const double xrowj = __shfl(x[je], src);
+        const double vr = c > j ? rowj : 0.0;
+        // the four rows' multipliers first (independent chains), then the updates
+        double colj[4], m[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) colj[e] = row_bcast<j>(w[e]);   // W[4 q + e][j]
+#pragma unroll
+        for (int e = 0; e < 4; ++e) m[e] = 4 * q + e > j ? colj[e] * inv : 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = fma(-m[e], vr, w[e]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = fma(-m[e], xrowj, x[e]);
+    });
+    // the diagonal of w is the pivot sequence
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (4 * q + e == c) piv[c] = w[e];
+    wave_sync();
+    const double rdc = 1.0 / sqrt(piv[c]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = 4 * q + e;
+        const double rdr = 1.0 / sqrt(piv[r]);
+        Ws[r * LDP + c] = r > c ? w[e] * rdc : (r == c ? sqrt(piv[c]) : 0.0);
+        Ts[r * 16 + c] = r >= c ? x[e] * rdr : 0.0;
+    }
+    return bad;
+}
+
+// acc (16x16, MFMA result layout) += A B over K = 16: A at Pa (row stride
+// lda), B given transposed (Bt[n][k]) at Pb (row stride ldb).  One wave.
+__device__ __forceinline__ void mfma16_nt(const double *Pa, int lda, const double *Pb, int ldb, f64x4 &acc) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+        const double a = Pa[(l & 15) * lda + k0 + (l >> 4)];
+        const double b = Pb[(l & 15) * ldb + k0 + (l >> 4)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+}
+
+// acc (16x16) += A B over K = 16 with B in natural layout (B[k][n] at Pb,
+// row stride ldb).  One wave.
+__device__ __forceinline__ void mfma16_nn(const double *Pa, int lda, const double *Pb, int ldb, f64x4 &acc) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+        const double a = Pa[(l & 15) * lda + k0 + (l >> 4)];
+        const double b = Pb[(k0 + (l >> 4)) * ldb + (l & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+}
+
+// element e of lane l of an MFMA result: row 4 e + l / 16, column l % 16
+template <typename Fn>
+__device__ __forceinline__ void for_acc16(const f64x4 &acc, Fn f) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) f(4 * e + (l >> 4), l & 15, acc[e]);
+}
+
+// Hierarchical factorisation of the 64x64 block held in LDS at W (row
+// stride LDP, lower triangle; overwritten by L), with LDS scratch of
+// DIAG_SCRATCH doubles; L to Ak (row stride ld), L^-1 to Linv (64 x 64,
+// zeros above).  256 threads; must be entered by the whole workgroup.
+constexpr int DIAG_SCRATCH = 4 * 256 + 6 * 256 + 4 * 256 + 64 + 8;
+__device__ __forceinline__ void chol_diag_hier(double *W, double *scr, double *__restrict__ Ak, long long ld, int k,
+                                               double *__restrict__ Linv, int32_t *__restrict__ info,
+                                               long long *stamps = nullptr) {
+    int nst = 0;
+    auto stamp = [&]() {
+        if (stamps && threadIdx.x == 0) stamps[nst] = (long long)__builtin_amdgcn_s_memtime();
+        ++nst;
+    };
+    stamp();
+    __builtin_amdgcn_s_setprio(3);
+    double *Ti = scr;                  // 4 x (16 x 16): L_ss^-1
+    double *V = scr + 4 * 256;         // 6 x (16 x 16): (L^-1)_ij, i > j, block index ij_index(i, j)
+    double *Tw = scr + 10 * 256;       // 4 x (16 x 16): one per wave
+    double *piv = scr + 14 * 256;      // 64 pivots
+    int *badw = reinterpret_cast<int *>(scr + 14 * 256 + 64);
+    const int tid = threadIdx.x, wave = tid >> 6;
+    auto vidx = [](int i, int j) { return (i * (i - 1)) / 2 + j; };   // (1,0)=0 (2,0)=1 (2,1)=2 (3,0)=3 ...
+    if (tid == 0) *badw = 0;
+    __syncthreads();
+    // wave 0 carries the chain F(s) -> P(s) -> update of D_{s+1,s+1} ->
+    // F(s+1); the other waves update the rest of the trailing blocks and
+    // form the blocks of L^-1 beside it
+    auto factor = [&](int s) {
+        const int b = chol16_wave(W + 16 * s * LDP + 16 * s, Ti + 256 * s, piv + 16 * s);
+        if (b && (threadIdx.x & 63) == 0 && *badw == 0) *badw = 16 * s + b;
+    };
+    auto update = [&](int s, int i, int j) {   // D_ij -= L_is L_js^T
+        double *Dij = W + 16 * i * LDP + 16 * j;
+        f64x4 acc = {};
+        mfma16_nt(W + 16 * i * LDP + 16 * s, LDP, W + 16 * j * LDP + 16 * s, LDP, acc);
+        double old[4];
+        for_acc16(acc, [&](int r, int cc, double) { old[r >> 2] = Dij[r * LDP + cc]; });
+        for_acc16(acc, [&](int r, int cc, double v) { Dij[r * LDP + cc] = old[r >> 2] - v; });
+    };
+    auto inverse_block = [&](int i, int j) {   // (L^-1)_ij = -L_ii^-1 sum_{k=j}^{i-1} L_ik (L^-1)_kj
+        f64x4 acc = {};
+        mfma16_nn(W + 16 * i * LDP + 16 * j, LDP, Ti + 256 * j, 16, acc);
+        for (int kk = j + 1; kk < i; ++kk) mfma16_nn(W + 16 * i * LDP + 16 * kk, LDP, V + 256 * vidx(kk, j), 16, acc);
+        double *T = Tw + 256 * wave;
+        for_acc16(acc, [&](int r, int cc, double v) { T[r * 16 + cc] = v; });
+        wave_sync();
+        f64x4 acc2 = {};
+        mfma16_nn(Ti + 256 * i, 16, T, 16, acc2);
+        double *Vij = V + 256 * vidx(i, j);
+        for_acc16(acc2, [&](int r, int cc, double v) { Vij[r * 16 + cc] = -v; });
+    };
+    if (wave == 0) factor(0);
+    __syncthreads();
+    stamp();
+    for (int s = 0; s < 4; ++s) {
+        // panels L_is = D_is L_ss^-T (waves 0 .. 2 - s); the blocks
+        // (L^-1)_sj, j < s, on the waves left (they need L_ss^-1, the final
+        // L_s. and the (L^-1)_kj of the earlier stages)
+        if (wave < 3 - s) {
+            const int i = s + 1 + wave;
+            double *Dis = W + 16 * i * LDP + 16 * s;
+            f64x4 acc = {};
+            mfma16_nt(Dis, LDP, Ti + 256 * s, 16, acc);
+            for_acc16(acc, [&](int r, int cc, double v) { Dis[r * LDP + cc] = v; });
+        } else if (wave - (3 - s) < s) {
+            inverse_block(s, wave - (3 - s));
+        }
+        __syncthreads();
+        stamp();
+        if (s == 3) break;
+        // trailing update; wave 0 takes D_{s+1,s+1} and factors it at once
+        if (wave == 0) {
+            update(s, s + 1, s + 1);
+            wave_sync();
+            factor(s + 1);
+        } else {
+            const int nb = 3 - s, nt = nb * (nb + 1) / 2;
+            for (int t = 1 + (wave - 1); t < nt; t += 3) {   // block t = 0 is D_{s+1,s+1}
+                int bi = 0;
+                while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+                const int bj = t - bi * (bi + 1) / 2;
+                update(s, s + 1 + bi, s + 1 + bj);
+            }
+        }
+        __syncthreads();
+        stamp();
+    }
+    const int bad = *badw;
+    if (bad) {
+        if (tid == 0) *info = k * 64 + bad;
+        return;
+    }
+    // outputs: L (lower) and L^-1 (zeros above the diagonal), each wave 16
+    // whole rows (one 512-byte store per row and array)
+    {
+        const int c = tid & 63, bj = c >> 4;
+        for (int rr = 0; rr < 16; ++rr) {
+            const int r = 16 * wave + rr, bi = r >> 4;
+            if (c <= r) Ak[(long long)r * ld + c] = W[r * LDP + c];
+            double v = 0.0;
+            if (bj == bi)
+                v = Ti[256 * bi + (r & 15) * 16 + (c & 15)];
+            else if (bj < bi)
+                v = V[256 * vidx(bi, bj) + (r & 15) * 16 + (c & 15)];
+            Linv[r * 64 + c] = v;
+        }
+    }
+    stamp();
+}
+
+#ifndef CHOL_DIAG_HIER
+#define CHOL_DIAG_HIER 1
+#endif
+
 __global__ __launch_bounds__(256) void chol_diag(double *__restrict__ A, int ld, int k, double *__restrict__ Linv,
                                                  int32_t *__restrict__ info) {
     if (*info != 0) return;
     double *Ak = A + (long long)(k * 64) * ld + k * 64;
+#if CHOL_DIAG_HIER
+    __shared__ __attribute__((aligned(16))) double Wd[64 * LDP];
+    __shared__ __attribute__((aligned(16))) double scr[DIAG_SCRATCH];
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        if (c <= r) Wd[r * LDP + c] = Ak[(long long)r * ld + c];
+    }
+    __syncthreads();
+    chol_diag_hier(Wd, scr, Ak, ld, k, Linv, info);
+#else
     chol_diag_block(Ak, ld, Ak, ld, k, Linv, info);
+#endif
 }
 
 // acc += P Q^T for 64-row blocks P (rows of length K at ldp) and Q, K a
@@ -457,7 +705,7 @@ __device__ __forceinline__ void gemm_nt_64(const double *__restrict__ P, long lo
 // S = Yk Yk^T + R on the lower 64x64 blocks (identity on the padding rows).
 __global__ __launch_bounds__(256) void syrk_f64_mfma(const double *__restrict__ Yk, int kdim, int Ny, double r_diag,
                                                      double *__restrict__ A, int ld) {
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
     int bi, bj;
     tri_index(blockIdx.x, bi, bj);
     f64x4 acc[2][2] = {};
@@ -474,7 +722,7 @@ __global__ __launch_bounds__(256) void syrk_f64_mfma(const double *__restrict__ 
 
 __global__ __launch_bounds__(256) void chol_panel(double *__restrict__ A, int ld, int k, const double *__restrict__ Linv,
                                                   const int32_t *__restrict__ info) {
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
     if (*info != 0) return;
     __builtin_amdgcn_s_setprio(3);   // on the factorisation's critical path, like the diagonal block
     const int i = k + 1 + blockIdx.x;
@@ -489,7 +737,7 @@ __global__ __launch_bounds__(256) void chol_panel(double *__restrict__ A, int ld
 // chain of step k+1 with the other blocks of step k.
 __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int ld, int k, int nbs,
                                                    double *__restrict__ Linv, int32_t *__restrict__ info) {
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
     if (*info != 0) return;
     int bi, bj;
     tri_index(blockIdx.x, bi, bj);
@@ -519,7 +767,11 @@ __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int l
     });
     if (lookahead) {
         __syncthreads();
+#if CHOL_DIAG_HIER
+        chol_diag_hier(tile, smem_d + 64 * LDP, Aij, ld, k + 1, Linv, info);
+#else
         chol_diag_block(tile, LDP, Aij, ld, k + 1, Linv, info);
+#endif
     }
 }
 
@@ -534,7 +786,7 @@ __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int l
 // in one pass over the probes.
 __global__ __launch_bounds__(256) void gram_extra(const double *__restrict__ A, int ld, int nyp, int mextp,
                                                   double *__restrict__ P) {
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
     int bi, bj;
     tri_index(blockIdx.x, bi, bj);
     const double *E = A + (long long)nyp * ld;
@@ -546,7 +798,7 @@ __global__ __launch_bounds__(256) void gram_extra(const double *__restrict__ A, 
 
 __global__ __launch_bounds__(256) void gram_extra_part(const double *__restrict__ A, int ld, int nyp, int kc,
                                                        double *__restrict__ part) {
-    extern __shared__ double smem_d[];
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
     int bi, bj;
     tri_index(blockIdx.x, bi, bj);
     const double *E = A + (long long)nyp * ld + (long long)blockIdx.y * kc;
@@ -1385,6 +1637,42 @@ hipError_t launch_update(const Plan &p, void *members, void *dc, void *ws, hipSt
 }
 
 }  // namespace menkf
+
+// Test hook: the 64x64 diagonal-block factorisation alone, one workgroup:
+// A (64 x 64, row-major, lower triangle read) -> L (lower, row stride 64),
+// Linv (64 x 64), info (0 or 1 + the first non-positive pivot); which = 0
+// the pivot sweep, 1 the hierarchical form.  stamps (nullptr or 32 words)
+// receive the shader clock at the hierarchical form's phase boundaries.
+namespace menkf {
+__global__ __launch_bounds__(256) void diag_test_kernel(int which, const double *A, double *L, double *Linv,
+                                                        int32_t *info, long long *stamps) {
+    __shared__ __attribute__((aligned(16))) double Wd[64 * LDP];
+    __shared__ __attribute__((aligned(16))) double scr[DIAG_SCRATCH];
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int r = e >> 6, c = e & 63;
+        if (c <= r) Wd[r * LDP + c] = A[e];
+    }
+    __syncthreads();
+    const long long t0 = (long long)__builtin_amdgcn_s_memtime();
+    if (which == 1)
+        chol_diag_hier(Wd, scr, L, 64, 0, Linv, info, stamps);
+    else
+        chol_diag_block(Wd, LDP, L, 64, 0, Linv, info);
+    __syncthreads();
+    if (stamps && threadIdx.x == 0) {
+        stamps[30] = t0;
+        stamps[31] = (long long)__builtin_amdgcn_s_memtime();
+    }
+}
+}  // namespace menkf
+
+extern "C" int menkf_test_chol_diag(int which, const double *A, double *L, double *Linv, int32_t *info,
+                                    long long *stamps, void *stream) {
+    if (which != 0 && which != 1) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(menkf::diag_test_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, which, A, L, Linv, info,
+                       stamps);
+    return (int)hipGetLastError();
+}
 
 // Test hook: Philox4x32-10 on n (counter, key) sextuples, device pointers.
 extern "C" int menkf_test_philox(const uint32_t *in_dev, uint32_t *out_dev, int n, void *stream) {
