@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the forecast schedules first")
     ap.add_argument("--workload", default="ns2d_1024_256_n64",
-                    choices=["ns2d_1024_256_n64", "uneven48", "inlet_dual", "euler_dual"],
+                    choices=["ns2d_1024_256_n64", "uneven48", "inlet_dual", "euler_dual", "learned_train"],
                     help="uneven48: the batch of 48 uneven instances in one graph; inlet_dual: the dual "
                          "(parameter + state) filter of the inlet-forced Burgers case (neither is the headline)")
     ap.add_argument("--dual-precision", default="f64", choices=["f64", "f32"])
@@ -411,53 +411,53 @@ def cpu_model():
     import subprocess
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
-        for line in out.splitlines():
-            if line.startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+        f = {k.strip(): v.strip() for k, v in (ln.split(":", 1) for ln in out.splitlines() if ":" in ln)}
+        if "Model name" in f:
+            return (f"{f['Model name']} (family {f.get('CPU family', '?')}, model {f.get('Model', '?')}, "
+                    f"{f.get('Socket(s)', '?')} socket(s), {f.get('CPU(s)', '?')} CPUs on the host)")
     except (OSError, subprocess.SubprocessError):
         pass
     return None
 
 
-def cpu_baseline(cfg):
-    """The FP64 oracle on a bounded sample of one cycle, extrapolated to cycles/s."""
-    import numpy as np
+def cpu_baseline(cfg, k=5):
+    """The FP64 oracle on the host: the fine forecast and the forecast of all
+    members (one batch, as in a cycle) over the first k of a cycle's time
+    steps, then the analysis, Pi_F and three sweeps; the forecasts scaled to
+    the cycle's n_obs steps."""
     from oracle import cycle as ocycle
     from oracle import enkf, grids, rng, smooth
     from oracle.models import Model
     from synthetic import fields
     cores = len(os.sched_getaffinity(0))
-    fine = fields.model_ic(cfg)
-    mem = fields.member_ics(cfg)
+    k = min(k, cfg.n_obs)
     mf, mc = Model(cfg, "fine"), Model(cfg, "coarse")
-    t = time.perf_counter()
-    mf.step(fine)
-    t_fine_step = time.perf_counter() - t
-    nm = 2
-    t = time.perf_counter()
-    mc.step(mem[:nm])
-    t_member_step = (time.perf_counter() - t) / nm
     idx, comp = fields.probes_for(cfg)
-    xs = grids.restrict(fine, cfg.ratio, cfg.dim)
-    y = np.zeros(cfg.n_probes)
-    eps = rng.perturbations(1, 1, cfg.n_members, cfg.n_probes, cfg.obs_sigma)
+    y = ocycle.observe_truth(cfg, fields.truth_ic(cfg), idx, comp)
+    eps = rng.perturbations(cfg.seed + 5, 1, cfg.n_members, cfg.n_probes, cfg.obs_sigma)
     t = time.perf_counter()
-    res = enkf.analysis(mem, xs, y, eps, ocycle.make_H(cfg, idx, comp), cfg.obs_sigma)
-    t_analysis = time.perf_counter() - t
+    xf, xf_prev = mf.forecast(fields.model_ic(cfg), k)
+    t_fine = time.perf_counter() - t
     t = time.perf_counter()
-    x = fine + grids.prolong(res["delta"], cfg.ratio, cfg.dim)
-    smooth.smooth(x, fine, mf, 3, 0.5)
-    t_prolong = time.perf_counter() - t
-    per_cycle = (cfg.n_obs * (t_fine_step + cfg.n_members * t_member_step) + t_analysis + t_prolong)
+    mem, _ = mc.forecast(fields.member_ics(cfg), k)
+    t_mem = time.perf_counter() - t
+    t = time.perf_counter()
+    res = enkf.analysis(mem, grids.restrict(xf, cfg.ratio, cfg.dim), y, eps, ocycle.make_H(cfg, idx, comp),
+                        cfg.obs_sigma)
+    t_an = time.perf_counter() - t
+    t = time.perf_counter()
+    smooth.smooth(xf + grids.prolong(res["delta"], cfg.ratio, cfg.dim), xf_prev, mf, 3, 0.5)
+    t_pro = time.perf_counter() - t
+    per_cycle = cfg.n_obs / k * (t_fine + t_mem) + t_an + t_pro
     return {
         "value": 1.0 / per_cycle,
         "unit": "cycles/s",
         "cores": cores,
         "cpu": cpu_model(),
         "kind": "oracle",
-        "sample": (f"1 fine RK4 step ({t_fine_step:.2f}s), {nm} member steps ({t_member_step:.2f}s each), "
-                   f"1 analysis ({t_analysis:.2f}s), prolong + 3 sweeps ({t_prolong:.2f}s); "
-                   f"extrapolated to one cycle = {cfg.n_obs} fine + {cfg.n_obs * cfg.n_members} member steps"),
+        "sample": (f"{k} of a cycle's {cfg.n_obs} time steps of the fine state ({t_fine:.1f}s) and of all "
+                   f"{cfg.n_members} members in one batch ({t_mem:.1f}s), one analysis ({t_an:.1f}s), "
+                   f"Pi_F + 3 sweeps ({t_pro:.1f}s); forecasts scaled by {cfg.n_obs}/{k}"),
     }
 
 
@@ -467,6 +467,88 @@ def load_net(cfg, path, judge_every):
     if not os.path.exists(path):
         return None, path
     return learned.load(path, guard=10.0, judge_every=judge_every), path
+
+
+FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (packed FP32 off)
+
+
+def bench_train(args):
+    """Training throughput of the learned prolongation's network: Adam steps of
+    menkf_net_train_step (forward, backward, Adam; BF16 storage, FP32
+    arithmetic) on random periodic 128^2 crops, 16 per step, of synthetic
+    pairs shaped like the 512^2 workload's, timed with HIP events on the
+    stream they run on.  Beside it the oracle's FP64 forward and backward of
+    one crop on the host."""
+    import numpy as np
+    import torch
+
+    import paper_2012_10091_amd as m
+    from oracle import net as onet
+    from paper_2012_10091_amd import learned
+    from synthetic import configs, fields
+    cfg = configs.CONFIGS["C4"]
+    batch, crop, npairs = 16, 128, 64
+    net = learned.load(learned.weights_for("ns2d_512_128_n32"))
+    rs = np.random.default_rng(cfg.seed + 71)
+    xf0 = fields.model_ic(cfg).astype(np.float32)
+    shape = (npairs, 4, cfg.ny, cfg.nx)
+    xf = torch.as_tensor(np.broadcast_to(xf0, shape) + 1e-2 * rs.standard_normal(shape).astype(np.float32),
+                         device="cuda").contiguous()
+    dproj = torch.as_tensor(1e-3 * rs.standard_normal(shape).astype(np.float32), device="cuda").contiguous()
+    target = torch.as_tensor(1e-3 * rs.standard_normal(shape).astype(np.float32), device="cuda").contiguous()
+    n_sets = args.warmup + args.steps
+    crops = torch.as_tensor(np.stack([rs.integers(0, npairs, (n_sets, batch)), rs.integers(0, cfg.ny, (n_sets, batch)),
+                                      rs.integers(0, cfg.nx, (n_sets, batch))], axis=2).astype(np.int32),
+                            device="cuda").contiguous()
+    tr = m.Trainer(net, batch=batch, crop=crop)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            tr.step(dproj, xf, target, crops[i], stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(args.warmup, n_sets):
+            tr.step(dproj, xf, target, crops[i], stream=stream)
+        e1.record(stream)
+    stream.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    steps_s = args.steps / sec
+    fl = learned.train_flops_per_crop(crop) * batch
+    tflops = fl * steps_s / 1e12
+    log(f"bench: training {steps_s:.1f} Adam steps/s ({steps_s * batch:.0f} crops/s), {tflops:.2f} TFLOP/s")
+    out = {
+        "metric": "learned-prolongation training Adam steps/s (batch 16 periodic 128^2 crops, 512^2 pairs)",
+        "value": steps_s, "unit": "Adam steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 / steps_s, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "learned_train_512_crop128_b16", "pairs": npairs, "crops_per_s": steps_s * batch,
+                   "flops_per_step": fl, "kernels": "menkf_net_train_step: direct convolutions on the vector "
+                                                   "units, BF16 activations, FP32 arithmetic, Adam in FP32"},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_NONPACKED_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_NONPACKED_PEAK_TFLOPS, "traffic": None,
+                     "peak_note": "FP32 FMA on the vector units without packed instructions (the build turns "
+                                  "them off): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz"},
+    }
+    if args.cpu_baseline:
+        log("bench: timing the oracle's forward + backward of one crop on the host")
+        cores = len(os.sched_getaffinity(0))
+        params = onet.init_params(cfg, zero_last=False)
+        x = onet.make_input(params, rs.standard_normal((4, crop, crop)) * 1e-3, xf0[:, :crop, :crop])
+        t = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t < 10.0:
+            o, cache = onet.forward(params, x)
+            _, g = onet.mse(o, np.zeros_like(o))
+            onet.backward(params, cache, g)
+            n += 1
+        dt = (time.perf_counter() - t) / n
+        out["cpu_baseline"] = {"value": 1.0 / (dt * batch), "unit": "Adam steps/s", "cores": cores, "cpu": cpu_model(),
+                               "kind": "oracle",
+                               "sample": f"{n} FP64 forward + backward passes of one periodic {crop}^2 crop "
+                                         f"({dt:.2f}s each), scaled to {batch} crops per step (Adam itself not timed)"}
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):
@@ -534,6 +616,12 @@ def bench_batch(args):
     log(f"bench: batch on {args.lanes} lanes: {cps:.2f} batch cycles/s, failed instances {bad}")
     cps1, bad1, _ = run(1)
     log(f"bench: batch on 1 lane: {cps1:.2f} batch cycles/s")
+    # the dominant kernel: the coarse stage kernel of the instance with the
+    # largest ensemble, timed alone on its own stream
+    big = max(insts, key=lambda i: i["cfg"].n_members * i["cfg"].nxc * i["cfg"].nyc)
+    rl = stage_kernel_roofline(big["cfg"], type("C", (), {"ctx": big["ctx"], "members": big["members"]})())
+    log(f"bench: stage kernel of {big['cfg'].name}: {rl['avg_launch_us']:.1f} us per launch, algorithmic "
+        f"{rl['achieved']:.0f} GB/s")
     out = {
         "metric": "uneven-batch assimilation cycles/s (48 independent 2D instances in one graph)",
         "value": cps, "unit": "batch cycles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -546,7 +634,27 @@ def bench_batch(args):
                    "one_lane_batch_cycles_per_s": cps1, "autotuned": bool(args.autotune),
                    "prolongation": f"learned, judged every {net.judge_every} cycles against Pi_F + {args.sweeps} "
                                    f"sweeps (its fallback)", "failed_instances": bad + bad1},
+        "roofline": {
+            "bound": "hbm", "achieved": rl["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": rl["achieved"] / HBM_PEAK_GBS, "traffic": None,
+            "kernel": rl["kernel"] + f" of the largest ensemble ({big['cfg'].name}), timed alone",
+            "avg_launch_us": rl["avg_launch_us"], "algorithmic_bytes_per_launch": rl["min_bytes"],
+            "algorithmic_bytes": "one read and one write of the state per time step, shared by the launches of a step",
+        },
     }
+    if args.cpu_baseline:
+        # the oracle's cycle of one instance per fine side (2 of its 20 time
+        # steps timed, the rest scaled), and the batch as 16 times those three
+        sample = []
+        for side in sorted({c.nx for c in cfgs}):
+            c = next(c for c in cfgs if c.nx == side)
+            log(f"bench: timing the oracle on {c.name} (bounded sample)")
+            sample.append((c.name, 1.0 / cpu_baseline(c, k=2)["value"]))
+        per_batch = len(cfgs) / len(sample) * sum(t for _, t in sample)
+        out["cpu_baseline"] = {"value": 1.0 / per_batch, "unit": "batch cycles/s", "cores": len(os.sched_getaffinity(0)),
+                               "cpu": cpu_model(), "kind": "oracle",
+                               "sample": "cycles (2 of 20 forecast steps timed, scaled) of " + ", ".join(f"{n} ({t:.1f}s)" for n, t in sample)
+                                         + f"; the batch of {len(cfgs)} taken as {len(cfgs) // len(sample)} times these"}
     print(json.dumps(out), flush=True)
 
 
@@ -1076,6 +1184,8 @@ def main():
         print("bench.py runs on one GPU: this build measures the single-GPU hot path "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "learned_train":
+        return bench_train(args)
     if args.workload == "uneven48":
         return bench_batch(args)
     if args.workload == "inlet_dual":
