@@ -50,9 +50,12 @@ def parse():
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the forecast schedules first")
     ap.add_argument("--workload", default="ns2d_1024_256_n64",
-                    choices=["ns2d_1024_256_n64", "uneven48", "inlet_dual", "euler_dual", "learned_train"],
-                    help="uneven48: the batch of 48 uneven instances in one graph; inlet_dual: the dual "
-                         "(parameter + state) filter of the inlet-forced Burgers case (neither is the headline)")
+                    choices=["ns2d_1024_256_n64", "ns2d_512_128_n32", "burgers1d_16384_4096_n256", "uneven48",
+                             "inlet_dual", "euler_dual", "learned_train"],
+                    help="ns2d_512_128_n32: the learned-prolongation workload (2D 512^2/128^2, N = 32); "
+                         "burgers1d_16384_4096_n256: 1D Burgers at scale (plain MEnKF only); uneven48: the batch "
+                         "of 48 uneven instances in one graph; inlet_dual: the dual (parameter + state) filter of "
+                         "the inlet-forced Burgers case (none of these is the headline)")
     ap.add_argument("--dual-precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--time-scheme", default="ssprk3", choices=["ssprk3", "first_order"],
                     help="inlet_dual: SSP-RK3, or the paper's first-order scheme (forward Euler, one Jacobi "
@@ -70,9 +73,20 @@ def parse():
     return ap.parse_args()
 
 
-def make_cfg(small):
+def make_cfg(args):
     from synthetic import configs
-    return configs.tiny_2d(precision="f32") if small else configs.CONFIGS["C3"]
+    if args.small:
+        return configs.tiny_2d(precision="f32")
+    by_name = {c.name: c for c in configs.CONFIGS.values()}
+    return by_name[args.workload]
+
+
+def metric_for(cfg):
+    if cfg.name == "ns2d_1024_256_n64":
+        return METRIC
+    if cfg.dim == 2:
+        return f"assimilation cycles/s, 2D {cfg.nx}²/{cfg.nxc}² N={cfg.n_members}, learned vs plain at equal RMSE"
+    return f"assimilation cycles/s, 1D Burgers {cfg.nx}/{cfg.nxc} N={cfg.n_members}, plain MEnKF"
 
 
 class Cycle:
@@ -92,7 +106,7 @@ class Cycle:
         self.fine = torch.as_tensor(fields.model_ic(cfg), dtype=f32, device="cuda").contiguous()
         self.members = torch.as_tensor(fields.member_ics(cfg), dtype=f32, device="cuda").contiguous()
         self.prev = torch.empty_like(self.fine)
-        self.xs = torch.empty((4, cfg.nyc, cfg.nxc), dtype=f32, device="cuda")
+        self.xs = torch.empty(cfg.coarse_shape, dtype=f32, device="cuda")
         self.dc = torch.empty_like(self.xs)
         self.y = torch.zeros(cfg.n_probes, dtype=torch.float64, device="cuda")
         self.n_sweeps = n_sweeps
@@ -311,10 +325,50 @@ def stage_kernel_roofline(cfg, cyc, reps=2):
         "avg_launch_us": avg_s * 1e6,
         "launches_per_step": per_step,
         "contract_bytes": contract,
-        "traffic": measured_traffic(sc),
+        "traffic": measured_traffic(sc, cfg),
         "min_bytes": minimum,
         "achieved_contract": contract / avg_s / 1e9,
         "achieved": minimum / avg_s / 1e9,
+    }
+
+
+# FP32 operations per point and time step of the 1D Burgers forecast (three
+# SSP-RK3 stages): per stage 7 for L(u) (difference, product, scaling;
+# second difference, scaling, sum) and 2, 4, 4 for the stage combinations.
+BURGERS_FLOPS_PER_POINT_STEP = 3 * 7 + 2 + 4 + 4
+FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (packed FP32 off)
+
+
+def window_kernel_roofline(cfg, cyc, reps=5):
+    """The 1D member forecast (one launch per observation window, every
+    member's row held in LDS for the window) timed with HIP events on its
+    own stream, against the vector ALU peak: the state crosses HBM once per
+    window, so the launch is bound by its arithmetic and latency, not by
+    memory."""
+    import torch
+    import paper_2012_10091_amd as m
+    stream = torch.cuda.Stream()
+    scratch = cyc.members.clone()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        cyc.ctx.forecast(m.MENKF_COARSE, scratch, cfg.n_obs, stream=stream)
+        ev0.record(stream)
+        for _ in range(reps):
+            cyc.ctx.forecast(m.MENKF_COARSE, scratch, cfg.n_obs, stream=stream)
+        ev1.record(stream)
+    stream.synchronize()
+    avg_s = ev0.elapsed_time(ev1) / 1e3 / reps
+    pts = cfg.n_members * cfg.nxc
+    flops = BURGERS_FLOPS_PER_POINT_STEP * pts * cfg.n_obs
+    return {
+        "bound": "alu", "unit": "TFLOP/s", "peak": FP32_NONPACKED_PEAK_TFLOPS,
+        "kernel": f"burgers_window_lds<float,*> (one workgroup per member, the row in LDS for the "
+                  f"{cfg.n_obs}-step window; {cfg.n_members} x {cfg.nxc})",
+        "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops,
+        "flops_per_point_step": BURGERS_FLOPS_PER_POINT_STEP,
+        "achieved": flops / avg_s / 1e12, "hbm_bytes_per_launch": 2.0 * pts * 4,
+        "hbm_gbs": 2.0 * pts * 4 / avg_s / 1e9,
     }
 
 
@@ -343,11 +397,12 @@ def update_gemm_utilisation(cfg, cyc, reps=20):
     stream.synchronize()
     avg = e0.elapsed_time(e1) / 1e3 / reps
     N = cfg.n_members
-    npts = cfg.n_coarse * 4
+    npts = cfg.n_coarse * cfg.nfields
     terms = 3
     flops = terms * 2.0 * N * (N + 1) * npts
     nbytes = 2.0 * N * npts * 4
-    return {"kernel": "update_bf16 (X Z, BF16x3 on MFMA, FP32 accumulation)", "avg_launch_us": avg * 1e6,
+    name = "update_wave" if N <= 128 else "update_bf16"
+    return {"kernel": f"{name} (X Z, BF16x3 on MFMA, FP32 accumulation)", "avg_launch_us": avg * 1e6,
             "mfma_tflops": flops / avg / 1e12, "mfma_frac_of_bf16_peak": flops / avg / 1e12 / BF16_MFMA_PEAK_TFLOPS,
             "hbm_gbs": nbytes / avg / 1e9, "hbm_frac": nbytes / avg / 1e9 / HBM_PEAK_GBS}
 
@@ -388,10 +443,13 @@ def gain_fp64_utilisation(cfg, cyc, reps=5):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ns_march_pair_64x4x256sq_traffic.md")
 
 
-def measured_traffic(schedule):
+def measured_traffic(schedule, cfg):
     """HBM bytes per launch of the stage kernel from the committed counter
-    summary, or None when the kernel source or the schedule differs from the
-    one the counters were taken on."""
+    summary, or None when the kernel source, the ensemble's shape or the
+    schedule differs from the one the counters were taken on
+    (64 x 4 x 256^2)."""
+    if (cfg.n_members, cfg.nyc, cfg.nxc) != (64, 256, 256):
+        return None
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
@@ -420,27 +478,34 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(cfg, k=5):
+def cpu_baseline(cfg, budget_s=12.0):
     """The FP64 oracle on the host: the fine forecast and the forecast of all
-    members (one batch, as in a cycle) over the first k of a cycle's time
-    steps, then the analysis, Pi_F and three sweeps; the forecasts scaled to
-    the cycle's n_obs steps."""
+    members (one batch, as in a cycle) step by step until the cycle's n_obs
+    steps are done or the forecasts have taken about budget_s, then the
+    analysis, Pi_F and three sweeps; the forecasts scaled to the cycle's
+    n_obs steps when fewer were timed."""
+    import numpy as np
     from oracle import cycle as ocycle
     from oracle import enkf, grids, rng, smooth
     from oracle.models import Model
     from synthetic import fields
     cores = len(os.sched_getaffinity(0))
-    k = min(k, cfg.n_obs)
     mf, mc = Model(cfg, "fine"), Model(cfg, "coarse")
     idx, comp = fields.probes_for(cfg)
     y = ocycle.observe_truth(cfg, fields.truth_ic(cfg), idx, comp)
     eps = rng.perturbations(cfg.seed + 5, 1, cfg.n_members, cfg.n_probes, cfg.obs_sigma)
-    t = time.perf_counter()
-    xf, xf_prev = mf.forecast(fields.model_ic(cfg), k)
-    t_fine = time.perf_counter() - t
-    t = time.perf_counter()
-    mem, _ = mc.forecast(fields.member_ics(cfg), k)
-    t_mem = time.perf_counter() - t
+    xf = np.asarray(fields.model_ic(cfg), dtype=np.float64)
+    mem = np.asarray(fields.member_ics(cfg), dtype=np.float64)
+    t_fine = t_mem = 0.0
+    k = 0
+    while k < cfg.n_obs and (k == 0 or t_fine + t_mem < budget_s):
+        t = time.perf_counter()
+        xf, xf_prev = mf.forecast(xf, 1)
+        t_fine += time.perf_counter() - t
+        t = time.perf_counter()
+        mem, _ = mc.forecast(mem, 1)
+        t_mem += time.perf_counter() - t
+        k += 1
     t = time.perf_counter()
     res = enkf.analysis(mem, grids.restrict(xf, cfg.ratio, cfg.dim), y, eps, ocycle.make_H(cfg, idx, comp),
                         cfg.obs_sigma)
@@ -449,6 +514,7 @@ def cpu_baseline(cfg, k=5):
     smooth.smooth(xf + grids.prolong(res["delta"], cfg.ratio, cfg.dim), xf_prev, mf, 3, 0.5)
     t_pro = time.perf_counter() - t
     per_cycle = cfg.n_obs / k * (t_fine + t_mem) + t_an + t_pro
+    scaled = f"forecasts scaled by {cfg.n_obs}/{k}" if k < cfg.n_obs else "a whole cycle, not scaled"
     return {
         "value": 1.0 / per_cycle,
         "unit": "cycles/s",
@@ -457,19 +523,16 @@ def cpu_baseline(cfg, k=5):
         "kind": "oracle",
         "sample": (f"{k} of a cycle's {cfg.n_obs} time steps of the fine state ({t_fine:.1f}s) and of all "
                    f"{cfg.n_members} members in one batch ({t_mem:.1f}s), one analysis ({t_an:.1f}s), "
-                   f"Pi_F + 3 sweeps ({t_pro:.1f}s); forecasts scaled by {cfg.n_obs}/{k}"),
+                   f"Pi_F + 3 sweeps ({t_pro:.1f}s); {scaled}"),
     }
 
 
 def load_net(cfg, path, judge_every):
     from paper_2012_10091_amd import learned
-    path = path or learned.DEFAULT_WEIGHTS
+    path = path or learned.weights_for(cfg.name)
     if not os.path.exists(path):
         return None, path
     return learned.load(path, guard=10.0, judge_every=judge_every), path
-
-
-FP32_NONPACKED_PEAK_TFLOPS = 78.6   # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (packed FP32 off)
 
 
 def bench_train(args):
@@ -643,17 +706,17 @@ def bench_batch(args):
         },
     }
     if args.cpu_baseline:
-        # the oracle's cycle of one instance per fine side (2 of its 20 time
-        # steps timed, the rest scaled), and the batch as 16 times those three
+        # the oracle's cycle of one instance per fine side (its forecasts
+        # timed for about 4 s, the rest scaled), and the batch as 16 times those three
         sample = []
         for side in sorted({c.nx for c in cfgs}):
             c = next(c for c in cfgs if c.nx == side)
             log(f"bench: timing the oracle on {c.name} (bounded sample)")
-            sample.append((c.name, 1.0 / cpu_baseline(c, k=2)["value"]))
+            sample.append((c.name, 1.0 / cpu_baseline(c, budget_s=4.0)["value"]))
         per_batch = len(cfgs) / len(sample) * sum(t for _, t in sample)
         out["cpu_baseline"] = {"value": 1.0 / per_batch, "unit": "batch cycles/s", "cores": len(os.sched_getaffinity(0)),
                                "cpu": cpu_model(), "kind": "oracle",
-                               "sample": "cycles (2 of 20 forecast steps timed, scaled) of " + ", ".join(f"{n} ({t:.1f}s)" for n, t in sample)
+                               "sample": "cycles (forecast steps timed for ~4 s each, scaled to 20) of " + ", ".join(f"{n} ({t:.1f}s)" for n, t in sample)
                                          + f"; the batch of {len(cfgs)} taken as {len(cfgs) // len(sample)} times these"}
     print(json.dumps(out), flush=True)
 
@@ -1162,7 +1225,7 @@ def traffic_probe(args):
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    cfg = make_cfg(args.small)
+    cfg = make_cfg(args)
     cyc = Cycle(cfg, args.sweeps)
     if args.schedule:
         apply_schedule(cyc.ctx, parse_schedule(args.schedule))
@@ -1197,7 +1260,7 @@ def main():
     import torch
     import paper_2012_10091_amd as m
     m.load_library()
-    cfg = make_cfg(args.small)
+    cfg = make_cfg(args)
     n_cyc = args.warmup + args.steps
     log(f"bench: workload {cfg.name}, warmup {args.warmup}, steps {args.steps}")
     Y, _ = truth_observations(cfg, n_cyc)
@@ -1219,7 +1282,7 @@ def main():
     variants = {"plain": {"cycles_per_s": plain_cps, "ms_per_cycle": sec / args.steps * 1e3,
                           "prolongation": f"Pi_F + {args.sweeps} relaxed sweeps"}}
     value, ms = plain_cps, sec / args.steps * 1e3
-    net, wpath = load_net(cfg, args.weights, args.judge_every)
+    net, wpath = load_net(cfg, args.weights, args.judge_every) if cfg.dim == 2 else (None, None)
     headline = "plain"
     if net is not None and not args.small:
         learned = Cycle(cfg, args.sweeps, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
@@ -1258,19 +1321,55 @@ def main():
         variants["learned_ensemble_space_gain"] = {
             "cycles_per_s": ecps, "ms_per_cycle": esec / args.steps * 1e3,
             "gain": "(s^2 I + Y^T Y)^-1 Y^T [D | d*], N x N FP64 Cholesky (exact identity; not the headline)"}
-    elif net is None:
+    elif net is None and cfg.dim == 2:
         log(f"bench: no trained weights at {wpath}; learned variant not timed")
-    rl = stage_kernel_roofline(cfg, plain)
-    log(f"bench: stage kernel avg {rl['avg_launch_us']:.1f} us, algorithmic {rl['achieved']:.0f} GB/s "
-        f"({100 * rl['achieved'] / HBM_PEAK_GBS:.1f} % of HBM peak), contract {rl['achieved_contract']:.0f} GB/s")
+    if cfg.dim == 2:
+        rl = stage_kernel_roofline(cfg, plain)
+        log(f"bench: stage kernel avg {rl['avg_launch_us']:.1f} us, algorithmic {rl['achieved']:.0f} GB/s "
+            f"({100 * rl['achieved'] / HBM_PEAK_GBS:.1f} % of HBM peak), contract {rl['achieved_contract']:.0f} GB/s")
+        roofline = {
+            "bound": "hbm",
+            "achieved": rl["achieved"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": rl["achieved"] / HBM_PEAK_GBS,
+            "traffic": rl["traffic"],
+            "kernel": rl["kernel"],
+            "avg_launch_us": rl["avg_launch_us"],
+            "algorithmic_bytes_per_launch": rl["min_bytes"],
+            "algorithmic_bytes": "one read and one write of the state per time step (2 F 4 B per point), "
+                                 "shared equally by the launches of a step",
+            "launches_per_step": rl["launches_per_step"],
+            "contract_bytes_per_launch": rl["contract_bytes"],
+            "contract_gbs": rl["achieved_contract"],
+            "contract_frac": rl["achieved_contract"] / HBM_PEAK_GBS,
+            "traffic_vs_algorithmic": (rl["traffic"] / rl["min_bytes"]) if rl["traffic"] else None,
+            "infinity_cache_split": MALL_NOTE,
+        }
+    else:
+        rl = window_kernel_roofline(cfg, plain)
+        log(f"bench: window kernel avg {rl['avg_launch_us']:.1f} us, {rl['achieved']:.2f} TFLOP/s FP32 "
+            f"({100 * rl['achieved'] / rl['peak']:.1f} % of the vector peak), HBM {rl['hbm_gbs']:.0f} GB/s")
     gu = gain_fp64_utilisation(cfg, plain)
     log(f"bench: gain {gu['avg_us']:.0f} us, {gu['tflops']:.1f} TFLOP/s FP64 "
         f"({100 * gu['frac_of_fp64_peak']:.1f} % of peak)")
+    if cfg.dim == 1:
+        # the 1D member forecast keeps every row in LDS for the window and
+        # takes a few per cent of a cycle; the gain (FP64 S, Cholesky of the
+        # N_y x N_y matrix, solves) dominates, so it is the roofline call
+        roofline = {"bound": "mfma", "achieved": gu["tflops"], "peak": FP64_PEAK_TFLOPS_MATRIX, "unit": "TFLOP/s",
+                    "frac": gu["frac_of_fp64_peak"], "traffic": None,
+                    "kernel": f"menkf_gain: FP64 S = Y Y^T + R on MFMA, blocked FP64 Cholesky of the "
+                              f"{cfg.n_probes} x {cfg.n_probes} matrix with the solves, Z",
+                    "avg_call_us": gu["avg_us"], "algorithmic_flops_per_call": gu["flops"],
+                    "algorithmic_flops": "2 N_y^2 N (S) + N_y^3 / 3 (Cholesky) + 2 N_y^2 (N + 1) (solves) "
+                                         "+ 2 N_y N (N + 1) (Z)",
+                    "member_forecast": rl}
     ug = update_gemm_utilisation(cfg, plain)
     log(f"bench: member update {ug['avg_launch_us']:.1f} us, MFMA {ug['mfma_tflops']:.0f} TFLOP/s "
         f"({100 * ug['mfma_frac_of_bf16_peak']:.1f} % of BF16 peak), HBM {ug['hbm_gbs']:.0f} GB/s")
     out = {
-        "metric": METRIC,
+        "metric": metric_for(cfg),
         "value": value,
         "unit": "cycles/s",
         "n_gpus": 1,
@@ -1289,29 +1388,12 @@ def main():
             "schedules": {k: {"tile": list(v["tile"]), "member_chunk": v["member_chunk"]} for k, v in tuned.items()}
             if tuned else "default",
             "precision": "FP32 stencils, FP64 innovation covariance/Cholesky/gain of x*, BF16x3 member update",
+            "fields": cfg.nfields,
             "anomaly_gemm": ug,
             "gain_fp64": gu,
             "variants": variants,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": rl["achieved"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": rl["achieved"] / HBM_PEAK_GBS,
-            "traffic": rl["traffic"],
-            "kernel": rl["kernel"],
-            "avg_launch_us": rl["avg_launch_us"],
-            "algorithmic_bytes_per_launch": rl["min_bytes"],
-            "algorithmic_bytes": "one read and one write of the state per time step (2 F 4 B per point), "
-                                 "shared equally by the launches of a step",
-            "launches_per_step": rl["launches_per_step"],
-            "contract_bytes_per_launch": rl["contract_bytes"],
-            "contract_gbs": rl["achieved_contract"],
-            "contract_frac": rl["achieved_contract"] / HBM_PEAK_GBS,
-            "traffic_vs_algorithmic": (rl["traffic"] / rl["min_bytes"]) if rl["traffic"] else None,
-            "infinity_cache_split": MALL_NOTE,
-        },
+        "roofline": roofline,
     }
     if args.cpu_baseline and not args.small:
         log("bench: timing the oracle on the host (bounded sample)")
