@@ -361,10 +361,9 @@ __device__ __forceinline__ void chol_diag_block(const double *src, long long lds
 // The pivots are those of the unblocked sweep (the diagonal of the
 // successive Schur complements); a pivot that is not positive is recorded
 // and the first one reported through the status word, outputs untouched.
-// The 16-pivot sweep: lane l holds column c = l % 16, rows r = 4 (l / 16) + e
-// (e < 4) of the sub-block (w, the block being reduced, and x, the rows of
-// the inverse, both unscaled as in chol_diag_block); at the end
-// L[r][c] = w / sqrt(p_c) and L^-1[r][c] = x / sqrt(p_r).
+// In the 16-pivot sweep the block being reduced and the rows of the
+// inverse are both unscaled, as in chol_diag_block; at the end
+// L[r][c] = W[r][c] / sqrt(p_c) and L^-1[r][c] = X[r][c] / sqrt(p_r).
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -390,55 +389,58 @@ __device__ __forceinline__ double row_bcast(double v) {
 // triangle read), by one wave: L_ss over the lower triangle of Ws (zeros
 // above), L_ss^-1 into Ts (16 x 16, zeros above), the pivots into piv[16].
 // Returns 1 + the first non-positive pivot (0 if none); uniform.
+// Lane l holds column c = l % 16 of W, rows r = 4 (l / 16) + e, and the
+// inverse rows transposed: xt[e] = X[c][r].  With m_c = W[j][c] / p_j for
+// c > j (0 otherwise), step j is
+//   W[r][c] -= W[r][j] m_c     (every r: rows r <= j change only above the
+//                               diagonal, which is never read back)
+//   X[c][k] -= m_c X[j][k]     (X[j][k]: lane j of the caller's 16-lane row)
+// so both updates share the one per-lane multiplier m_c and need no mask on
+// the rows; the pivot column and X[j][.] arrive by row broadcasts, the
+// pivot row by a lane permute.
 __device__ __forceinline__ int chol16_wave(double *Ws, double *Ts, double *piv) {
     const int l = threadIdx.x & 63, q = l >> 4, c = l & 15;
-    double w[4], x[4];
+    double w[4], xt[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int r = 4 * q + e;
         w[e] = r >= c ? Ws[r * LDP + c] : Ws[c * LDP + r];
-        x[e] = r == c ? 1.0 : 0.0;
+        xt[e] = r == c ? 1.0 : 0.0;
     }
-    // the sweep is one basic block (no branch): the scheduler can issue a
-    // step's lane exchanges as soon as the previous step has produced them
-    int bad = 0;
     static_for<0, 16>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
         constexpr int jq = j >> 2, je = j & 3;
         const double p = readlane_d(w[je], 16 * jq + j);   // W[j][j]
-        bad = (bad == 0 && !(p > 0.0)) ? j + 1 : bad;
         const double inv = pivot_recip(p);   // garbage after a bad pivot: the outputs are not written then
-        const int src = 16 * jq + c;   // lane holding (row j, column c)
-        const double rowj = __shfl(w[je], src);
-        const double xrowj = __shfl(x[je], src);
-        const double vr = c > j ? rowj : 0.0;
-        // the four rows' multipliers first (independent chains), then the updates
-        double colj[4], m[4];
+        const double rowj = __shfl(w[je], 16 * jq + c);   // W[j][c]
+        const double mc = c > j ? rowj * inv : 0.0;
+        double colj[4], xj[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) colj[e] = row_bcast<j>(w[e]);   // W[4 q + e][j]
+        for (int e = 0; e < 4; ++e) colj[e] = row_bcast<j>(w[e]);    // W[4 q + e][j]
 #pragma unroll
-        for (int e = 0; e < 4; ++e) m[e] = 4 * q + e > j ? colj[e] * inv : 0.0;
+        for (int e = 0; e < 4; ++e) xj[e] = row_bcast<j>(xt[e]);     // X[j][4 q + e]
 #pragma unroll
-        for (int e = 0; e < 4; ++e) w[e] = fma(-m[e], vr, w[e]);
+        for (int e = 0; e < 4; ++e) w[e] = fma(-colj[e], mc, w[e]);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[e] = fma(-m[e], xrowj, x[e]);
+        for (int e = 0; e < 4; ++e) xt[e] = fma(-mc, xj[e], xt[e]);
     });
     // the diagonal of w is the pivot sequence
 #pragma unroll
     for (int e = 0; e < 4; ++e)
         if (4 * q + e == c) piv[c] = w[e];
     wave_sync();
-    const double rdc = 1.0 / sqrt(piv[c]);
+    const double pc = piv[c];
+    const unsigned long long nonpos = __ballot(l < 16 && !(pc > 0.0));
+    const int bad = nonpos ? __builtin_ctzll(nonpos) + 1 : 0;
+    const double rdc = 1.0 / sqrt(pc);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int r = 4 * q + e;
-        const double rdr = 1.0 / sqrt(piv[r]);
-        Ws[r * LDP + c] = r > c ? w[e] * rdc : (r == c ? sqrt(piv[c]) : 0.0);
-        Ts[r * 16 + c] = r >= c ? x[e] * rdr : 0.0;
+        Ws[r * LDP + c] = r > c ? w[e] * rdc : (r == c ? sqrt(pc) : 0.0);
+        Ts[c * 16 + r] = c >= r ? xt[e] * rdc : 0.0;   // L^-1[c][r] = X[c][r] / d_c
     }
     return bad;
 }
-
 // acc (16x16, MFMA result layout) += A B over K = 16: A at Pa (row stride
 // lda), B given transposed (Bt[n][k]) at Pb (row stride ldb).  One wave.
 __device__ __forceinline__ void mfma16_nt(const double *Pa, int lda, const double *Pb, int ldb, f64x4 &acc) {
