@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--weights", default=None)
     ap.add_argument("--small", action="store_true", help="tiny workload (functional check only)")
     ap.add_argument("--autotune", type=int, default=1, help="autotune the forecast schedules first")
+    ap.add_argument("--pipelined", type=int, default=1,
+                    help="time pipelined cycles (each cycle's fine-grid correction applied at the start of the next, "
+                         "beside its factorisation); the ordinary cycles are timed beside them")
     ap.add_argument("--workload", default="ns2d_1024_256_n64",
                     choices=["ns2d_1024_256_n64", "ns2d_512_128_n32", "burgers1d_16384_4096_n256", "uneven48",
                              "inlet_dual", "euler_dual", "learned_train"],
@@ -92,7 +95,7 @@ def metric_for(cfg):
 class Cycle:
     """Device state of one assimilation instance and its captured cycle."""
 
-    def __init__(self, cfg, n_sweeps, mode=0, net=None):
+    def __init__(self, cfg, n_sweeps, mode=0, net=None, pipelined=False):
         import torch
 
         import paper_2012_10091_amd as m
@@ -116,6 +119,7 @@ class Cycle:
         self.graph = None
         self.aux = torch.cuda.Stream()
         self.overlap = True
+        self.pipelined = pipelined
 
     def autotune(self):
         """Pick the forecast schedules of both levels with the library's autotuner."""
@@ -128,12 +132,15 @@ class Cycle:
         return self.tuned
 
     def issue(self, stream):
-        """One cycle (menkf_cycle).  With overlap, the fine forecast runs on a
-        second stream beside the members' (at 1024^2/256^2 this no longer
-        pays: both forecasts fill the GPU)."""
+        """One cycle (menkf_cycle).  With overlap the fine forecast runs on a
+        second stream beside the late block steps of the factorisation;
+        pipelined cycles apply the previous cycle's fine-grid correction
+        there too, ahead of the fine forecast (each replay still does one
+        whole cycle of work)."""
         self.ctx.cycle(self.fine, self.prev, self.members, self.xs, self.dc, self.y, self.seed,
                        self.m.MENKF_CYCLE_DEVICE, self.cfg.n_obs, n_sweeps=self.n_sweeps, alpha=0.5, mode=self.mode,
-                       net=self.net, stream=stream, aux_stream=self.aux if self.overlap else None)
+                       net=self.net, stream=stream, aux_stream=self.aux if self.overlap else None,
+                       pipelined=self.pipelined)
 
     def set_state(self, fine, members):
         self.fine.copy_(fine)
@@ -1265,7 +1272,8 @@ def main():
     log(f"bench: workload {cfg.name}, warmup {args.warmup}, steps {args.steps}")
     Y, _ = truth_observations(cfg, n_cyc)
     log("bench: observations ready")
-    plain = Cycle(cfg, args.sweeps)
+    pipe = bool(args.pipelined)
+    plain = Cycle(cfg, args.sweeps, pipelined=pipe)
     tuned = None
     if args.schedule:
         apply_schedule(plain.ctx, parse_schedule(args.schedule))
@@ -1280,12 +1288,24 @@ def main():
     plain_cps = args.steps / sec
     log(f"bench: plain {plain_cps:.2f} cycles/s (graph events {sec:.3f}s, wall {wall:.3f}s), status {status}")
     variants = {"plain": {"cycles_per_s": plain_cps, "ms_per_cycle": sec / args.steps * 1e3,
-                          "prolongation": f"Pi_F + {args.sweeps} relaxed sweeps"}}
+                          "prolongation": f"Pi_F + {args.sweeps} relaxed sweeps", "pipelined": pipe}}
+
+    def ordinary(mode=0, net=None):
+        # the same cycle with the correction at its end (not pipelined)
+        o = Cycle(cfg, args.sweeps, mode=mode, net=net)
+        if tuned:
+            apply_schedule(o.ctx, {k: (tuple(v["tile"]), v["member_chunk"]) for k, v in tuned.items()})
+        osec, _ = time_cycles(o, Y, args.warmup, args.steps)
+        return {"cycles_per_s": args.steps / osec, "ms_per_cycle": osec / args.steps * 1e3, "pipelined": False}
+
+    if pipe:
+        variants["plain_ordinary"] = ordinary()
+        log(f"bench: plain, ordinary cycles {variants['plain_ordinary']['cycles_per_s']:.2f} cycles/s")
     value, ms = plain_cps, sec / args.steps * 1e3
     net, wpath = load_net(cfg, args.weights, args.judge_every) if cfg.dim == 2 else (None, None)
     headline = "plain"
     if net is not None and not args.small:
-        learned = Cycle(cfg, args.sweeps, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
+        learned = Cycle(cfg, args.sweeps, mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net, pipelined=pipe)
         net.judge_stats.zero_()
         if tuned:
             learned.ctx.set_schedule(m.MENKF_FINE, tuned["fine"]["tile"], tuned["fine"]["member_chunk"])
@@ -1303,7 +1323,10 @@ def main():
                                "prolongation": f"network; judged every {net.judge_every} cycles against Pi_F + "
                                                f"{args.sweeps} sweeps (its fallback above distance {net.judge_tol})",
                                "timed_cycles_judged": int(tjs[1]), "timed_cycles_on_plain": int(tjs[2]),
-                               "weights": os.path.relpath(wpath, ROOT)}
+                               "weights": os.path.relpath(wpath, ROOT), "pipelined": pipe}
+        if pipe:
+            variants["learned_ordinary"] = ordinary(m.MENKF_PROLONG_LEARNED_FALLBACK, net)
+            log(f"bench: learned, ordinary cycles {variants['learned_ordinary']['cycles_per_s']:.2f} cycles/s")
         variants["rmse"] = cmp
         if cmp["equal_rmse"] and lstatus == 0:
             value, ms, headline = lcps, lsec / args.steps * 1e3, "learned"
@@ -1311,7 +1334,7 @@ def main():
         # identity for R = s^2 I; not the headline, which keeps the N_y x N_y
         # FP64 Cholesky of the workload)
         ens = Cycle(with_gain_mode(cfg, m.MENKF_GAIN_ENSEMBLE_SPACE), args.sweeps,
-                    mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net)
+                    mode=m.MENKF_PROLONG_LEARNED_FALLBACK, net=net, pipelined=pipe)
         if tuned:
             ens.ctx.set_schedule(m.MENKF_FINE, tuned["fine"]["tile"], tuned["fine"]["member_chunk"])
             ens.ctx.set_schedule(m.MENKF_COARSE, tuned["coarse"]["tile"], tuned["coarse"]["member_chunk"])

@@ -550,7 +550,24 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  * of Z are bitwise those of menkf_gain; z*, delta^C and the fine state
  * agree with it to FP64 roundoff.  In the other gain modes the fine
  * forecast runs beside the member forecast and results are bitwise the
- * same as without aux_stream. */
+ * same as without aux_stream.
+ *
+ * pipelined = 1 defers the fine-grid correction (Algo. 4 steps 5-6) by one
+ * call, software pipelining of consecutive cycles: the call begins with the
+ * correction left pending by the previous pipelined call,
+ *   menkf_prolong_smooth(deltac, fine, fine_prev, n_sweeps, alpha, prolong_mode, net),
+ * and ends with menkf_update, leaving its own delta^C pending in deltac
+ * (a device word of the context records whether a correction is pending:
+ * none after menkf_set_workspace or menkf_cycle_flush, so the first
+ * pipelined call corrects nothing).  With aux_stream the pending correction
+ * runs there ahead of the fine forecast (with MENKF_GAIN_EXACT_R beside the
+ * late block steps of the factorisation), off the member chain that bounds
+ * the cycle.  After the call fine holds the uncorrected forecast x^F_f;
+ * menkf_cycle_flush applies the pending correction, after which K
+ * pipelined calls have given bitwise the results of K calls with
+ * pipelined = 0.  Flush before reading fine as an analysis, before a call
+ * with pipelined = 0 and before changing n_sweeps, alpha, prolong_mode or
+ * net.  feedback must be 0 (it needs the corrected state). */
 typedef struct {
     menkf_ctx *ctx;
     void *fine, *fine_prev, *members, *xstar, *deltac;
@@ -561,10 +578,17 @@ typedef struct {
     int32_t prolong_mode;
     const menkf_net *net;
     menkf_stream aux_stream;
-    int32_t feedback;   /* 1: end the cycle with menkf_recentre(members, fine) */
+    int32_t feedback;    /* 1: end the cycle with menkf_recentre(members, fine) */
+    int32_t pipelined;   /* 1: correction deferred to the next call (above) */
 } menkf_cycle_args;
 
 menkf_status menkf_cycle(const menkf_cycle_args *args, menkf_stream stream);
+
+/* The correction left pending by the last pipelined menkf_cycle of
+ * args->ctx (fine, fine_prev, deltac, n_sweeps, alpha, prolong_mode and net
+ * of args, as that call had them; nothing when none is pending), issued on
+ * stream; clears the pending word.  Capturable. */
+menkf_status menkf_cycle_flush(const menkf_cycle_args *args, menkf_stream stream);
 
 /* Batch of independent instances of uneven sizes advanced together: a
  * batch owns n_lanes HIP streams (default priority) and their events.

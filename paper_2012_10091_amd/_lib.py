@@ -83,6 +83,7 @@ class MenkfCycleArgs(ctypes.Structure):
         ("net", ctypes.POINTER(MenkfNet)),
         ("aux_stream", c_void_p),
         ("feedback", c_int32),
+        ("pipelined", c_int32),
     ]
 
 
@@ -140,6 +141,7 @@ SIGNATURES = {
     "menkf_diagnostics_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "menkf_ram_ratio": (c_double, [c_int32, c_int32, c_int32]),
     "menkf_cycle": (c_int32, [ctypes.POINTER(MenkfCycleArgs), c_void_p]),
+    "menkf_cycle_flush": (c_int32, [ctypes.POINTER(MenkfCycleArgs), c_void_p]),
     "menkf_batch_create": (c_int32, [c_int32, ctypes.POINTER(c_void_p)]),
     "menkf_batch_destroy": (None, [c_void_p]),
     "menkf_batch_cycle": (c_int32, [c_void_p, ctypes.POINTER(MenkfCycleArgs), c_int32, c_void_p]),

@@ -326,7 +326,7 @@ class Context:
 
     def cycle_args(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
                    n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None,
-                   aux_stream=None, feedback: bool = False):
+                   aux_stream=None, feedback: bool = False, pipelined: bool = False):
         """The menkf_cycle_args of one cycle of this instance (buffers checked here)."""
         self._state(fine, self.fine_shape, "fine")
         self._state(fine_prev, self.fine_shape, "fine_prev")
@@ -350,14 +350,31 @@ class Context:
         if aux_stream is not None:
             a.aux_stream = aux_stream.cuda_stream
         a.feedback = 1 if feedback else 0
+        a.pipelined = 1 if pipelined else 0
         return a
 
     def cycle(self, fine, fine_prev, members, xstar, deltac, yobs, seed: int, cycle: int, nsteps: int,
               n_sweeps: int = 1, alpha: float = 0.5, mode: int = MENKF_PROLONG_PLAIN, net=None, stream=None,
-              aux_stream=None, feedback: bool = False):
+              aux_stream=None, feedback: bool = False, pipelined: bool = False):
         a = self.cycle_args(fine, fine_prev, members, xstar, deltac, yobs, seed, cycle, nsteps, n_sweeps, alpha,
-                            mode, net, aux_stream, feedback)
+                            mode, net, aux_stream, feedback, pipelined)
         self._check(self.lib.menkf_cycle(ctypes.byref(a), _stream(stream)))
+
+    def cycle_flush(self, fine, fine_prev, deltac, n_sweeps: int = 1, alpha: float = 0.5,
+                    mode: int = MENKF_PROLONG_PLAIN, net=None, stream=None):
+        """menkf_cycle_flush: the correction a pipelined cycle left pending."""
+        self._state(fine, self.fine_shape, "fine")
+        self._state(fine_prev, self.fine_shape, "fine_prev")
+        self._state(deltac, self.coarse_shape, "deltac")
+        a = _lib.MenkfCycleArgs()
+        a.ctx = self.handle
+        a.fine, a.fine_prev, a.deltac = _ptr(fine), _ptr(fine_prev), _ptr(deltac)
+        a.n_sweeps, a.alpha, a.prolong_mode = n_sweeps, alpha, mode
+        if net is not None:
+            ns = net if isinstance(net, _lib.MenkfNet) else net.c_struct()
+            a.net = ctypes.pointer(ns)
+            a._keep = ns
+        self._check(self.lib.menkf_cycle_flush(ctypes.byref(a), _stream(stream)))
 
     def recentre(self, members: torch.Tensor, xf: torch.Tensor, stream=None):
         self._state(members, self.coarse_shape, "members")

@@ -258,6 +258,7 @@ menkf_status menkf_set_workspace(menkf_ctx *ctx, void *ws, size_t bytes) {
     if (e == hipSuccess) e = launch_set_word((int32_t *)((char *)ws + ctx->plan.off_info), 0, nullptr);
     if (e == hipSuccess) e = launch_set_word64((uint64_t *)((char *)ws + ctx->plan.off_info + 64), 1, nullptr);
     if (e == hipSuccess) e = launch_zero_words((int32_t *)((char *)ws + ctx->plan.off_info + JUDGE_WORDS), JW_N, nullptr);
+    if (e == hipSuccess) e = launch_zero_words((int32_t *)((char *)ws + ctx->plan.off_info + PIPE_WORDS), PW_N, nullptr);
     if (e != hipSuccess) return hip_fail(ctx, e, "menkf_set_workspace");
     return MENKF_OK;
 }
@@ -456,13 +457,12 @@ menkf_status menkf_update(menkf_ctx *ctx, void *members, void *dc, menkf_stream 
 // into xf.  Every kernel is launched on every call; the device words of
 // the judge make the unneeded ones return at once.
 static menkf_status learned_with_judge(menkf_ctx *ctx, const void *dc, void *xf, const void *xprev, int n_sweeps,
-                                       double alpha, const menkf_net *net, hipStream_t s) {
+                                       double alpha, const menkf_net *net, const int32_t *info, hipStream_t s) {
     const Plan &p = ctx->plan;
     if (!(net->guard > 0.0f)) return fail(ctx, MENKF_E_ARG, "LEARNED_FALLBACK needs guard > 0");
     if (net->judge_every < 0) return fail(ctx, MENKF_E_ARG, "judge_every must be >= 0");
     if (net->judge_every > 0 && !(net->judge_tol >= 0.0f))
         return fail(ctx, MENKF_E_ARG, "judge_tol must be >= 0 when judging");
-    const int32_t *info = (const int32_t *)((char *)ctx->ws + p.off_info);
     int32_t *jw = (int32_t *)((char *)ctx->ws + p.off_info + JUDGE_WORDS);
     void *W = (char *)ctx->ws + p.off_f1;
     void *P[2] = {(char *)ctx->ws + p.off_f2, (char *)ctx->ws + p.off_facc};
@@ -480,9 +480,12 @@ static menkf_status learned_with_judge(menkf_ctx *ctx, const void *dc, void *xf,
     return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_prolong_smooth (learned with judge)");
 }
 
-menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, const void *xprev, int32_t n_sweeps,
-                                  double alpha, int32_t mode, const menkf_net *net, menkf_stream stream) {
-    NEED_WS(ctx);
+// The correction of menkf_prolong_smooth; every kernel returns at once when
+// *info (the status word, or the skip word of a deferred correction) is
+// non-zero.
+static menkf_status prolong_impl(menkf_ctx *ctx, const void *dc, void *xf, const void *xprev, int32_t n_sweeps,
+                                 double alpha, int32_t mode, const menkf_net *net, const int32_t *info,
+                                 hipStream_t s) {
     const Plan &p = ctx->plan;
     if (!dc || !xf) return fail(ctx, MENKF_E_ARG, "null state pointer");
     if (n_sweeps < 0 || n_sweeps > 64) return fail(ctx, MENKF_E_ARG, "n_sweeps must be in [0, 64]");
@@ -490,8 +493,6 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
     if (!(alpha > 0 && alpha <= 1)) return fail(ctx, MENKF_E_ARG, "alpha must be in (0, 1]");
     if (mode != MENKF_PROLONG_PLAIN && mode != MENKF_PROLONG_LEARNED && mode != MENKF_PROLONG_LEARNED_FALLBACK)
         return fail(ctx, MENKF_E_ARG, "bad prolongation mode %d", mode);
-    hipStream_t s = (hipStream_t)stream;
-    const int32_t *info = (const int32_t *)((char *)ctx->ws + p.off_info);
     void *W = (char *)ctx->ws + p.off_f1;
     hipError_t e;
     const void *src;
@@ -511,7 +512,7 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
         for (int i = 0; i < 4; ++i)
             if (!(net->out_scale[i] != 0.0f)) return fail(ctx, MENKF_E_ARG, "net out_scale must be non-zero");
         if (mode == MENKF_PROLONG_LEARNED_FALLBACK)
-            return learned_with_judge(ctx, dc, xf, xprev, n_sweeps, alpha, net, s);
+            return learned_with_judge(ctx, dc, xf, xprev, n_sweeps, alpha, net, info, s);
         // the network reads x^F_f with a halo: write the result to the workspace copy
         e = launch_net_prolong(p, dc, xf, W, net, 0, info, nullptr, s);
         src = W;
@@ -529,6 +530,24 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_prolong_smooth (copy)");
     }
     return MENKF_OK;
+}
+
+menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, const void *xprev, int32_t n_sweeps,
+                                  double alpha, int32_t mode, const menkf_net *net, menkf_stream stream) {
+    NEED_WS(ctx);
+    const int32_t *info = (const int32_t *)((char *)ctx->ws + ctx->plan.off_info);
+    return prolong_impl(ctx, dc, xf, xprev, n_sweeps, alpha, mode, net, info, (hipStream_t)stream);
+}
+
+// The correction left pending by the last pipelined cycle (none pending:
+// every kernel returns at once), issued on s.
+static menkf_status pending_correction(menkf_ctx *ctx, const menkf_cycle_args *a, hipStream_t s) {
+    const int32_t *info = (const int32_t *)((char *)ctx->ws + ctx->plan.off_info);
+    int32_t *pw = (int32_t *)((char *)ctx->ws + ctx->plan.off_info + PIPE_WORDS);
+    const hipError_t e = launch_pipe_skip(info, pw, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (pending correction)");
+    return prolong_impl(ctx, a->deltac, a->fine, a->fine_prev, a->n_sweeps, a->alpha, a->prolong_mode, a->net,
+                        pw + PW_SKIP, s);
 }
 
 menkf_status menkf_recentre(menkf_ctx *ctx, void *members, const void *xf, menkf_stream stream) {
@@ -767,9 +786,17 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         return fail(ctx, MENKF_E_ARG, "menkf_cycle: null buffer");
     if (a->nsteps < 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: nsteps must be >= 1");
     if (a->feedback != 0 && a->feedback != 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: feedback must be 0 or 1");
+    if (a->pipelined != 0 && a->pipelined != 1) return fail(ctx, MENKF_E_ARG, "menkf_cycle: pipelined must be 0 or 1");
+    if (a->pipelined && a->feedback)
+        return fail(ctx, MENKF_E_ARG, "menkf_cycle: a pipelined cycle cannot recentre on the fine analysis");
     if (!ctx->idx) return fail(ctx, MENKF_E_ARG, "probes not set (menkf_set_probes)");
     menkf_status st;
-    if (a->aux_stream && a->aux_stream != stream && p.defer_ok) {
+    const bool aux = a->aux_stream && a->aux_stream != stream;
+    if (a->pipelined && !aux) {
+        st = pending_correction(ctx, a, (hipStream_t)stream);
+        if (st != MENKF_OK) return st;
+    }
+    if (aux && p.defer_ok) {
         // The fine forecast, x* and the small system of the x* column run on
         // the second stream while the N_y x N_y factorisation (with d* = 0)
         // runs on the first; z* follows once both are done.
@@ -795,7 +822,10 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         if (e0 != hipSuccess) (void)hipEventRecord(ctx->ev_fork, s0);   // keep the fork well formed
         e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
-        st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
+        // a pipelined cycle first applies the previous cycle's correction
+        // here, beside the late block steps and off the member chain
+        st = a->pipelined ? pending_correction(ctx, a, s1) : MENKF_OK;
+        if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
         if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, a->aux_stream);
         // join also after a failed issue, so that a capture stays well formed
         e = hipEventRecord(ctx->ev_join, s1);
@@ -806,12 +836,13 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (join)");
         e = launch_xstar_gain(p, a->xstar, a->yobs, ctx->idx, ctx->comp, ctx->ws, s0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (x* column)");
-    } else if (a->aux_stream && a->aux_stream != stream) {
+    } else if (aux) {
         hipStream_t s0 = (hipStream_t)stream, s1 = (hipStream_t)a->aux_stream;
         hipError_t e = hipEventRecord(ctx->ev_fork, s0);
         if (e == hipSuccess) e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
-        st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
+        st = a->pipelined ? pending_correction(ctx, a, s1) : MENKF_OK;
+        if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
         if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_COARSE, a->members, p.N, a->nsteps, nullptr, stream);
         // join also after a failed issue, so that a capture stays well formed
         e = hipEventRecord(ctx->ev_join, s1);
@@ -827,11 +858,29 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         if (st == MENKF_OK) st = menkf_gain(ctx, a->members, a->xstar, a->yobs, a->seed, a->cycle, nullptr, stream);
     }
     if (st == MENKF_OK) st = menkf_update(ctx, a->members, a->deltac, stream);
+    if (st == MENKF_OK && a->pipelined) {
+        // the correction is left pending for the next call (or the flush)
+        const hipError_t e = launch_set_word((int32_t *)((char *)ctx->ws + p.off_info + PIPE_WORDS) + PW_PEND, 1,
+                                             (hipStream_t)stream);
+        return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_cycle (pending word)");
+    }
     if (st == MENKF_OK)
         st = menkf_prolong_smooth(ctx, a->deltac, a->fine, a->fine_prev, a->n_sweeps, a->alpha, a->prolong_mode,
                                   a->net, stream);
     if (st == MENKF_OK && a->feedback) st = menkf_recentre(ctx, a->members, a->fine, stream);
     return st;
+}
+
+menkf_status menkf_cycle_flush(const menkf_cycle_args *a, menkf_stream stream) {
+    if (!a) return fail(nullptr, MENKF_E_ARG, "args is NULL");
+    menkf_ctx *ctx = a->ctx;
+    NEED_WS(ctx);
+    if (!a->fine || !a->fine_prev || !a->deltac) return fail(ctx, MENKF_E_ARG, "menkf_cycle_flush: null buffer");
+    menkf_status st = pending_correction(ctx, a, (hipStream_t)stream);
+    if (st != MENKF_OK) return st;
+    const hipError_t e = launch_set_word((int32_t *)((char *)ctx->ws + ctx->plan.off_info + PIPE_WORDS) + PW_PEND, 0,
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_cycle_flush");
 }
 
 // Estimated device time (us) of one cycle of an instance, for the lane

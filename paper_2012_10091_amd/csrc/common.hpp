@@ -201,6 +201,11 @@ constexpr int JUDGE_WORDS = 128;
 enum { JW_CALLS = 0, JW_STICK = 1, JW_TILES = 2, JW_SKIP_NET = 3, JW_SKIP_PLAIN = 4, JW_JUDGE = 5, JW_USE_PLAIN = 6,
        JW_N = 8 };
 constexpr int JUDGE_BLOCKS = 512;
+// Words of the pipelined cycle (from byte PIPE_WORDS of the status block):
+// a correction is pending (left by the last pipelined cycle), and the skip
+// word of the deferred correction (no correction pending, or a failure)
+constexpr int PIPE_WORDS = 192;
+enum { PW_PEND = 0, PW_SKIP = 1, PW_N = 2 };
 
 constexpr int CHOL_NB = 64;
 
@@ -276,6 +281,7 @@ size_t diagnostics_noalloc_need(const Plan &p);   // doubles of the array one ca
 size_t diagnostics_noalloc_capacity();              // doubles the array holds
 hipError_t launch_set_word(int32_t *w, int32_t v, hipStream_t s);
 hipError_t launch_set_word64(uint64_t *w, uint64_t v, hipStream_t s);
+hipError_t launch_pipe_skip(const int32_t *info, int32_t *pw, hipStream_t s);
 // learned prolongation
 // gate: the kernel does nothing when *gate != 0 (the status word, or the
 // judge's skip word); tile_count (optional) counts this call's guarded tiles

@@ -241,4 +241,14 @@ hipError_t launch_set_word64(uint64_t *w, uint64_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// skip word of a deferred correction: nothing pending, or a failed analysis
+__global__ void pipe_skip_kernel(const int32_t *__restrict__ info, int32_t *__restrict__ pw) {
+    pw[PW_SKIP] = (pw[PW_PEND] == 0 || *info != 0) ? 1 : 0;
+}
+
+hipError_t launch_pipe_skip(const int32_t *info, int32_t *pw, hipStream_t s) {
+    hipLaunchKernelGGL(pipe_skip_kernel, dim3(1), dim3(1), 0, s, info, pw);
+    return hipGetLastError();
+}
+
 }  // namespace menkf

@@ -406,7 +406,8 @@ hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, voi
 // The plain correction (Pi_F and the relaxed sweeps) judges the network's
 // and replaces it when the network strays: a few single-thread kernels
 // keep the decision on the device, so a captured cycle replays it.
-//   pre:    count the call; judged call when calls % judge_every == 0;
+//   pre:    count the call (not one skipped by its status word); judged
+//           call when calls % judge_every == 0;
 //           skip the network when the plain correction is kept (stick) and
 //           this call is not judged; clear the guarded-tile count
 //   mid:    the plain correction is formed when judged, kept, or a tile
@@ -417,8 +418,8 @@ hipError_t launch_net_prolong(const Plan &p, const void *dc, const void *xf, voi
 //   select: x^F_a = plain or network correction
 __global__ void judge_pre_kernel(const int32_t *__restrict__ info, int32_t *__restrict__ jw, int every) {
     const uint32_t c = (uint32_t)jw[JW_CALLS];
-    const int judge = every > 0 && (c % (uint32_t)every) == 0u;
-    jw[JW_CALLS] = (int32_t)(c + 1u);
+    const int judge = *info == 0 && every > 0 && (c % (uint32_t)every) == 0u;
+    if (*info == 0) jw[JW_CALLS] = (int32_t)(c + 1u);
     jw[JW_JUDGE] = judge;
     jw[JW_TILES] = 0;
     jw[JW_SKIP_NET] = (*info != 0 || (jw[JW_STICK] && !judge)) ? 1 : 0;
