@@ -594,12 +594,16 @@ def bench_train(args):
         "ms_per_step": 1e3 / steps_s, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "learned_train_512_crop128_b16", "pairs": npairs, "crops_per_s": steps_s * batch,
-                   "flops_per_step": fl, "kernels": "menkf_net_train_step: direct convolutions on the vector "
-                                                   "units, BF16 activations, FP32 arithmetic, Adam in FP32"},
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_NONPACKED_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP32_NONPACKED_PEAK_TFLOPS, "traffic": None,
-                     "peak_note": "FP32 FMA on the vector units without packed instructions (the build turns "
-                                  "them off): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz"},
+                   "flops_per_step": fl,
+                   "kernels": "menkf_net_train_step: every convolution on BF16 MFMA 32x32x16 with FP32 "
+                              "accumulation (forward of the three layers, data gradients with the FP32 output "
+                              "gradient as BF16 hi + lo terms, weight gradients as 32 x 32 products over the "
+                              "pixels, one per tap, gradient hi + lo), BF16 activations, Adam in FP32"},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "peak_note": "dense BF16 MFMA peak; achieved counts each convolution MAC of the forward and "
+                                  "both gradients once (not the hi + lo products, nor the zero rows that pad "
+                                  "4 or 8 channels to the 32-wide MFMA tile)"},
     }
     if args.cpu_baseline:
         log("bench: timing the oracle's forward + backward of one crop on the host")

@@ -564,7 +564,6 @@ struct TrainShapes {
     int B, C, H0, H1, H2, H3;
 };
 
-__device__ __forceinline__ float bfr(float v) { return (float)(__bf16)v; }
 
 __global__ __launch_bounds__(256) void train_gather(const float *__restrict__ dproj, const float *__restrict__ xf,
                                                     const float *__restrict__ target, const int32_t *__restrict__ crops,
@@ -593,36 +592,6 @@ __global__ __launch_bounds__(256) void train_gather(const float *__restrict__ dp
     }
 }
 
-// Valid 3x3 convolution, thread per output.  OUT_BF16: BF16 + ReLU output
-// (hidden layers); else FP32 output without activation (last layer).
-template <bool HIDDEN>
-__global__ __launch_bounds__(256) void train_conv_fwd(const __bf16 *__restrict__ in, int Ci, int Hi,
-                                                      const float *__restrict__ w, const float *__restrict__ bias,
-                                                      int Co, int B, void *__restrict__ out) {
-    const int Ho = Hi - 2;
-    const long long per = (long long)Ho * Ho;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= per * Co * B) return;
-    const int b = (int)(t / (per * Co));
-    const long long rem = t - (long long)b * per * Co;
-    const int o = (int)(rem / per);
-    const int pix = (int)(rem - (long long)o * per);
-    const int y = pix / Ho, x = pix - y * Ho;
-    float acc = bias[o];
-    for (int c = 0; c < Ci; ++c) {
-        const __bf16 *ip = in + ((long long)b * Ci + c) * Hi * Hi + (long long)y * Hi + x;
-        const float *wp = w + (o * Ci + c) * 9;
-#pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-            for (int kx = 0; kx < 3; ++kx) acc += bfr(wp[ky * 3 + kx]) * (float)ip[ky * Hi + kx];
-    }
-    if (HIDDEN)
-        ((__bf16 *)out)[t] = (__bf16)fmaxf(acc, 0.0f);
-    else
-        ((float *)out)[t] = acc;
-}
-
 // g = 2 (out - tgt) / n and per-block partial sums of (out - tgt)^2.
 __global__ __launch_bounds__(256) void train_mse(const float *__restrict__ out, const float *__restrict__ tgt, long long n,
                                                  float *__restrict__ g, double *__restrict__ part) {
@@ -642,86 +611,228 @@ __global__ __launch_bounds__(256) void train_mse(const float *__restrict__ out, 
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// loss = sum of the block partials / n: each lane sums a strided subset,
+// then a fixed-order halving over the wave.
 __global__ __launch_bounds__(64) void train_loss_final(const double *__restrict__ part, int nb, long long n,
                                                        double *__restrict__ loss) {
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < nb; ++i) s += part[i];
-        *loss = s / (double)n;
+    __shared__ double s[64];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 64) acc += part[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 32; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *loss = s[0] / (double)n;
 }
 
-// Gradient w.r.t. the input of a valid conv, multiplied by the ReLU mask of
-// that input (act > 0): thread per input element.
-__global__ __launch_bounds__(256) void train_conv_bwd_data(const float *__restrict__ gout, int Co, int Ho,
-                                                           const float *__restrict__ w, const __bf16 *__restrict__ act,
-                                                           int Ci, int B, float *__restrict__ gin) {
-    const int Hi = Ho + 2;
-    const long long per = (long long)Hi * Hi;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= per * Ci * B) return;
-    if (!((float)act[t] > 0.0f)) {
-        gin[t] = 0.0f;
-        return;
-    }
-    const int b = (int)(t / (per * Ci));
-    const long long rem = t - (long long)b * per * Ci;
-    const int c = (int)(rem / per);
-    const int pix = (int)(rem - (long long)c * per);
-    const int y = pix / Hi, x = pix - y * Hi;
-    float acc = 0.0f;
-    for (int o = 0; o < Co; ++o) {
-        const float *gp = gout + ((long long)b * Co + o) * Ho * Ho;
-        const float *wp = w + (o * Ci + c) * 9;
+// A valid 3x3 convolution on MFMA for the training passes, from a source
+// of Cs <= 32 channels (planes Hs x Hs, NCHW, read with a zero border of
+// width pad) to Cd <= 32 channels (planes Hd x Hd, Hd = Hs + 2 pad - 2):
+//   forward (MODE CONV_HIDDEN or CONV_LAST, pad 0): the source is BF16,
+//     z[o][y][x] = bias[o] + sum_{c,k} bf16(W[o][c][k]) src[c][y+ky][x+kx],
+//     dst = bf16(relu(z)) (hidden layers) or z in FP32 (the last layer);
+//   data gradient (MODE CONV_DGRAD, pad 2) of a layer with weights
+//   W[o][c][k] (o < Cs, c < Cd): the source is the FP32 output gradient,
+//   entered as BF16 hi + lo terms, and the taps are flipped,
+//     dst[c][y][x] = (act[c][y][x] > 0) sum_{o,k} bf16(W[o][c][8-k]) gpad[o][y+ky][x+kx].
+// A workgroup (4 waves) loops over tiles of 4 output rows x 32 columns
+// (all Cd channels; wave w takes row w of the tile).  The source tile
+// (6 rows x 34 columns x 32 channels) is staged in LDS channel-innermost,
+// so that a B fragment (8 channels of one pixel) is one 16-byte read; the
+// weight fragments stay in registers for all tiles.  MFMA 32x32x16:
+// A[m = output channel][k = source channel], B[k][n = output column].
+constexpr int CT_Y = 4, CT_X = 32, CT_SR = CT_Y + 2, CT_SC = CT_X + 2, CT_CP = 40;
+enum { CONV_HIDDEN = 0, CONV_LAST = 1, CONV_DGRAD = 2 };
+
+template <int MODE>
+__global__ __launch_bounds__(256) void train_conv_mfma(const void *__restrict__ src_, int Cs, int Hs, int pad,
+                                                       const float *__restrict__ W, const float *__restrict__ bias,
+                                                       int Cd, int Hd, int B, void *__restrict__ dst_,
+                                                       const __bf16 *__restrict__ act) {
+    constexpr bool BWD = MODE == CONV_DGRAD;
+    __shared__ __attribute__((aligned(16))) __bf16 sh[BWD ? 2 : 1][CT_SR * CT_SC * CT_CP];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, h = l >> 5, n = l & 31;
+    const int nch = Cs > 16 ? 2 : 1;                 // K chunks of 16 source channels
+    // weight fragments: lane row m = n (output channel), K = 16 q + 8 h + e
+    bf16x8 wa[2][9];
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
-            const int yy = y - ky;
-            if (yy < 0 || yy >= Ho) continue;
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const int xx = x - kx;
-                if (xx < 0 || xx >= Ho) continue;
-                acc += bfr(wp[ky * 3 + kx]) * gp[yy * Ho + xx];
+        for (int k = 0; k < 9; ++k)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int cs = 16 * q + 8 * h + e;
+                float w = 0.0f;
+                if (n < Cd && cs < Cs) w = BWD ? W[(cs * Cd + n) * 9 + 8 - k] : W[(n * Cs + cs) * 9 + k];
+                wa[q][k][e] = (__bf16)w;
+            }
+    const int tilesx = (Hd + CT_X - 1) / CT_X, tilesy = (Hd + CT_Y - 1) / CT_Y;
+    const int ntiles = B * tilesy * tilesx;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tx = tile % tilesx, ty = (tile / tilesx) % tilesy, b = tile / (tilesx * tilesy);
+        const int x0 = tx * CT_X, y0 = ty * CT_Y;
+        __syncthreads();   // the previous tile's reads are done
+        for (int i = threadIdx.x; i < 32 * CT_SR * CT_SC; i += 256) {
+            const int col = i % CT_SC, rr = (i / CT_SC) % CT_SR, c = i / (CT_SC * CT_SR);
+            const int sy = y0 + rr - pad, sx = x0 + col - pad;
+            float v = 0.0f;
+            if (c < Cs && sy >= 0 && sy < Hs && sx >= 0 && sx < Hs) {
+                const long long gi = (((long long)b * Cs + c) * Hs + sy) * Hs + sx;
+                if constexpr (BWD)
+                    v = ((const float *)src_)[gi];
+                else
+                    v = (float)((const __bf16 *)src_)[gi];
+            }
+            const int li = (rr * CT_SC + col) * CT_CP + c;
+            const __bf16 hi = (__bf16)v;
+            sh[0][li] = hi;
+            if constexpr (BWD) sh[BWD ? 1 : 0][li] = (__bf16)(v - (float)hi);
+        }
+        __syncthreads();
+        f32x16 acc = {};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (q < nch) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const int li = ((wave + k / 3) * CT_SC + n + k % 3) * CT_CP + 16 * q + 8 * h;
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sh[0][li]);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[q][k], bv, acc, 0, 0, 0);
+                    if constexpr (BWD) {
+                        const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(&sh[BWD ? 1 : 0][li]);
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[q][k], bl, acc, 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // element e: output channel 8 (e / 4) + 4 h + e % 4, column x0 + n
+        const int y = y0 + wave, x = x0 + n;
+        if (y < Hd && x < Hd) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int m = 8 * (e >> 2) + 4 * h + (e & 3);
+                if (m < Cd) {
+                    const long long oi = (((long long)b * Cd + m) * Hd + y) * Hd + x;
+                    if constexpr (MODE == CONV_DGRAD)
+                        ((float *)dst_)[oi] = ((float)act[oi] > 0.0f) ? acc[e] : 0.0f;
+                    else if constexpr (MODE == CONV_LAST)
+                        ((float *)dst_)[oi] = acc[e] + bias[m];
+                    else
+                        ((__bf16 *)dst_)[oi] = (__bf16)fmaxf(acc[e] + bias[m], 0.0f);
+                }
             }
         }
     }
-    gin[t] = acc;
 }
 
-// dW[o][c][ky][kx] = sum_{b,y,x} gout[b][o][y][x] in[b][c][y+ky][x+kx]: one
-// block per (o, c), fixed-order reduction.  db[o] from the blocks with c == 0.
-__global__ __launch_bounds__(256) void train_conv_bwd_weight(const float *__restrict__ gout, int Co, int Ho,
-                                                             const __bf16 *__restrict__ in, int Ci, int B,
-                                                             float *__restrict__ dw, float *__restrict__ db) {
-    __shared__ float s[10][256];
-    const int o = blockIdx.x / Ci, c = blockIdx.x % Ci;
-    const int Hi = Ho + 2;
-    float acc[10] = {};
-    const long long per = (long long)Ho * Ho;
-    for (int b = 0; b < B; ++b) {
-        const float *gp = gout + ((long long)b * Co + o) * per;
-        const __bf16 *ip = in + ((long long)b * Ci + c) * Hi * Hi;
-        for (long long p = threadIdx.x; p < per; p += 256) {
-            const int y = (int)(p / Ho), x = (int)(p - (long long)y * Ho);
-            const float g = gp[p];
+// Weight and bias gradients of a valid 3x3 convolution on MFMA (BF16 in,
+// FP32 accumulation): for every tap k = 3 ky + kx
+//   C_k[o][c] = sum_{b,y,x} g[b][o][y][x] in[b][c][y + ky][x + kx]
+// a 32 x 32 product over the output pixels (Co, Ci <= 32, the rest zero).
+// A work item is one 16-pixel run of an output row; the items are split
+// evenly over the waves of the grid.  The FP32 gradient enters as two BF16
+// terms (hi + lo residue), so the products keep about 16 bits of it.  MFMA
+// 32x32x16: lane l holds A[o = l % 32][p = 8 (l / 32) + e] and
+// B[p = 8 (l / 32) + e][c = l % 32].  Per workgroup the waves' sums are
+// added in LDS in wave order and written as one partial; train_wgrad_reduce
+// adds the partials in workgroup order (deterministic).
+constexpr int WG_PART = 9 * 1024 + 32;   // floats per workgroup partial: C_k, then the bias sums
+
+__global__ __launch_bounds__(256) void train_wgrad_mfma(const float *__restrict__ g, int Co, int Ho,
+                                                        const __bf16 *__restrict__ in, int Ci, int B,
+                                                        float *__restrict__ part) {
+    __shared__ float red[WG_PART];
+    const int Hi = Ho + 2, nxc = (Ho + 15) / 16;
+    const long long items = (long long)B * Ho * nxc;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, h = l >> 5, r = l & 31;
+    const long long gw = (long long)blockIdx.x * 4 + wave, nw = (long long)gridDim.x * 4;
+    const long long i0 = items * gw / nw, i1 = items * (gw + 1) / nw;
+    const bool orow = r < Co, ccol = r < Ci;
+    f32x16 acc[9];
 #pragma unroll
-            for (int ky = 0; ky < 3; ++ky)
+    for (int k = 0; k < 9; ++k) acc[k] = f32x16{};
+    float dbs = 0.0f;
+    for (long long it = i0; it < i1; ++it) {
+        const int b = (int)(it / ((long long)Ho * nxc));
+        const int rem = (int)(it - (long long)b * Ho * nxc);
+        const int y = rem / nxc, x0 = 16 * (rem - y * nxc) + 8 * h;
+        // A: 8 gradient values of channel o = r (zero past the row or Co)
+        const float *gp = g + (((long long)b * Co + (orow ? r : 0)) * Ho + y) * Ho;
+        bf16x8 ahi, alo;
 #pragma unroll
-                for (int kx = 0; kx < 3; ++kx) acc[ky * 3 + kx] += g * (float)ip[(y + ky) * Hi + x + kx];
-            acc[9] += g;
+        for (int e = 0; e < 8; ++e) {
+            const int x = x0 + e;
+            const float v = (orow && x < Ho) ? gp[x < Ho ? x : 0] : 0.0f;
+            const __bf16 hi = (__bf16)v;
+            ahi[e] = hi;
+            alo[e] = (__bf16)(v - (float)hi);
+            dbs += v;
+        }
+        // B: input rows y + ky of channel c = r, 10 values from x0 (zero past the row or Ci)
+        const __bf16 *ip = in + (((long long)b * Ci + (ccol ? r : 0)) * Hi + y) * Hi;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            __bf16 v[10];
+#pragma unroll
+            for (int e = 0; e < 10; ++e) {
+                const int x = x0 + e;
+                v[e] = (ccol && x < Hi) ? ip[ky * Hi + (x < Hi ? x : 0)] : (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                bf16x8 bf;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bf[e] = v[e + kx];
+                acc[3 * ky + kx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bf, acc[3 * ky + kx], 0, 0, 0);
+                acc[3 * ky + kx] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bf, acc[3 * ky + kx], 0, 0, 0);
+            }
         }
     }
+    dbs += __shfl_xor(dbs, 32);
+    // the waves' sums into LDS in wave order
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
 #pragma unroll
-    for (int k = 0; k < 10; ++k) s[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
+            for (int k = 0; k < 9; ++k)
 #pragma unroll
-            for (int k = 0; k < 10; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+                for (int e = 0; e < 16; ++e) {
+                    const int idx = k * 1024 + (8 * (e >> 2) + 4 * h + (e & 3)) * 32 + r;
+                    red[idx] = (w == 0 ? 0.0f : red[idx]) + acc[k][e];
+                }
+            if (h == 0) red[9 * 1024 + r] = (w == 0 ? 0.0f : red[9 * 1024 + r]) + dbs;
+        }
         __syncthreads();
     }
-    if (threadIdx.x < 9) dw[(o * Ci + c) * 9 + threadIdx.x] = s[threadIdx.x][0];
-    if (threadIdx.x == 9 && c == 0) db[o] = s[9][0];
+    float *dst = part + (long long)blockIdx.x * WG_PART;
+    for (int i = threadIdx.x; i < WG_PART; i += 256) dst[i] = red[i];
+}
+
+// dw[(o Ci + c) 9 + k] and db[o] from the workgroup partials: thread j of
+// the 8 per output adds partials j, j + 8, ... in order, then the 8 sums are
+// added in order (deterministic).
+__global__ __launch_bounds__(256) void train_wgrad_reduce(const float *__restrict__ part, int nwg, int Co, int Ci,
+                                                          float *__restrict__ dw, float *__restrict__ db) {
+    __shared__ float red[8][32];
+    const int j = threadIdx.x >> 5, t = blockIdx.x * 32 + (threadIdx.x & 31);
+    float s = 0.0f;
+    if (t < WG_PART) {
+#pragma unroll 8
+        for (int w = j; w < nwg; w += 8) s += part[(long long)w * WG_PART + t];
+    }
+    red[j][threadIdx.x & 31] = s;
+    __syncthreads();
+    if (j != 0 || t >= WG_PART) return;
+    float tot = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tot += red[k][threadIdx.x];
+    if (t < 9 * 1024) {
+        const int k = t >> 10, o = (t >> 5) & 31, c = t & 31;
+        if (o < Co && c < Ci) dw[(o * Ci + c) * 9 + k] = tot;
+    } else if (t - 9 * 1024 < Co) {
+        db[t - 9 * 1024] = tot;
+    }
 }
 
 __global__ __launch_bounds__(256) void train_adam(float *__restrict__ p, const float *__restrict__ g,
@@ -740,8 +851,10 @@ __global__ __launch_bounds__(256) void train_adam(float *__restrict__ p, const f
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct TrainLayout {
-    size_t in0, a1, a2, out, tgt, g3, g2, g1, part, total;
+    size_t in0, a1, a2, out, tgt, g3, g2, g1, part, wpart, total;
 };
+
+constexpr int WGRAD_WGS = 256;   // workgroups of train_wgrad_mfma
 
 static TrainLayout train_layout(int B, int C) {
     TrainLayout L;
@@ -761,6 +874,7 @@ static TrainLayout train_layout(int B, int C) {
     L.g2 = take((size_t)B * 32 * H2 * H2 * 4);
     L.g1 = take((size_t)B * 32 * H1 * H1 * 4);
     L.part = take(1024 * 8);
+    L.wpart = take((size_t)WGRAD_WGS * WG_PART * 4);
     L.total = o;
     return L;
 }
@@ -768,6 +882,13 @@ static TrainLayout train_layout(int B, int C) {
 size_t net_train_workspace(int B, int C) { return train_layout(B, C).total; }
 
 static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+// workgroups of train_conv_mfma for an output plane of side Hd: one per
+// tile, at most 1024 (they loop over the tiles)
+static unsigned conv_grid(int B, int Hd) {
+    const long long tiles = (long long)B * ((Hd + CT_Y - 1) / CT_Y) * ((Hd + CT_X - 1) / CT_X);
+    return (unsigned)(tiles < 1024 ? tiles : 1024);
+}
 
 // The training step in three phases sharing the descriptor's workspace:
 // forward (layer activations, the loss and its gradient with respect to
@@ -802,12 +923,12 @@ static hipError_t net_train_phases(const menkf_net_train *t, int phases, hipStre
     if (phases & TRAIN_FORWARD) {
         hipLaunchKernelGGL(train_gather, dim3(nblk((long long)sh.H0 * sh.H0 * B)), dim3(256), 0, s, t->dproj, t->xf,
                            t->target, t->crops_dev, t->H, t->W, sh, nc, in0, tgt);
-        hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
-                           (const __bf16 *)in0, 8, sh.H0, P + P_W1, P + P_B1, 32, B, (void *)a1);
-        hipLaunchKernelGGL(train_conv_fwd<true>, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
-                           (const __bf16 *)a1, 32, sh.H1, P + P_W2, P + P_B2, 32, B, (void *)a2);
-        hipLaunchKernelGGL(train_conv_fwd<false>, dim3(nblk((long long)sh.H3 * sh.H3 * 4 * B)), dim3(256), 0, s,
-                           (const __bf16 *)a2, 32, sh.H2, P + P_W3, P + P_B3, 4, B, (void *)out);
+        hipLaunchKernelGGL(train_conv_mfma<CONV_HIDDEN>, dim3(conv_grid(B, sh.H1)), dim3(256), 0, s, (const void *)in0, 8,
+                           sh.H0, 0, P + P_W1, P + P_B1, 32, sh.H1, B, (void *)a1, (const __bf16 *)nullptr);
+        hipLaunchKernelGGL(train_conv_mfma<CONV_HIDDEN>, dim3(conv_grid(B, sh.H2)), dim3(256), 0, s, (const void *)a1, 32,
+                           sh.H1, 0, P + P_W2, P + P_B2, 32, sh.H2, B, (void *)a2, (const __bf16 *)nullptr);
+        hipLaunchKernelGGL(train_conv_mfma<CONV_LAST>, dim3(conv_grid(B, sh.H3)), dim3(256), 0, s, (const void *)a2, 32,
+                           sh.H2, 0, P + P_W3, P + P_B3, 4, sh.H3, B, (void *)out, (const __bf16 *)nullptr);
         const long long nout = (long long)B * 4 * sh.H3 * sh.H3;
         int nbm = (int)nblk(nout);
         if (nbm > 1024) nbm = 1024;
@@ -816,19 +937,22 @@ static hipError_t net_train_phases(const menkf_net_train *t, int phases, hipStre
         hipLaunchKernelGGL(train_loss_final, dim3(1), dim3(64), 0, s, (const double *)part, nbm, nout, t->loss_dev);
     }
     if (phases & TRAIN_BACKWARD) {
+        float *wpart = (float *)(w + L.wpart);
+        auto wgrad = [&](const float *gout, int Co, int Ho, const __bf16 *act, int Ci, float *dw, float *db) {
+            hipLaunchKernelGGL(train_wgrad_mfma, dim3(WGRAD_WGS), dim3(256), 0, s, gout, Co, Ho, act, Ci, B, wpart);
+            hipLaunchKernelGGL(train_wgrad_reduce, dim3((WG_PART + 31) / 32), dim3(256), 0, s,
+                               (const float *)wpart, WGRAD_WGS, Co, Ci, dw, db);
+        };
         // layer 3
-        hipLaunchKernelGGL(train_conv_bwd_weight, dim3(4 * 32), dim3(256), 0, s, (const float *)g3, 4, sh.H3,
-                           (const __bf16 *)a2, 32, B, G + P_W3, G + P_B3);
-        hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H2 * sh.H2 * 32 * B)), dim3(256), 0, s,
-                           (const float *)g3, 4, sh.H3, P + P_W3, (const __bf16 *)a2, 32, B, g2);
+        wgrad((const float *)g3, 4, sh.H3, (const __bf16 *)a2, 32, G + P_W3, G + P_B3);
+        hipLaunchKernelGGL(train_conv_mfma<CONV_DGRAD>, dim3(conv_grid(B, sh.H2)), dim3(256), 0, s, (const void *)g3, 4,
+                           sh.H3, 2, P + P_W3, (const float *)nullptr, 32, sh.H2, B, (void *)g2, (const __bf16 *)a2);
         // layer 2
-        hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 32), dim3(256), 0, s, (const float *)g2, 32, sh.H2,
-                           (const __bf16 *)a1, 32, B, G + P_W2, G + P_B2);
-        hipLaunchKernelGGL(train_conv_bwd_data, dim3(nblk((long long)sh.H1 * sh.H1 * 32 * B)), dim3(256), 0, s,
-                           (const float *)g2, 32, sh.H2, P + P_W2, (const __bf16 *)a1, 32, B, g1);
+        wgrad((const float *)g2, 32, sh.H2, (const __bf16 *)a1, 32, G + P_W2, G + P_B2);
+        hipLaunchKernelGGL(train_conv_mfma<CONV_DGRAD>, dim3(conv_grid(B, sh.H1)), dim3(256), 0, s, (const void *)g2, 32,
+                           sh.H2, 2, P + P_W2, (const float *)nullptr, 32, sh.H1, B, (void *)g1, (const __bf16 *)a1);
         // layer 1
-        hipLaunchKernelGGL(train_conv_bwd_weight, dim3(32 * 8), dim3(256), 0, s, (const float *)g1, 32, sh.H1,
-                           (const __bf16 *)in0, 8, B, G + P_W1, G + P_B1);
+        wgrad((const float *)g1, 32, sh.H1, (const __bf16 *)in0, 8, G + P_W1, G + P_B1);
     }
     if (phases & TRAIN_ADAM) {
         const float c1 = 1.0f - powf(t->beta1, (float)t->step);
