@@ -559,9 +559,10 @@ double menkf_ram_ratio(int32_t dim, int32_t ratio, int32_t n_members);
  * and ends with menkf_update, leaving its own delta^C pending in deltac
  * (a device word of the context records whether a correction is pending:
  * none after menkf_set_workspace or menkf_cycle_flush, so the first
- * pipelined call corrects nothing).  With aux_stream the pending correction
- * runs there ahead of the fine forecast (with MENKF_GAIN_EXACT_R beside the
- * late block steps of the factorisation), off the member chain that bounds
+ * pipelined call corrects nothing; whether one is pending is read when the
+ * call starts).  With aux_stream the pending correction runs there ahead of
+ * the fine forecast (with MENKF_GAIN_EXACT_R beside the early block steps of
+ * the factorisation, after the x* system), off the member chain that bounds
  * the cycle.  After the call fine holds the uncorrected forecast x^F_f;
  * menkf_cycle_flush applies the pending correction, after which K
  * pipelined calls have given bitwise the results of K calls with

@@ -539,13 +539,20 @@ menkf_status menkf_prolong_smooth(menkf_ctx *ctx, const void *dc, void *xf, cons
     return prolong_impl(ctx, dc, xf, xprev, n_sweeps, alpha, mode, net, info, (hipStream_t)stream);
 }
 
-// The correction left pending by the last pipelined cycle (none pending:
-// every kernel returns at once), issued on s.
-static menkf_status pending_correction(menkf_ctx *ctx, const menkf_cycle_args *a, hipStream_t s) {
+// The correction left pending by the last pipelined cycle: the skip word
+// (nothing pending, or a failed analysis) is set on s_skip when the call
+// starts, so that a failure of this call's own analysis does not race with
+// it; the correction follows on s (every kernel returns at once when the
+// word is set).
+static menkf_status pending_skip(menkf_ctx *ctx, hipStream_t s_skip) {
     const int32_t *info = (const int32_t *)((char *)ctx->ws + ctx->plan.off_info);
     int32_t *pw = (int32_t *)((char *)ctx->ws + ctx->plan.off_info + PIPE_WORDS);
-    const hipError_t e = launch_pipe_skip(info, pw, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (pending correction)");
+    const hipError_t e = launch_pipe_skip(info, pw, s_skip);
+    return e == hipSuccess ? MENKF_OK : hip_fail(ctx, e, "menkf_cycle (pending correction)");
+}
+
+static menkf_status pending_correction(menkf_ctx *ctx, const menkf_cycle_args *a, hipStream_t s) {
+    const int32_t *pw = (const int32_t *)((char *)ctx->ws + ctx->plan.off_info + PIPE_WORDS);
     return prolong_impl(ctx, a->deltac, a->fine, a->fine_prev, a->n_sweeps, a->alpha, a->prolong_mode, a->net,
                         pw + PW_SKIP, s);
 }
@@ -792,8 +799,9 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
     if (!ctx->idx) return fail(ctx, MENKF_E_ARG, "probes not set (menkf_set_probes)");
     menkf_status st;
     const bool aux = a->aux_stream && a->aux_stream != stream;
-    if (a->pipelined && !aux) {
-        st = pending_correction(ctx, a, (hipStream_t)stream);
+    if (a->pipelined) {
+        st = pending_skip(ctx, (hipStream_t)stream);
+        if (st == MENKF_OK && !aux) st = pending_correction(ctx, a, (hipStream_t)stream);
         if (st != MENKF_OK) return st;
     }
     if (aux && p.defer_ok) {
@@ -812,6 +820,9 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         if ((e = hipEventRecord(ctx->ev_front, s0)) == hipSuccess) e = hipStreamWaitEvent(s1, ctx->ev_front, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
         hipError_t e1 = launch_xstar_factor(p, ctx->ws, s1);
+        // a pipelined cycle applies the previous cycle's correction here,
+        // beside the early block steps and off the member chain
+        st = a->pipelined ? pending_correction(ctx, a, s1) : MENKF_OK;
         // The factorisation is issued next and records the second fork
         // event once its remaining trailing updates fit about three
         // workgroups per compute unit: the early block steps, bound by the
@@ -822,9 +833,6 @@ menkf_status menkf_cycle(const menkf_cycle_args *a, menkf_stream stream) {
         if (e0 != hipSuccess) (void)hipEventRecord(ctx->ev_fork, s0);   // keep the fork well formed
         e = hipStreamWaitEvent(s1, ctx->ev_fork, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "menkf_cycle (fork)");
-        // a pipelined cycle first applies the previous cycle's correction
-        // here, beside the late block steps and off the member chain
-        st = a->pipelined ? pending_correction(ctx, a, s1) : MENKF_OK;
         if (st == MENKF_OK) st = menkf_forecast(ctx, MENKF_FINE, a->fine, 1, a->nsteps, a->fine_prev, a->aux_stream);
         if (st == MENKF_OK) st = menkf_restrict(ctx, a->fine, a->xstar, a->aux_stream);
         // join also after a failed issue, so that a capture stays well formed
@@ -876,7 +884,8 @@ menkf_status menkf_cycle_flush(const menkf_cycle_args *a, menkf_stream stream) {
     menkf_ctx *ctx = a->ctx;
     NEED_WS(ctx);
     if (!a->fine || !a->fine_prev || !a->deltac) return fail(ctx, MENKF_E_ARG, "menkf_cycle_flush: null buffer");
-    menkf_status st = pending_correction(ctx, a, (hipStream_t)stream);
+    menkf_status st = pending_skip(ctx, (hipStream_t)stream);
+    if (st == MENKF_OK) st = pending_correction(ctx, a, (hipStream_t)stream);
     if (st != MENKF_OK) return st;
     const hipError_t e = launch_set_word((int32_t *)((char *)ctx->ws + ctx->plan.off_info + PIPE_WORDS) + PW_PEND, 0,
                                          (hipStream_t)stream);
