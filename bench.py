@@ -1192,6 +1192,9 @@ def bench_euler(args):
             "avg_launch_us": avg_s * 1e6, "flops_per_launch": flops,
         },
     }
+    if args.cpu_baseline:
+        log("bench: timing the oracle's dual cycle on the host (bounded sample)")
+        out["cpu_baseline"] = dual_cpu_baseline(cfg, n_cycles=20)
     print(json.dumps(out), flush=True)
 
 
