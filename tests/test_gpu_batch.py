@@ -3,8 +3,9 @@ independent instances: menkf_cycle equals the sequence of calls it stands
 for; a batch spread over several streams equals the same cycles issued one
 after another on one stream; its captured graph replays equal eager batches;
 and at the full uneven-batch workload (48 instances, fine 256^2 to 768^2,
-N 16 to 128, 256 to 2048 probes) one instance is followed through the oracle
-and the rest are checked against their own sequential cycles."""
+N 16 to 128, 256 to 2048 probes) one instance is followed through the oracle,
+three more (learned prolongation) have their analysis checked against the
+oracle's, and the batch is checked against sequential cycles."""
 
 import numpy as np
 import pytest
@@ -312,3 +313,21 @@ def test_uneven_batch_full_size():
     assert rel_l2(to_np(got[small]["members"]) - memf, res["members"] - memf) < 1e-3
     assert rel_l2(to_np(got[small]["fine"]), x) < 1e-5
     assert rel_l2(to_np(got[small]["fine"]) - xf, x - xf) < 1e-2
+
+    # three more instances (learned prolongation, the largest ensemble and
+    # the most probes among them): the members after the batch cycle against
+    # the oracle's analysis of the device forecast (the prolongation does not
+    # enter the members)
+    most_probes = max(range(len(cfgs)), key=lambda k: cfgs[k].n_probes)
+    for k in sorted({big, most_probes, len(cfgs) // 2} - {small}):
+        i, cfg = insts[k], cfgs[k]
+        say(f"oracle analysis of {cfg.name}: fine {cfg.nx}^2, N {cfg.n_members}, {cfg.n_probes} probes")
+        xf_d, mem_d = init[k]["fine"].clone(), init[k]["members"].clone()
+        i["ctx"].forecast(0, xf_d, cfg.n_obs)
+        i["ctx"].forecast(1, mem_d, cfg.n_obs)
+        memf = to_np(mem_d)
+        xstar = grids.restrict(to_np(xf_d), cfg.ratio, 2)
+        eps = rng.perturbations(cfg.seed + 5, 1, cfg.n_members, cfg.n_probes, cfg.obs_sigma)
+        res = enkf.analysis(memf, xstar, to_np(i["y"]), eps, ocycle.make_H(cfg, i["idx"], i["comp"]), cfg.obs_sigma)
+        assert rel_l2(to_np(got[k]["members"]), res["members"]) < 1e-5, cfg.name
+        assert rel_l2(to_np(got[k]["members"]) - memf, res["members"] - memf) < 1e-3, cfg.name
