@@ -59,7 +59,30 @@ def test_learned_prolongation_matches_oracle(cfg):
     nn_o = corr - dproj
     assert np.linalg.norm(nn_o) > 0.1 * np.linalg.norm(dproj)      # the network contributes
     assert rel_l2(got, corr) < 2e-2, rel_l2(got, corr)
-    assert rel_l2(got - dproj, nn_o) < 5e-2, rel_l2(got - dproj, nn_o)
+    assert rel_l2(got - dproj, nn_o) < 2e-2, rel_l2(got - dproj, nn_o)   # measured 3.9e-3 (BF16 storage)
+
+
+@pytest.mark.parametrize("cfg", [configs.tiny_2d(), configs.ragged_2d()], ids=["tiny", "ragged"])
+def test_learned_prolongation_matches_oracle_steps_at_bf16_storage(cfg):
+    """The inference kernel against the oracle's steps with its BF16 storage
+    (input and hidden activations; the test weights are BF16 already): the
+    network's part of the correction agrees to the FP32 rounding of the
+    corrected state, well inside what the BF16 storage itself costs."""
+    import paper_2012_10091_amd as m
+    ctx, _, _ = make_ctx(cfg)
+    p = _params(cfg)
+    gnet = _gpu_net(p)
+    dc, xf = _inputs(cfg)
+    xf_d = to_dev(xf, F32)
+    say("learned prolongation at BF16 storage", cfg.name)
+    ctx.prolong_smooth(to_dev(dc, F32), xf_d, None, n_sweeps=0, mode=m.MENKF_PROLONG_LEARNED, net=gnet)
+    dproj = grids.prolong(dc, cfg.ratio, 2)
+    inp = bf16_round(onet.make_input(p, dproj.astype(np.float32), xf.astype(np.float32)))
+    a1 = bf16_round(np.maximum(onet.conv(inp, p.w1, p.b1), 0.0))
+    a2 = bf16_round(np.maximum(onet.conv(a1, p.w2, p.b2), 0.0))
+    nn_o = onet.conv(a2, p.w3, p.b3) / p.out_scale[:, None, None]
+    got = to_np(xf_d) - xf - dproj
+    assert rel_l2(got, nn_o) < 2e-3, rel_l2(got, nn_o)          # measured 2.4e-4 - 3.7e-4
 
 
 def test_zero_last_layer_equals_plain_bitwise():
