@@ -2,7 +2,11 @@
 menkf_cycle_flush): the fine-grid correction of Algo. 4 steps 5-6 deferred
 to the next call changes no arithmetic, so K pipelined calls and a flush are
 bitwise K ordinary calls, eager and as a replayed graph, with the plain and
-the judged learned correction, on one stream and with a second stream."""
+the judged learned correction, on one stream and with a second stream, for
+the exact-R gain (second stream forked inside the factorisation) and the
+ensemble-space gain (second stream beside the member forecast)."""
+
+import dataclasses
 
 import pytest
 import torch
@@ -46,15 +50,25 @@ def _flush(inst, mode, net, stream=None):
                             stream=stream)
 
 
+def _ensemble_space(cfg):
+    # the ensemble-space gain: with a second stream the fine forecast runs
+    # beside the member forecast (no deferred x* column)
+    @dataclasses.dataclass(frozen=True)
+    class C(type(cfg)):
+        gain_mode: int = 2
+    return C(**dataclasses.asdict(cfg))
+
+
+@pytest.mark.parametrize("ens", [False, True], ids=["exact-R", "ensemble-space"])
 @pytest.mark.parametrize("aux", [False, True], ids=["one-stream", "aux-stream"])
 @pytest.mark.parametrize("mode", [0, 2], ids=["plain", "learned-judged"])
-def test_pipelined_cycles_and_flush_equal_ordinary_cycles(aux, mode):
-    cfg = configs.tiny_2d()
+def test_pipelined_cycles_and_flush_equal_ordinary_cycles(aux, mode, ens):
+    cfg = _ensemble_space(configs.tiny_2d()) if ens else configs.tiny_2d()
     a, b = _instance(cfg), _instance(cfg)
     na, nb = (_net(2), _net(2)) if mode else (None, None)
     sa = torch.cuda.Stream() if aux else None
     sb = torch.cuda.Stream() if aux else None
-    say(f"pipelined vs ordinary cycles, tiny_2d, mode {mode}, aux stream {aux}")
+    say(f"pipelined vs ordinary cycles, tiny_2d, mode {mode}, aux stream {aux}, ensemble-space gain {ens}")
     for c in (1, 2, 3):
         _cycle(a, cfg, c, mode, na, sa, True)
         _cycle(b, cfg, c, mode, nb, sb, False)
